@@ -1,0 +1,509 @@
+/*
+ * FP64 reference implementation of the explicit particle-in-cell cycle.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark load this file's library.  The product
+ * path (the HIP library) never links, calls or includes anything from here,
+ * and this file includes nothing from the product path.
+ *
+ * It is deliberately plain and slow: one particle at a time, one node at a
+ * time, in double precision, in the order the method states its steps:
+ *
+ *   field gather (cubic B-spline at each component's staggered position)
+ *   -> relativistic Boris push -> move -> charge-conserving current deposit
+ *   (Esirkepov's density decomposition, cubic shapes) -> optional binomial
+ *   current filter -> FDTD update B(n+1/2), E(n+1), B(n+1).
+ *
+ * The field update is the paper's eq. (2.1): D_t B = -curl' E,
+ * D_t E = c^2 curl B - J/eps0 (normalised: c = eps0 = 1), where curl' takes
+ * D_i S_i in place of D_i (Section 2), and S_x is the 3x3 transverse stencil
+ * of Section 2 (centre alpha_x, +-y neighbours beta_y, +-z neighbours beta_z,
+ * corners gamma_yz; S_y, S_z by cyclic permutation).  With alpha = 1 and
+ * beta = gamma = 0 every S_i is the identity and the update is the standard
+ * Yee scheme (Section 1).  The PIC cycle itself is the one the introduction
+ * describes (fields on a grid, particles in continuous phase space).
+ *
+ * Layout: field component arrays of nx*ny*nz doubles, x fastest, index
+ * (i,j,k) -> i + nx*(j + ny*k).  Yee staggering: E_x(i+1/2,j,k),
+ * E_y(i,j+1/2,k), E_z(i,j,k+1/2), B_x(i,j+1/2,k+1/2), B_y(i+1/2,j,k+1/2),
+ * B_z(i+1/2,j+1/2,k); J like E; rho on nodes (i,j,k).  Array index (i,j,k)
+ * holds the value at the staggered point whose integer parts are (i,j,k).
+ * Particles: absolute positions x[3][np] in c/w_p, momenta u = gamma v/c,
+ * density weights w (n/ppc).  y and z are periodic; x is periodic or, for a
+ * moving window, bounded by zero-valued ghost fields.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    int64_t n[3];     /* cells */
+    double d[3];      /* cell sizes */
+    double dt;        /* time step */
+    int32_t xbc;      /* 0: periodic in x; 1: zero ghost beyond both x edges */
+    int32_t pad_;
+    double alpha[3];  /* centre weights of S_x, S_y, S_z */
+    double beta[3];   /* beta_x, beta_y, beta_z */
+    double gam[3];    /* gamma_yz, gamma_zx, gamma_xy */
+} ora_grid;
+
+enum { ORA_OK = 0, ORA_EINVAL = -1, ORA_ENONFINITE = -5 };
+
+/* ------------------------------------------------------------------ */
+/* grid helpers                                                        */
+
+static int64_t wrap(int64_t i, int64_t n) {
+    int64_t r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+static int64_t ncell(const ora_grid *g) { return g->n[0] * g->n[1] * g->n[2]; }
+
+/* Value of a field component at integer index (i,j,k) with the boundary rule:
+ * y, z periodic; x periodic or zero outside [0, nx). */
+static double fld(const ora_grid *g, const double *F, int64_t i, int64_t j, int64_t k) {
+    if (g->xbc == 1) {
+        if (i < 0 || i >= g->n[0]) return 0.0;
+    } else {
+        i = wrap(i, g->n[0]);
+    }
+    j = wrap(j, g->n[1]);
+    k = wrap(k, g->n[2]);
+    return F[i + g->n[0] * (j + g->n[1] * k)];
+}
+
+/* Flat index of (i,j,k) or -1 when x falls outside a bounded window. */
+static int64_t node(const ora_grid *g, int64_t i, int64_t j, int64_t k) {
+    if (g->xbc == 1) {
+        if (i < 0 || i >= g->n[0]) return -1;
+    } else {
+        i = wrap(i, g->n[0]);
+    }
+    j = wrap(j, g->n[1]);
+    k = wrap(k, g->n[2]);
+    return i + g->n[0] * (j + g->n[1] * k);
+}
+
+/* ------------------------------------------------------------------ */
+/* shape                                                               */
+
+/* Cubic (third-order) B-spline of support 4 cells, the macroparticle shape
+ * named in Sections 1 and 3.1: S(xi) = 2/3 - xi^2 + |xi|^3/2 for |xi| < 1,
+ * (2-|xi|)^3/6 for 1 <= |xi| < 2, 0 beyond. */
+double ora_bspline3(double xi) {
+    double a = fabs(xi);
+    if (a < 1.0) return 2.0 / 3.0 - a * a + 0.5 * a * a * a;
+    if (a < 2.0) {
+        double t = 2.0 - a;
+        return t * t * t / 6.0;
+    }
+    return 0.0;
+}
+
+/* Staggering of the six field components: offset (0 or 1/2 cell) per axis. */
+static const double STAG_E[3][3] = {{0.5, 0, 0}, {0, 0.5, 0}, {0, 0, 0.5}};
+static const double STAG_B[3][3] = {{0, 0.5, 0.5}, {0.5, 0, 0.5}, {0.5, 0.5, 0}};
+
+/* Interpolate component array F (staggered by sh[3]) at absolute position x. */
+static double gather1(const ora_grid *g, const double *F, const double sh[3], const double x[3]) {
+    int64_t base[3];
+    double wgt[3][4];
+    for (int a = 0; a < 3; ++a) {
+        double s = x[a] / g->d[a] - sh[a];
+        int64_t i = (int64_t)floor(s);
+        base[a] = i - 1;
+        for (int m = 0; m < 4; ++m) wgt[a][m] = ora_bspline3((double)(base[a] + m) - s);
+    }
+    double acc = 0.0;
+    for (int c = 0; c < 4; ++c)
+        for (int b = 0; b < 4; ++b)
+            for (int a = 0; a < 4; ++a)
+                acc += fld(g, F, base[0] + a, base[1] + b, base[2] + c) * wgt[0][a] * wgt[1][b] * wgt[2][c];
+    return acc;
+}
+
+/* Field gather at one position: each component with a cubic spline at its
+ * own staggered grid (momentum-conserving interpolation). */
+void ora_gather(const ora_grid *g, const double *E, const double *B, const double x[3],
+                double Ep[3], double Bp[3]) {
+    int64_t nc = ncell(g);
+    for (int c = 0; c < 3; ++c) {
+        Ep[c] = gather1(g, E + c * nc, STAG_E[c], x);
+        Bp[c] = gather1(g, B + c * nc, STAG_B[c], x);
+    }
+}
+
+/* Relativistic Boris rotation, u = gamma v / c, normalised units:
+ * h = q dt / (2 m); u- = u + h E; t = h B / gamma(u-); s = 2t/(1+t^2);
+ * u' = u- + u- x t; u+ = u- + u' x s; u_new = u+ + h E. */
+void ora_boris(double u[3], const double Ep[3], const double Bp[3], double qm, double dt) {
+    double h = 0.5 * qm * dt;
+    double um[3] = {u[0] + h * Ep[0], u[1] + h * Ep[1], u[2] + h * Ep[2]};
+    double gm = sqrt(1.0 + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
+    double t[3] = {h * Bp[0] / gm, h * Bp[1] / gm, h * Bp[2] / gm};
+    double t2 = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+    double s[3] = {2.0 * t[0] / (1.0 + t2), 2.0 * t[1] / (1.0 + t2), 2.0 * t[2] / (1.0 + t2)};
+    double up[3] = {um[0] + um[1] * t[2] - um[2] * t[1],
+                    um[1] + um[2] * t[0] - um[0] * t[2],
+                    um[2] + um[0] * t[1] - um[1] * t[0]};
+    double upl[3] = {um[0] + up[1] * s[2] - up[2] * s[1],
+                     um[1] + up[2] * s[0] - up[0] * s[2],
+                     um[2] + up[0] * s[1] - up[1] * s[0]};
+    for (int a = 0; a < 3; ++a) u[a] = upl[a] + h * Ep[a];
+}
+
+/* Gather + Boris + move for every particle.  x is read at time n, u at n-1/2;
+ * on return u is at n+1/2, x_new (unwrapped, x^n + dt u/gamma) at n+1 and x
+ * holds x_new wrapped into the periodic box. */
+int ora_push(const ora_grid *g, int64_t np, double *x, double *u, double *x_new,
+             double q, double m, const double *E, const double *B) {
+    int bad = 0;
+    for (int64_t p = 0; p < np; ++p) {
+        double xp[3] = {x[p], x[np + p], x[2 * np + p]};
+        double up[3] = {u[p], u[np + p], u[2 * np + p]};
+        double Ep[3], Bp[3];
+        ora_gather(g, E, B, xp, Ep, Bp);
+        ora_boris(up, Ep, Bp, q / m, g->dt);
+        double gam = sqrt(1.0 + up[0] * up[0] + up[1] * up[1] + up[2] * up[2]);
+        for (int a = 0; a < 3; ++a) {
+            if (!isfinite(up[a])) bad = 1;
+            u[a * np + p] = up[a];
+            double xn = xp[a] + g->dt * up[a] / gam;
+            x_new[a * np + p] = xn;
+            double L = g->n[a] * g->d[a];
+            if (a == 0 && g->xbc == 1) {
+                x[p] = xn;
+            } else {
+                x[a * np + p] = xn - L * floor(xn / L);
+            }
+        }
+    }
+    return bad ? ORA_ENONFINITE : ORA_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* charge-conserving current deposit                                   */
+
+/* Esirkepov's decomposition for one particle moving from x0 to x1 (x1 not
+ * wrapped).  Per axis the union support is the 5 nodes base..base+4 with
+ * base = min(floor(s0), floor(s1)) - 1, s = x/d.  With S0, S1 the cubic
+ * weights of the old and new position and dS = S1 - S0:
+ *   W^x_abc = dSx_a (S0y_b S0z_c + dSy_b S0z_c/2 + S0y_b dSz_c/2 + dSy_b dSz_c/3)
+ * (and cyclically for y, z); the current is the running sum along its axis:
+ *   J_x(base_x+a+1/2, base_y+b, base_z+c) += -q w (dx/dt) sum_{a'<=a} W^x_{a'bc}.
+ * Summed over axes, W gives S1S1S1 - S0S0S0, so the discrete continuity
+ * equation holds exactly. */
+void ora_deposit_one(const ora_grid *g, const double x0[3], const double x1[3], double w, double q,
+                     double *J) {
+    int64_t nc = ncell(g);
+    int64_t base[3];
+    double S0[3][5], dS[3][5];
+    for (int a = 0; a < 3; ++a) {
+        double s0 = x0[a] / g->d[a], s1 = x1[a] / g->d[a];
+        int64_t i0 = (int64_t)floor(s0), i1 = (int64_t)floor(s1);
+        base[a] = (i0 < i1 ? i0 : i1) - 1;
+        for (int m = 0; m < 5; ++m) {
+            double node_pos = (double)(base[a] + m);
+            S0[a][m] = ora_bspline3(node_pos - s0);
+            dS[a][m] = ora_bspline3(node_pos - s1) - S0[a][m];
+        }
+    }
+    for (int comp = 0; comp < 3; ++comp) {
+        /* comp = direction of the current; (t1, t2) the two other axes */
+        int t1 = (comp + 1) % 3, t2 = (comp + 2) % 3;
+        double coef = -q * w * g->d[comp] / g->dt;
+        for (int b = 0; b < 5; ++b)
+            for (int c = 0; c < 5; ++c) {
+                double trans = S0[t1][b] * S0[t2][c] + 0.5 * dS[t1][b] * S0[t2][c] +
+                               0.5 * S0[t1][b] * dS[t2][c] + dS[t1][b] * dS[t2][c] / 3.0;
+                double run = 0.0;
+                for (int a = 0; a < 5; ++a) {
+                    run += dS[comp][a] * trans;
+                    int64_t idx[3];
+                    idx[comp] = base[comp] + a;
+                    idx[t1] = base[t1] + b;
+                    idx[t2] = base[t2] + c;
+                    int64_t f = node(g, idx[0], idx[1], idx[2]);
+                    if (f >= 0) J[comp * nc + f] += coef * run;
+                }
+            }
+    }
+}
+
+/* J += deposit of all particles moving x0 -> x1 (x1 unwrapped). */
+void ora_deposit(const ora_grid *g, int64_t np, const double *x0, const double *x1, const double *w,
+                 double q, double *J) {
+    for (int64_t p = 0; p < np; ++p) {
+        double a[3] = {x0[p], x0[np + p], x0[2 * np + p]};
+        double b[3] = {x1[p], x1[np + p], x1[2 * np + p]};
+        ora_deposit_one(g, a, b, w[p], q, J);
+    }
+}
+
+/* Charge density on nodes: rho(i,j,k) += q w S S S (cubic shape at the node grid). */
+void ora_rho(const ora_grid *g, int64_t np, const double *x, const double *w, double q, double *rho) {
+    for (int64_t p = 0; p < np; ++p) {
+        int64_t base[3];
+        double wgt[3][4];
+        for (int a = 0; a < 3; ++a) {
+            double s = x[a * np + p] / g->d[a];
+            int64_t i = (int64_t)floor(s);
+            base[a] = i - 1;
+            for (int m = 0; m < 4; ++m) wgt[a][m] = ora_bspline3((double)(base[a] + m) - s);
+        }
+        for (int c = 0; c < 4; ++c)
+            for (int b = 0; b < 4; ++b)
+                for (int a = 0; a < 4; ++a) {
+                    int64_t f = node(g, base[0] + a, base[1] + b, base[2] + c);
+                    if (f >= 0) rho[f] += q * w[p] * wgt[0][a] * wgt[1][b] * wgt[2][c];
+                }
+    }
+}
+
+/* Continuity residual on nodes: (rho1 - rho0) dx/dt + sum_d (dx/d_d)(J_d - J_d[-e_d]).
+ * Writes it to res (may be NULL) and returns max |res|. */
+double ora_continuity(const ora_grid *g, const double *rho0, const double *rho1, const double *J,
+                      double *res) {
+    int64_t nc = ncell(g);
+    double mx = 0.0;
+    for (int64_t k = 0; k < g->n[2]; ++k)
+        for (int64_t j = 0; j < g->n[1]; ++j)
+            for (int64_t i = 0; i < g->n[0]; ++i) {
+                int64_t f = i + g->n[0] * (j + g->n[1] * k);
+                double r = (rho1[f] - rho0[f]) * g->d[0] / g->dt;
+                r += (fld(g, J, i, j, k) - fld(g, J, i - 1, j, k));
+                r += (g->d[0] / g->d[1]) * (fld(g, J + nc, i, j, k) - fld(g, J + nc, i, j - 1, k));
+                r += (g->d[0] / g->d[2]) * (fld(g, J + 2 * nc, i, j, k) - fld(g, J + 2 * nc, i, j, k - 1));
+                if (res) res[f] = r;
+                if (fabs(r) > mx) mx = fabs(r);
+            }
+    return mx;
+}
+
+/* ------------------------------------------------------------------ */
+/* field update                                                        */
+
+/* Transverse smoothing S_d of component array F at (i,j,k), Section 2:
+ * centre alpha_d, the two transverse axes t1 = d+1, t2 = d+2 (cyclic) with
+ * neighbour weights beta_t1, beta_t2 and corner weight gamma_{t1 t2}. */
+static double smooth(const ora_grid *g, const double *F, int d, int64_t i, int64_t j, int64_t k) {
+    int64_t p[3] = {i, j, k};
+    int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+    double acc = g->alpha[d] * fld(g, F, i, j, k);
+    for (int s = -1; s <= 1; s += 2) {
+        int64_t q1[3] = {p[0], p[1], p[2]};
+        q1[t1] += s;
+        acc += g->beta[t1] * fld(g, F, q1[0], q1[1], q1[2]);
+        int64_t q2[3] = {p[0], p[1], p[2]};
+        q2[t2] += s;
+        acc += g->beta[t2] * fld(g, F, q2[0], q2[1], q2[2]);
+        for (int s2 = -1; s2 <= 1; s2 += 2) {
+            int64_t qc[3] = {p[0], p[1], p[2]};
+            qc[t1] += s;
+            qc[t2] += s2;
+            acc += g->gam[d] * fld(g, F, qc[0], qc[1], qc[2]);
+        }
+    }
+    return acc;
+}
+
+/* Forward difference of S_d F along axis d at (i,j,k): (S_d F(p+e_d) - S_d F(p)) / d_d. */
+static double dsmooth(const ora_grid *g, const double *F, int d, int64_t i, int64_t j, int64_t k) {
+    int64_t q[3] = {i, j, k};
+    q[d] += 1;
+    return (smooth(g, F, d, q[0], q[1], q[2]) - smooth(g, F, d, i, j, k)) / g->d[d];
+}
+
+/* Backward difference of F along axis d at (i,j,k): (F(p) - F(p-e_d)) / d_d. */
+static double dback(const ora_grid *g, const double *F, int d, int64_t i, int64_t j, int64_t k) {
+    int64_t q[3] = {i, j, k};
+    q[d] -= 1;
+    return (fld(g, F, i, j, k) - fld(g, F, q[0], q[1], q[2])) / g->d[d];
+}
+
+/* B -= h curl' E  (B on faces, forward differences of the smoothed E). */
+static void b_half(const ora_grid *g, const double *E, double *B, double h) {
+    int64_t nc = ncell(g);
+    double *tmp = (double *)malloc(sizeof(double) * 3 * nc);
+    const double *Ex = E, *Ey = E + nc, *Ez = E + 2 * nc;
+    for (int64_t k = 0; k < g->n[2]; ++k)
+        for (int64_t j = 0; j < g->n[1]; ++j)
+            for (int64_t i = 0; i < g->n[0]; ++i) {
+                int64_t f = i + g->n[0] * (j + g->n[1] * k);
+                /* (curl' E)_x = D_y S_y E_z - D_z S_z E_y, and cyclic */
+                tmp[f] = dsmooth(g, Ez, 1, i, j, k) - dsmooth(g, Ey, 2, i, j, k);
+                tmp[nc + f] = dsmooth(g, Ex, 2, i, j, k) - dsmooth(g, Ez, 0, i, j, k);
+                tmp[2 * nc + f] = dsmooth(g, Ey, 0, i, j, k) - dsmooth(g, Ex, 1, i, j, k);
+            }
+    for (int64_t f = 0; f < 3 * nc; ++f) B[f] -= h * tmp[f];
+    free(tmp);
+}
+
+/* E += dt (curl B - J)  (E on edges, backward differences of B). */
+static void e_full(const ora_grid *g, double *E, const double *B, const double *J) {
+    int64_t nc = ncell(g);
+    double *tmp = (double *)malloc(sizeof(double) * 3 * nc);
+    const double *Bx = B, *By = B + nc, *Bz = B + 2 * nc;
+    for (int64_t k = 0; k < g->n[2]; ++k)
+        for (int64_t j = 0; j < g->n[1]; ++j)
+            for (int64_t i = 0; i < g->n[0]; ++i) {
+                int64_t f = i + g->n[0] * (j + g->n[1] * k);
+                tmp[f] = dback(g, Bz, 1, i, j, k) - dback(g, By, 2, i, j, k);
+                tmp[nc + f] = dback(g, Bx, 2, i, j, k) - dback(g, Bz, 0, i, j, k);
+                tmp[2 * nc + f] = dback(g, By, 0, i, j, k) - dback(g, Bx, 1, i, j, k);
+            }
+    for (int64_t f = 0; f < 3 * nc; ++f) E[f] += g->dt * (tmp[f] - (J ? J[f] : 0.0));
+    free(tmp);
+}
+
+/* One field step: B^{n+1/2} = B^n - dt/2 curl'E^n; E^{n+1} = E^n + dt (curl B^{n+1/2} - J^{n+1/2});
+ * B^{n+1} = B^{n+1/2} - dt/2 curl'E^{n+1}. */
+void ora_field_step(const ora_grid *g, double *E, double *B, const double *J) {
+    b_half(g, E, B, 0.5 * g->dt);
+    e_full(g, E, B, J);
+    b_half(g, E, B, 0.5 * g->dt);
+}
+
+/* Only the first half of the B update (used to check B at half steps). */
+void ora_b_half(const ora_grid *g, const double *E, double *B, double h) { b_half(g, E, B, h); }
+
+/* Discrete divergences: div E (on nodes) and div B (on cell centres). */
+void ora_div_e(const ora_grid *g, const double *E, double *out) {
+    int64_t nc = ncell(g);
+    for (int64_t k = 0; k < g->n[2]; ++k)
+        for (int64_t j = 0; j < g->n[1]; ++j)
+            for (int64_t i = 0; i < g->n[0]; ++i) {
+                int64_t f = i + g->n[0] * (j + g->n[1] * k);
+                out[f] = dback(g, E, 0, i, j, k) + dback(g, E + nc, 1, i, j, k) + dback(g, E + 2 * nc, 2, i, j, k);
+            }
+}
+
+void ora_div_b(const ora_grid *g, const double *B, double *out) {
+    int64_t nc = ncell(g);
+    for (int64_t k = 0; k < g->n[2]; ++k)
+        for (int64_t j = 0; j < g->n[1]; ++j)
+            for (int64_t i = 0; i < g->n[0]; ++i) {
+                int64_t f = i + g->n[0] * (j + g->n[1] * k);
+                out[f] = (fld(g, B, i + 1, j, k) - fld(g, B, i, j, k)) / g->d[0] +
+                         (fld(g, B + nc, i, j + 1, k) - fld(g, B + nc, i, j, k)) / g->d[1] +
+                         (fld(g, B + 2 * nc, i, j, k + 1) - fld(g, B + 2 * nc, i, j, k)) / g->d[2];
+            }
+}
+
+/* ------------------------------------------------------------------ */
+/* current filter                                                      */
+
+/* One (1/4, 1/2, 1/4) pass along each axis x, y, z on each component array,
+ * with the grid's boundary rule (periodic, or zero ghost beyond the x edges). */
+void ora_binomial(const ora_grid *g, double *J) {
+    int64_t nc = ncell(g);
+    double *tmp = (double *)malloc(sizeof(double) * nc);
+    for (int comp = 0; comp < 3; ++comp) {
+        double *F = J + comp * nc;
+        for (int ax = 0; ax < 3; ++ax) {
+            for (int64_t k = 0; k < g->n[2]; ++k)
+                for (int64_t j = 0; j < g->n[1]; ++j)
+                    for (int64_t i = 0; i < g->n[0]; ++i) {
+                        int64_t p[3] = {i, j, k}, lo[3] = {i, j, k}, hi[3] = {i, j, k};
+                        lo[ax] -= 1;
+                        hi[ax] += 1;
+                        tmp[i + g->n[0] * (j + g->n[1] * k)] =
+                            0.25 * fld(g, F, lo[0], lo[1], lo[2]) + 0.5 * fld(g, F, p[0], p[1], p[2]) +
+                            0.25 * fld(g, F, hi[0], hi[1], hi[2]);
+                    }
+            memcpy(F, tmp, sizeof(double) * nc);
+        }
+    }
+    free(tmp);
+}
+
+/* ------------------------------------------------------------------ */
+/* coefficients of the perfect-dispersion smoothing                    */
+
+/* Reading of Section 2: with r_y = (dx/dy)^2, r_z = (dx/dz)^2 (both <= 1 by
+ * the stated constraint dx <= dy, dz):
+ *   beta = (1/8, r_y/8, r_z/8); gamma_yz = r_y r_z/16, gamma_zx = r_z/16,
+ *   gamma_xy = r_y/16; alpha_d = 1 - 2 beta_t1 - 2 beta_t2 - 4 gamma_{t1 t2}
+ * (unit DC gain, so on-axis waves keep sigma_x = 1).  variant 1 drops the
+ * corner weights (all gamma = 0), variant 2 is the identity (Yee). */
+int ora_pd_coeffs(const double d[3], int variant, double alpha[3], double beta[3], double gam[3]) {
+    if (d[0] <= 0 || d[1] <= 0 || d[2] <= 0) return ORA_EINVAL;
+    if (variant == 2) {
+        for (int a = 0; a < 3; ++a) {
+            alpha[a] = 1.0;
+            beta[a] = 0.0;
+            gam[a] = 0.0;
+        }
+        return ORA_OK;
+    }
+    if (d[0] > d[1] || d[0] > d[2]) return ORA_EINVAL;
+    double ry = (d[0] / d[1]) * (d[0] / d[1]);
+    double rz = (d[0] / d[2]) * (d[0] / d[2]);
+    beta[0] = 0.125;
+    beta[1] = ry / 8.0;
+    beta[2] = rz / 8.0;
+    if (variant == 1) {
+        gam[0] = gam[1] = gam[2] = 0.0;
+    } else {
+        gam[0] = ry * rz / 16.0;
+        gam[1] = rz / 16.0;
+        gam[2] = ry / 16.0;
+    }
+    for (int a = 0; a < 3; ++a) {
+        int t1 = (a + 1) % 3, t2 = (a + 2) % 3;
+        alpha[a] = 1.0 - 2.0 * beta[t1] - 2.0 * beta[t2] - 4.0 * gam[a];
+    }
+    return ORA_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* diagnostics                                                         */
+
+/* out[0] = total charge q sum w dV, out[1] = field energy 1/2 sum (E^2+B^2) dV,
+ * out[2] = kinetic energy m sum w (gamma - 1) dV, out[3] = max |J|. */
+void ora_diag(const ora_grid *g, int64_t np, const double *u, const double *w, double q, double m,
+              const double *E, const double *B, const double *J, double out[4]) {
+    int64_t nc = ncell(g);
+    double dv = g->d[0] * g->d[1] * g->d[2];
+    double charge = 0, ef = 0, ek = 0, mj = 0;
+    for (int64_t p = 0; p < np; ++p) {
+        double u2 = u[p] * u[p] + u[np + p] * u[np + p] + u[2 * np + p] * u[2 * np + p];
+        charge += q * w[p] * dv;
+        ek += m * w[p] * (sqrt(1.0 + u2) - 1.0) * dv;
+    }
+    for (int64_t f = 0; f < 3 * nc; ++f) {
+        ef += 0.5 * (E[f] * E[f] + B[f] * B[f]) * dv;
+        if (J && fabs(J[f]) > mj) mj = fabs(J[f]);
+    }
+    out[0] = charge;
+    out[1] = ef;
+    out[2] = ek;
+    out[3] = mj;
+}
+
+/* ------------------------------------------------------------------ */
+/* whole step                                                          */
+
+/* One PIC step for one species on a grid whose x boundary is periodic or
+ * bounded (no window motion here).  x, u: in/out; J: out (overwritten with
+ * J^{n+1/2}, after the filter when jpost == 1); E, B: in/out. x_prev (may be
+ * NULL) receives x^n.  Returns ORA_ENONFINITE if a non-finite value appears. */
+int ora_step(const ora_grid *g, int64_t np, double *x, double *u, const double *w, double q, double m,
+             double *E, double *B, double *J, int jpost, double *x_prev) {
+    int64_t nc = ncell(g);
+    double *x0 = (double *)malloc(sizeof(double) * 3 * np);
+    double *x1 = (double *)malloc(sizeof(double) * 3 * np);
+    memcpy(x0, x, sizeof(double) * 3 * np);
+    int st = ora_push(g, np, x, u, x1, q, m, E, B);
+    memset(J, 0, sizeof(double) * 3 * nc);
+    ora_deposit(g, np, x0, x1, w, q, J);
+    if (jpost == 1) ora_binomial(g, J);
+    ora_field_step(g, E, B, J);
+    if (x_prev) memcpy(x_prev, x0, sizeof(double) * 3 * np);
+    free(x0);
+    free(x1);
+    for (int64_t f = 0; f < 3 * nc && st == ORA_OK; ++f)
+        if (!isfinite(E[f]) || !isfinite(B[f])) st = ORA_ENONFINITE;
+    return st;
+}
