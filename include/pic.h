@@ -1,0 +1,212 @@
+/*
+ * pic.h -- C ABI of the MI355X particle-in-cell library (libpic355.so).
+ *
+ * The library advances the explicit electromagnetic PIC cycle of
+ * arXiv:1204.0838 (Section 1: fields on a grid, macroparticles in continuous
+ * phase space; Section 2, eq. 2.1: D_t B = -curl' E, D_t E = c^2 curl B - J/eps0)
+ * on one AMD Instinct MI355X (gfx950):
+ *
+ *   cubic B-spline gather of E, B (third-order shapes, Sections 1 and 3.1)
+ *   -> relativistic Boris push -> move -> charge-conserving (Esirkepov) cubic
+ *   deposit of J -> optional J filter -> FDTD update in Yee form (curl' = curl,
+ *   Section 1) or perfect-dispersion form (curl' with the transverse
+ *   smoothing stencils S_x, S_y, S_z of Section 2).
+ *
+ * Units are plasma-normalised (the w_pe of Section 1): lengths c/w_pe,
+ * times 1/w_pe, momenta u = gamma v / c, fields m_e c w_pe / e, densities n0;
+ * so c = eps0 = 1.  Electrons have q = -1, m = 1.  Ions are an immobile
+ * neutralising background and are not represented.
+ *
+ * Memory ownership: every device buffer (fields, particles, workspace) is
+ * allocated by the caller (e.g. PyTorch-ROCm tensors) and passed as a raw
+ * device pointer; the library stores the pointers and never allocates or
+ * frees device memory.  Host pointers are marked "host".
+ *
+ * Streams: all calls enqueue asynchronously on the caller's HIP stream given
+ * to pic_init_grid, except those documented as synchronising.
+ *
+ * Errors: every call returns pic_status (0 = OK, < 0 = error) and never
+ * throws.  The context keeps a sticky error whose text pic_last_error
+ * returns.  Device-side conditions (a particle moving one cell or more per
+ * step, a non-finite momentum, a tile overflow) set a device flag which the
+ * next synchronising call (pic_sync, pic_reduce, pic_species_view) reports.
+ *
+ * Threading: one context per host thread; calls on one context are not
+ * re-entrant.
+ *
+ * Field layout: each of the nine component arrays E[3], B[3], J[3] is a dense
+ * FP32 array of n[0]*n[1]*n[2] values, x fastest: index(i,j,k) =
+ * i + n0*(j + n1*k).  Yee staggering: index (i,j,k) holds E_x(i+1/2,j,k),
+ * E_y(i,j+1/2,k), E_z(i,j,k+1/2), B_x(i,j+1/2,k+1/2), B_y(i+1/2,j,k+1/2),
+ * B_z(i+1/2,j+1/2,k), J like E.  y and z are periodic.  x is periodic, or
+ * (moving window) a circular buffer whose window origin advances one cell per
+ * shift; the two planes where the window ends meet see zero fields beyond.
+ *
+ * Particle layout (structure of arrays, one entry per macroparticle):
+ *   cell  int32   linear cell index i + n0*(j + n1*k) (storage coordinates);
+ *                 a negative value marks a removed particle
+ *   off   float[3] in-cell offsets in [0, 1): position = (i + off_x) dx, ...
+ *   u     float[3] u = gamma v / c
+ *   w     float   density weight n/ppc (charge per cell volume q*w)
+ *   id    int32   caller's tag, carried through sorting
+ */
+#ifndef PIC355_H
+#define PIC355_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PIC_OK = 0,
+    PIC_EINVAL = -1,     /* invalid argument or descriptor */
+    PIC_ENOMEM = -2,     /* workspace or particle capacity too small */
+    PIC_EDEVICE = -3,    /* a HIP runtime call failed */
+    PIC_EOVERFLOW = -4,  /* tile / capacity overflow detected on the device */
+    PIC_ENONFINITE = -5, /* non-finite momentum detected on the device */
+    PIC_ECFL = -6,       /* a particle moved >= 1 cell in a step, or the time step breaks stability */
+    PIC_ESTATE = -7      /* call out of order (e.g. deposit before gather_push) */
+} pic_status;
+
+enum { PIC_SOLVER_YEE = 0, PIC_SOLVER_PD = 1 };
+enum { PIC_BC_PERIODIC = 0, PIC_BC_MOVING_WINDOW = 1 };
+enum { PIC_JPOST_NONE = 0, PIC_JPOST_BINOMIAL = 1, PIC_JPOST_DENOISER = 2 };
+
+/* Grid and solver descriptor.
+ *   n[3], d[3]   cells and cell sizes; every n >= 4.
+ *   dt           time step.  Yee: must satisfy the 3D Courant limit
+ *                dt < 1/sqrt(sum 1/d^2).  PD (Section 2): requires
+ *                d[0] <= d[1], d[2] (the paper's only constraint) and
+ *                dt <= d[0] (c dt = dx gives no axial dispersion).
+ *   solver       PIC_SOLVER_YEE or PIC_SOLVER_PD.
+ *   pd_variant   PD stencil coefficients: 0 = with corner weights,
+ *                1 = corner weights zero.
+ *   bc_x         PIC_BC_PERIODIC or PIC_BC_MOVING_WINDOW.
+ *   jpost        current post-processing before the field update.
+ *   tile[3]      cells per particle tile of the fused step (0 = default 8).
+ *   sort_interval steps between cell sorts in pic_step (0 = default). */
+typedef struct {
+    int32_t n[3];
+    int32_t solver;
+    double d[3];
+    double dt;
+    int32_t pd_variant;
+    int32_t bc_x;
+    int32_t jpost;
+    int32_t tile[3];
+    int32_t sort_interval;
+    int32_t reserved_[3];
+} pic_grid_desc;
+
+/* Caller-owned FP32 device arrays, each n[0]*n[1]*n[2] values (layout above). */
+typedef struct {
+    float *E[3];
+    float *B[3];
+    float *J[3];
+} pic_field_bufs;
+
+/* Caller-owned particle arrays of one species (device memory, SoA, `capacity`
+ * entries each).  q, m in units of e, m_e. */
+typedef struct {
+    double q, m;
+    int64_t capacity;
+    int32_t *cell;
+    float *off[3];
+    float *u[3];
+    float *w;
+    int32_t *id;
+} pic_species_bufs;
+
+/* FP64 diagnostics (pic_reduce). */
+typedef struct {
+    double charge;      /* sum q w dV over live particles */
+    double e_field;     /* 1/2 sum (E^2 + B^2) dV */
+    double e_kin;       /* sum m w (gamma - 1) dV */
+    double max_abs_J;   /* max |J| over the three components */
+    int64_t n_particles;/* live particles over all species */
+    int64_t step;       /* completed steps */
+} pic_diag;
+
+typedef struct pic_ctx pic_ctx;
+
+/* Bytes of device workspace pic_init_grid needs for this grid and a total
+ * particle capacity (summed over species) of max_particles.  Pure host. */
+size_t pic_workspace_bytes(const pic_grid_desc *desc, int64_t max_particles);
+
+/* Validate a descriptor without touching the GPU.  On error writes a message
+ * into msg (host, msg_len bytes, may be NULL).  Pure host. */
+pic_status pic_validate_grid(const pic_grid_desc *desc, char *msg, size_t msg_len);
+
+/* Create a context.  desc, fields: host structs, copied.  workspace: device
+ * buffer of at least pic_workspace_bytes(desc, max_particles) bytes, 256-byte
+ * aligned, owned by the caller and kept alive until pic_destroy.  stream:
+ * hipStream_t of the caller (NULL = default stream).  On success *out holds
+ * the new context; on failure *out is NULL.  Fields are not modified. */
+pic_status pic_init_grid(pic_ctx **out, const pic_grid_desc *desc, const pic_field_bufs *fields,
+                         void *workspace, size_t workspace_bytes, int64_t max_particles, void *stream);
+
+/* Register a species.  bufs: host struct, copied; the arrays must already
+ * hold n_particles valid particles (0 <= n_particles <= capacity), each with
+ * cell in [0, ncells) and off in [0, 1).  *species_out (host) receives the
+ * species index.  Asynchronous. */
+pic_status pic_init_species(pic_ctx *ctx, const pic_species_bufs *bufs, int64_t n_particles,
+                            int32_t *species_out);
+
+/* Field gather + Boris push + move for one species: x^n, u^{n-1/2} ->
+ * x^{n+1}, u^{n+1/2}, using E^n, B^n.  Keeps x^n in the workspace for
+ * pic_deposit.  Asynchronous. */
+pic_status pic_gather_push(pic_ctx *ctx, int32_t species);
+
+/* Charge-conserving cubic deposit of the species' motion x^n -> x^{n+1}
+ * (the last pic_gather_push) into the exact fixed-point current accumulator;
+ * then J (FP32) is set to the accumulated current of all species deposited
+ * since the last field step.  Asynchronous. */
+pic_status pic_deposit(pic_ctx *ctx, int32_t species);
+
+/* J post-processing (desc.jpost), then B^{n+1/2} = B^n - dt/2 curl'E^n,
+ * E^{n+1} = E^n + dt (curl B^{n+1/2} - J), B^{n+1} = B^{n+1/2} - dt/2 curl'E^{n+1}
+ * (Section 2, eq. 2.1), then clears the current accumulator.  After a
+ * filter, J holds the filtered current.  Asynchronous. */
+pic_status pic_field_step(pic_ctx *ctx);
+
+/* nsteps full production steps: periodic cell sort, fused tiled
+ * gather+push+deposit of every species, J post-processing, field update and
+ * window motion.  Equal to pic_gather_push + pic_deposit (all species) +
+ * pic_field_step per step, bit for bit.  Asynchronous. */
+pic_status pic_step(pic_ctx *ctx, int32_t nsteps);
+
+/* Counting sort of one species by tile and cell; drops removed particles.
+ * The species' data may move to the workspace copy (see pic_species_view).
+ * Asynchronous. */
+pic_status pic_sort(pic_ctx *ctx, int32_t species);
+
+/* Current device arrays and live count of a species (host struct out).
+ * Synchronises the stream and reports device-side errors. */
+pic_status pic_species_view(pic_ctx *ctx, int32_t species, pic_species_bufs *out, int64_t *n_live);
+
+/* Continuity check of the last gather_push/deposit pair, FP64 on the device:
+ * max over nodes of |(rho^{n+1} - rho^n) dx/dt + sum_d (dx/d_d)(J_d - J_d[-e_d])|
+ * with rho deposited in FP64 from the stored FP32 positions and J the FP32
+ * current.  *resid and *max_abs_j are host outputs.  Synchronises. */
+pic_status pic_continuity(pic_ctx *ctx, int32_t species, double *resid, double *max_abs_j);
+
+/* FP64 diagnostics (host output).  Synchronises; reports device errors. */
+pic_status pic_reduce(pic_ctx *ctx, pic_diag *host_out);
+
+/* Wait for queued work; report device-side errors. */
+pic_status pic_sync(pic_ctx *ctx);
+
+/* Text of the sticky error (never NULL). */
+const char *pic_last_error(const pic_ctx *ctx);
+
+/* Release the context (host memory only; caller buffers are untouched). */
+void pic_destroy(pic_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PIC355_H */

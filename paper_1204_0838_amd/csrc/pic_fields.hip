@@ -1,0 +1,209 @@
+// FDTD field kernels: the B half step with the (optionally smoothed) curl of E,
+// the E step with the standard curl of B and the current, the binomial current
+// filter, and small utility kernels.
+//
+// Boundaries: y and z periodic.  x periodic, or (moving window) a circular
+// buffer in which the two planes where the window ends meet see zero-valued
+// ghost fields across that seam.
+#include "pic_internal.h"
+
+namespace pic {
+
+// Neighbour indices of one cell along each axis with the boundary rule.
+struct Nbr {
+    int i, j, k;              // cell
+    int ip, im, jp, jm, kp, km;  // neighbour coordinates (wrapped)
+    bool xp_ok, xm_ok;        // false when the x neighbour lies across the window seam
+};
+
+__device__ __forceinline__ Nbr neighbours(const Geom& g, int idx) {
+    Nbr n;
+    n.k = idx / g.nxy;
+    const int r = idx - n.k * g.nxy;
+    n.j = r / g.n[0];
+    n.i = r - n.j * g.n[0];
+    n.ip = n.i + 1 == g.n[0] ? 0 : n.i + 1;
+    n.im = n.i == 0 ? g.n[0] - 1 : n.i - 1;
+    n.jp = n.j + 1 == g.n[1] ? 0 : n.j + 1;
+    n.jm = n.j == 0 ? g.n[1] - 1 : n.j - 1;
+    n.kp = n.k + 1 == g.n[2] ? 0 : n.k + 1;
+    n.km = n.k == 0 ? g.n[2] - 1 : n.k - 1;
+    n.xp_ok = true;
+    n.xm_ok = true;
+    if (g.window) {
+        int xw = n.i - g.origin;
+        if (xw < 0) xw += g.n[0];
+        n.xp_ok = xw != g.n[0] - 1;
+        n.xm_ok = xw != 0;
+    }
+    return n;
+}
+
+__device__ __forceinline__ int at(const Geom& g, int i, int j, int k) { return i + g.n[0] * (j + g.n[1] * k); }
+
+// Transverse smoothing S_axis of F at cell (i,j,k) (Section 2 stencil):
+// centre alpha_axis, +-t1 neighbours beta_t1, +-t2 neighbours beta_t2, the four
+// corners gamma_{t1 t2}; t1 = axis+1, t2 = axis+2 cyclically.  x neighbours
+// across the window seam read as zero.  Coordinates are of the evaluation
+// point, which may itself be the +1 neighbour of the cell being updated.
+template <int AXIS>
+__device__ __forceinline__ float smooth(const Geom& g, const PDCoef& c, const float* __restrict__ F, int i, int j,
+                                        int k) {
+    // neighbours of (i,j,k) along each axis, with seam handling on x
+    const int ip = i + 1 == g.n[0] ? 0 : i + 1, im = i == 0 ? g.n[0] - 1 : i - 1;
+    const int jp = j + 1 == g.n[1] ? 0 : j + 1, jm = j == 0 ? g.n[1] - 1 : j - 1;
+    const int kp = k + 1 == g.n[2] ? 0 : k + 1, km = k == 0 ? g.n[2] - 1 : k - 1;
+    bool xp = true, xm = true;
+    if (g.window) {
+        int xw = i - g.origin;
+        if (xw < 0) xw += g.n[0];
+        xp = xw != g.n[0] - 1;
+        xm = xw != 0;
+    }
+    const float ctr = F[at(g, i, j, k)];
+    if (AXIS == 0) {   // smoothing in y (beta_y) and z (beta_z), corners gamma_yz
+        const float ny = F[at(g, i, jp, k)] + F[at(g, i, jm, k)];
+        const float nz = F[at(g, i, j, kp)] + F[at(g, i, j, km)];
+        const float cr = (F[at(g, i, jp, kp)] + F[at(g, i, jm, kp)]) + (F[at(g, i, jp, km)] + F[at(g, i, jm, km)]);
+        return fmaf(c.gam[0], cr, fmaf(c.beta[2], nz, fmaf(c.beta[1], ny, c.alpha[0] * ctr)));
+    } else if (AXIS == 1) {   // smoothing in z (beta_z) and x (beta_x), corners gamma_zx
+        const float nz = F[at(g, i, j, kp)] + F[at(g, i, j, km)];
+        const float fxp = xp ? F[at(g, ip, j, k)] : 0.0f, fxm = xm ? F[at(g, im, j, k)] : 0.0f;
+        const float nx = fxp + fxm;
+        const float cr = ((xp ? F[at(g, ip, j, kp)] : 0.0f) + (xm ? F[at(g, im, j, kp)] : 0.0f)) +
+                         ((xp ? F[at(g, ip, j, km)] : 0.0f) + (xm ? F[at(g, im, j, km)] : 0.0f));
+        return fmaf(c.gam[1], cr, fmaf(c.beta[0], nx, fmaf(c.beta[2], nz, c.alpha[1] * ctr)));
+    } else {   // smoothing in x (beta_x) and y (beta_y), corners gamma_xy
+        const float fxp = xp ? F[at(g, ip, j, k)] : 0.0f, fxm = xm ? F[at(g, im, j, k)] : 0.0f;
+        const float nx = fxp + fxm;
+        const float ny = F[at(g, i, jp, k)] + F[at(g, i, jm, k)];
+        const float cr = ((xp ? F[at(g, ip, jp, k)] : 0.0f) + (xm ? F[at(g, im, jp, k)] : 0.0f)) +
+                         ((xp ? F[at(g, ip, jm, k)] : 0.0f) + (xm ? F[at(g, im, jm, k)] : 0.0f));
+        return fmaf(c.gam[2], cr, fmaf(c.beta[1], ny, fmaf(c.beta[0], nx, c.alpha[2] * ctr)));
+    }
+}
+
+// Value of S_axis F at (i,j,k), or F itself for the Yee scheme.
+template <bool PD, int AXIS>
+__device__ __forceinline__ float sval(const Geom& g, const PDCoef& c, const float* __restrict__ F, int i, int j,
+                                      int k) {
+    if (PD) return smooth<AXIS>(g, c, F, i, j, k);
+    return F[at(g, i, j, k)];
+}
+
+// B -= h curl' E with forward differences; curl'_x = D_y S_y E_z - D_z S_z E_y, cyclic.
+template <bool PD>
+__global__ void __launch_bounds__(256) k_bhalf(Geom g, PDCoef c, const float* __restrict__ Ex,
+                                               const float* __restrict__ Ey, const float* __restrict__ Ez,
+                                               float* __restrict__ Bx, float* __restrict__ By,
+                                               float* __restrict__ Bz, float h) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= g.ncell) return;
+    const Nbr n = neighbours(g, idx);
+    // E at the +x neighbour is zero across the window seam
+    const float dyEz = (sval<PD, 1>(g, c, Ez, n.i, n.jp, n.k) - sval<PD, 1>(g, c, Ez, n.i, n.j, n.k)) * g.inv_d[1];
+    const float dzEy = (sval<PD, 2>(g, c, Ey, n.i, n.j, n.kp) - sval<PD, 2>(g, c, Ey, n.i, n.j, n.k)) * g.inv_d[2];
+    const float dzEx = (sval<PD, 2>(g, c, Ex, n.i, n.j, n.kp) - sval<PD, 2>(g, c, Ex, n.i, n.j, n.k)) * g.inv_d[2];
+    const float ezp = n.xp_ok ? sval<PD, 0>(g, c, Ez, n.ip, n.j, n.k) : 0.0f;
+    const float eyp = n.xp_ok ? sval<PD, 0>(g, c, Ey, n.ip, n.j, n.k) : 0.0f;
+    const float dxEz = (ezp - sval<PD, 0>(g, c, Ez, n.i, n.j, n.k)) * g.inv_d[0];
+    const float dxEy = (eyp - sval<PD, 0>(g, c, Ey, n.i, n.j, n.k)) * g.inv_d[0];
+    const float dyEx = (sval<PD, 1>(g, c, Ex, n.i, n.jp, n.k) - sval<PD, 1>(g, c, Ex, n.i, n.j, n.k)) * g.inv_d[1];
+    Bx[idx] -= h * (dyEz - dzEy);
+    By[idx] -= h * (dzEx - dxEz);
+    Bz[idx] -= h * (dxEy - dyEx);
+}
+
+// E += dt (curl B - J) with backward differences.
+__global__ void __launch_bounds__(256) k_efull(Geom g, float* __restrict__ Ex, float* __restrict__ Ey,
+                                               float* __restrict__ Ez, const float* __restrict__ Bx,
+                                               const float* __restrict__ By, const float* __restrict__ Bz,
+                                               const float* __restrict__ Jx, const float* __restrict__ Jy,
+                                               const float* __restrict__ Jz) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= g.ncell) return;
+    const Nbr n = neighbours(g, idx);
+    const float bz = Bz[idx], by = By[idx], bx = Bx[idx];
+    const float bzm_x = n.xm_ok ? Bz[at(g, n.im, n.j, n.k)] : 0.0f;
+    const float bym_x = n.xm_ok ? By[at(g, n.im, n.j, n.k)] : 0.0f;
+    const float dyBz = (bz - Bz[at(g, n.i, n.jm, n.k)]) * g.inv_d[1];
+    const float dzBy = (by - By[at(g, n.i, n.j, n.km)]) * g.inv_d[2];
+    const float dzBx = (bx - Bx[at(g, n.i, n.j, n.km)]) * g.inv_d[2];
+    const float dxBz = (bz - bzm_x) * g.inv_d[0];
+    const float dxBy = (by - bym_x) * g.inv_d[0];
+    const float dyBx = (bx - Bx[at(g, n.i, n.jm, n.k)]) * g.inv_d[1];
+    Ex[idx] += g.dt * ((dyBz - dzBy) - Jx[idx]);
+    Ey[idx] += g.dt * ((dzBx - dxBz) - Jy[idx]);
+    Ez[idx] += g.dt * ((dxBy - dyBx) - Jz[idx]);
+}
+
+// One (1/4, 1/2, 1/4) pass along each axis, as the separable 27-point product
+// stencil, src -> dst (distinct buffers).
+__global__ void __launch_bounds__(256) k_binomial(Geom g, const float* __restrict__ s0, const float* __restrict__ s1,
+                                                  const float* __restrict__ s2, float* __restrict__ d0,
+                                                  float* __restrict__ d1, float* __restrict__ d2) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= g.ncell) return;
+    const Nbr n = neighbours(g, idx);
+    const float wx[3] = {0.25f, 0.5f, 0.25f};
+    const int xs[3] = {n.im, n.i, n.ip};
+    const bool xok[3] = {n.xm_ok, true, n.xp_ok};
+    const int ys[3] = {n.jm, n.j, n.jp};
+    const int zs[3] = {n.km, n.k, n.kp};
+    const float* src[3] = {s0, s1, s2};
+    float* dst[3] = {d0, d1, d2};
+#pragma unroll
+    for (int comp = 0; comp < 3; ++comp) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            float ay = 0.0f;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                float ax = 0.0f;
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    if (xok[a]) ax = fmaf(wx[a], src[comp][at(g, xs[a], ys[b], zs[c])], ax);
+                ay = fmaf(wx[b], ax, ay);
+            }
+            acc = fmaf(wx[c], ay, acc);
+        }
+        dst[comp][idx] = acc;
+    }
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+hipError_t launch_bhalf(const Geom& g, int pd, const PDCoef& c, float* const E[3], float* const B[3], float h,
+                        hipStream_t st) {
+    const int nb = (g.ncell + 255) / 256;
+    if (pd)
+        hipLaunchKernelGGL(k_bhalf<true>, dim3(nb), dim3(256), 0, st, g, c, E[0], E[1], E[2], B[0], B[1], B[2], h);
+    else
+        hipLaunchKernelGGL(k_bhalf<false>, dim3(nb), dim3(256), 0, st, g, c, E[0], E[1], E[2], B[0], B[1], B[2], h);
+    return hipGetLastError();
+}
+
+hipError_t launch_efull(const Geom& g, float* const E[3], float* const B[3], float* const J[3], hipStream_t st) {
+    const int nb = (g.ncell + 255) / 256;
+    hipLaunchKernelGGL(k_efull, dim3(nb), dim3(256), 0, st, g, E[0], E[1], E[2], B[0], B[1], B[2], J[0], J[1], J[2]);
+    return hipGetLastError();
+}
+
+hipError_t launch_binomial(const Geom& g, float* const src[3], float* const dst[3], hipStream_t st) {
+    const int nb = (g.ncell + 255) / 256;
+    hipLaunchKernelGGL(k_binomial, dim3(nb), dim3(256), 0, st, g, src[0], src[1], src[2], dst[0], dst[1], dst[2]);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t nb = (n + 255) / 256;
+    hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)nb), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+}  // namespace pic

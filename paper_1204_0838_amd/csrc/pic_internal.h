@@ -1,0 +1,48 @@
+// Internal interface between the host ABI (pic_abi.hip) and the kernel
+// translation units.  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pic_device.h"
+
+namespace pic {
+
+struct FieldPtrs {
+    float* E[3];
+    float* B[3];
+};
+
+// particle kernels (pic_particles.hip)
+hipError_t launch_gather_push(const Geom& g, const FieldPtrs& f, const SpeciesDev& s, const PrevDev& prev,
+                              const int* d_count, int max_count, int* d_err, hipStream_t st);
+hipError_t launch_deposit(const Geom& g, const SpeciesDev& s, const PrevDev& prev, const int* d_count,
+                          int max_count, unsigned long long* acc, hipStream_t st);
+hipError_t launch_jfinal(const Geom& g, unsigned long long* acc, float* const J[3], const double scale[3],
+                         int zero_acc, hipStream_t st);
+
+// field kernels (pic_fields.hip)
+hipError_t launch_bhalf(const Geom& g, int pd, const PDCoef& c, float* const E[3], float* const B[3], float h,
+                        hipStream_t st);
+hipError_t launch_efull(const Geom& g, float* const E[3], float* const B[3], float* const J[3], hipStream_t st);
+hipError_t launch_binomial(const Geom& g, float* const src[3], float* const dst[3], hipStream_t st);
+hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t st);
+
+// reductions (pic_reduce.hip)
+// out[0] += sum q w dV, out[1] += sum m w (gamma-1) dV (FP64); cnt[0] += live count
+hipError_t launch_diag_particles(const Geom& g, const SpeciesDev& s, double q, double m, double dv,
+                                 const int* d_count, int max_count, double* out, unsigned long long* cnt,
+                                 hipStream_t st);
+// out[2] += 1/2 sum (E^2 + B^2) dV; maxbits[0] = max |J| as float bits
+hipError_t launch_diag_fields(const Geom& g, float* const E[3], float* const B[3], float* const J[3], double dv,
+                              double* out, unsigned int* maxbits, hipStream_t st);
+// rho += sign * q w S S S (FP64 atomics) for positions (cell, off)
+hipError_t launch_rho(const Geom& g, const int* cell, float* const off[3], const float* w, double q, double sign,
+                      const int* d_count, int max_count, double* rho, hipStream_t st);
+// max over nodes of |rho dx/dt + sum_d (dx/d_d)(J_d - J_d[-e_d])| as double bits
+// ry = dx/dy, rz = dx/dz
+hipError_t launch_continuity(const Geom& g, const double* rho, float* const J[3], double dx_dt, double ry,
+                             double rz, unsigned long long* maxbits, hipStream_t st);
+
+}  // namespace pic

@@ -1,0 +1,280 @@
+"""Thin ctypes binding of the C ABI in include/pic.h (libpic355.so).
+
+Argument marshalling only: every step of the PIC cycle runs in the HIP
+library.  PyTorch-ROCm provides the device memory (fields, particles,
+workspace) and the stream; this module passes raw pointers across the ABI
+and turns status codes into exceptions.  There is no fallback: without the
+built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpic355.so")
+
+PIC_OK, PIC_EINVAL, PIC_ENOMEM, PIC_EDEVICE, PIC_EOVERFLOW, PIC_ENONFINITE, PIC_ECFL, PIC_ESTATE = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+STATUS_NAMES = {0: "PIC_OK", -1: "PIC_EINVAL", -2: "PIC_ENOMEM", -3: "PIC_EDEVICE", -4: "PIC_EOVERFLOW",
+                -5: "PIC_ENONFINITE", -6: "PIC_ECFL", -7: "PIC_ESTATE"}
+SOLVERS = {"yee": 0, "pd": 1}
+JPOST = {"none": 0, "binomial": 1, "denoiser": 2}
+
+
+class PicError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("solver", ctypes.c_int32), ("d", ctypes.c_double * 3),
+                ("dt", ctypes.c_double), ("pd_variant", ctypes.c_int32), ("bc_x", ctypes.c_int32),
+                ("jpost", ctypes.c_int32), ("tile", ctypes.c_int32 * 3), ("sort_interval", ctypes.c_int32),
+                ("reserved_", ctypes.c_int32 * 3)]
+
+
+_vp = ctypes.c_void_p
+
+
+class FieldBufs(ctypes.Structure):
+    _fields_ = [("E", _vp * 3), ("B", _vp * 3), ("J", _vp * 3)]
+
+
+class SpeciesBufs(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_double), ("m", ctypes.c_double), ("capacity", ctypes.c_int64),
+                ("cell", _vp), ("off", _vp * 3), ("u", _vp * 3), ("w", _vp), ("id", _vp)]
+
+
+class Diag(ctypes.Structure):
+    _fields_ = [("charge", ctypes.c_double), ("e_field", ctypes.c_double), ("e_kin", ctypes.c_double),
+                ("max_abs_J", ctypes.c_double), ("n_particles", ctypes.c_int64), ("step", ctypes.c_int64)]
+
+
+# every symbol the header declares, with its ctypes signature
+_SIGS = {
+    "pic_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(GridDesc), ctypes.c_int64]),
+    "pic_validate_grid": (ctypes.c_int, [ctypes.POINTER(GridDesc), ctypes.c_char_p, ctypes.c_size_t]),
+    "pic_init_grid": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(GridDesc), ctypes.POINTER(FieldBufs), _vp,
+                                     ctypes.c_size_t, ctypes.c_int64, _vp]),
+    "pic_init_species": (ctypes.c_int, [_vp, ctypes.POINTER(SpeciesBufs), ctypes.c_int64,
+                                        ctypes.POINTER(ctypes.c_int32)]),
+    "pic_gather_push": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "pic_deposit": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "pic_field_step": (ctypes.c_int, [_vp]),
+    "pic_step": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "pic_sort": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "pic_species_view": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(SpeciesBufs),
+                                        ctypes.POINTER(ctypes.c_int64)]),
+    "pic_continuity": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_double)]),
+    "pic_reduce": (ctypes.c_int, [_vp, ctypes.POINTER(Diag)]),
+    "pic_sync": (ctypes.c_int, [_vp]),
+    "pic_last_error": (ctypes.c_char_p, [_vp]),
+    "pic_destroy": (None, [_vp]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libpic355.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1204_0838_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def make_desc(n, d, dt, solver="yee", bc_x=0, jpost="none", pd_variant=0, tile=(0, 0, 0), sort_interval=0):
+    g = GridDesc()
+    for a in range(3):
+        g.n[a] = int(n[a])
+        g.d[a] = float(d[a])
+        g.tile[a] = int(tile[a])
+    g.dt = float(dt)
+    g.solver = SOLVERS[solver] if isinstance(solver, str) else int(solver)
+    g.bc_x = int(bc_x)
+    g.jpost = JPOST[jpost] if isinstance(jpost, str) else int(jpost)
+    g.pd_variant = int(pd_variant)
+    g.sort_interval = int(sort_interval)
+    return g
+
+
+def validate(desc: GridDesc):
+    """Host-only descriptor check: returns (status, message)."""
+    buf = ctypes.create_string_buffer(256)
+    st = lib().pic_validate_grid(ctypes.byref(desc), buf, 256)
+    return st, buf.value.decode()
+
+
+def workspace_bytes(desc: GridDesc, max_particles: int) -> int:
+    return int(lib().pic_workspace_bytes(ctypes.byref(desc), int(max_particles)))
+
+
+def _ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Simulation:
+    """A grid with its fields, workspace and species, driven through the C ABI.
+
+    Fields are torch tensors ``E, B, J`` of shape [3, nz, ny, nx] (float32,
+    x fastest) on ``device``; particles live in caller-owned torch tensors.
+    """
+
+    def __init__(self, n, d, dt, solver="yee", bc_x=0, jpost="none", pd_variant=0, tile=(0, 0, 0),
+                 sort_interval=0, max_particles=0, device="cuda:0", stream=None):
+        self.desc = make_desc(n, d, dt, solver, bc_x, jpost, pd_variant, tile, sort_interval)
+        st, msg = validate(self.desc)
+        if st != PIC_OK:
+            raise PicError(st, msg)
+        self.device = torch.device(device)
+        self.n = tuple(int(v) for v in n)
+        shape = (3, self.n[2], self.n[1], self.n[0])
+        self.E = torch.zeros(shape, dtype=torch.float32, device=self.device)
+        self.B = torch.zeros(shape, dtype=torch.float32, device=self.device)
+        self.J = torch.zeros(shape, dtype=torch.float32, device=self.device)
+        self.max_particles = int(max_particles)
+        nbytes = workspace_bytes(self.desc, self.max_particles)
+        if nbytes == 0:
+            raise PicError(PIC_EINVAL, "workspace size query failed")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws_off = (-base) % 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        fb = FieldBufs()
+        for a in range(3):
+            fb.E[a] = self.E[a].data_ptr()
+            fb.B[a] = self.B[a].data_ptr()
+            fb.J[a] = self.J[a].data_ptr()
+        h = ctypes.c_void_p()
+        st = lib().pic_init_grid(ctypes.byref(h), ctypes.byref(self.desc), ctypes.byref(fb),
+                                 ctypes.c_void_p(base + self._ws_off), nbytes, self.max_particles,
+                                 ctypes.c_void_p(self.stream.cuda_stream))
+        if st != PIC_OK:
+            raise PicError(st, "pic_init_grid failed")
+        self.handle = h
+        self.species = []
+
+    # ------------------------------------------------------------ plumbing
+    def _check(self, st):
+        if st != PIC_OK:
+            msg = lib().pic_last_error(self.handle)
+            raise PicError(st, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().pic_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ species
+    def add_species(self, cell, off, u, w, ids, q=-1.0, m=1.0, capacity=None):
+        """Register a species from host or device arrays (copied into new device tensors)."""
+        n = int(len(cell))
+        cap = int(capacity if capacity is not None else n)
+        dev = self.device
+
+        def buf(src, dtype):
+            t = torch.zeros(cap, dtype=dtype, device=dev)
+            if n:
+                t[:n] = torch.as_tensor(np.asarray(src) if not torch.is_tensor(src) else src).to(dev, dtype)
+            return t
+
+        sp = {"cell": buf(cell, torch.int32), "off": [buf(off[a], torch.float32) for a in range(3)],
+              "u": [buf(u[a], torch.float32) for a in range(3)], "w": buf(w, torch.float32),
+              "id": buf(ids, torch.int32), "q": float(q), "m": float(m), "capacity": cap}
+        sb = SpeciesBufs()
+        sb.q, sb.m, sb.capacity = float(q), float(m), cap
+        sb.cell = sp["cell"].data_ptr()
+        for a in range(3):
+            sb.off[a] = sp["off"][a].data_ptr()
+            sb.u[a] = sp["u"][a].data_ptr()
+        sb.w = sp["w"].data_ptr()
+        sb.id = sp["id"].data_ptr()
+        idx = ctypes.c_int32()
+        self._check(lib().pic_init_species(self.handle, ctypes.byref(sb), n, ctypes.byref(idx)))
+        self.species.append(sp)
+        return idx.value
+
+    def add_particles(self, p, capacity=None):
+        """Register an ``inputs.Particles`` set."""
+        return self.add_species(p.cell, p.off, p.u, p.w, p.id, p.q, p.m, capacity)
+
+    # ------------------------------------------------------------ the cycle
+    def gather_push(self, s=0):
+        self._check(lib().pic_gather_push(self.handle, s))
+
+    def deposit(self, s=0):
+        self._check(lib().pic_deposit(self.handle, s))
+
+    def field_step(self):
+        self._check(lib().pic_field_step(self.handle))
+
+    def step(self, nsteps=1):
+        self._check(lib().pic_step(self.handle, int(nsteps)))
+
+    def sort(self, s=0):
+        self._check(lib().pic_sort(self.handle, s))
+
+    def sync(self):
+        self._check(lib().pic_sync(self.handle))
+
+    def continuity(self, s=0):
+        r, j = ctypes.c_double(), ctypes.c_double()
+        self._check(lib().pic_continuity(self.handle, s, ctypes.byref(r), ctypes.byref(j)))
+        return r.value, j.value
+
+    def reduce(self):
+        d = Diag()
+        self._check(lib().pic_reduce(self.handle, ctypes.byref(d)))
+        return {k: getattr(d, k) for k, _ in Diag._fields_}
+
+    # ------------------------------------------------------------ views
+    def _tensor_at(self, ptr, n, dtype, s):
+        """Tensor view of n elements at device address ptr (a species tensor or the workspace)."""
+        sp = self.species[s]
+        for t in [sp["cell"], sp["w"], sp["id"], *sp["off"], *sp["u"]]:
+            if t.data_ptr() == ptr:
+                return t[:n]
+        base = self.workspace.data_ptr()
+        off = ptr - base
+        if not (0 <= off < self.workspace.numel()):
+            raise PicError(PIC_EINVAL, "pointer outside the known buffers")
+        esz = torch.empty(0, dtype=dtype).element_size()
+        return self.workspace[off:off + n * esz].view(dtype)
+
+    def particles(self, s=0):
+        """Live-range device views of the species' current arrays (synchronises)."""
+        sb = SpeciesBufs()
+        n = ctypes.c_int64()
+        self._check(lib().pic_species_view(self.handle, s, ctypes.byref(sb), ctypes.byref(n)))
+        k = n.value
+        return {"cell": self._tensor_at(sb.cell, k, torch.int32, s),
+                "off": [self._tensor_at(sb.off[a], k, torch.float32, s) for a in range(3)],
+                "u": [self._tensor_at(sb.u[a], k, torch.float32, s) for a in range(3)],
+                "w": self._tensor_at(sb.w, k, torch.float32, s),
+                "id": self._tensor_at(sb.id, k, torch.int32, s), "count": k}
+
+    def particles_host(self, s=0):
+        """Numpy copy of the live particles: dict(cell, off[3,n], u[3,n], w, id)."""
+        v = self.particles(s)
+        return {"cell": v["cell"].cpu().numpy(), "off": np.stack([t.cpu().numpy() for t in v["off"]]),
+                "u": np.stack([t.cpu().numpy() for t in v["u"]]), "w": v["w"].cpu().numpy(),
+                "id": v["id"].cpu().numpy()}
