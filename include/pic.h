@@ -87,7 +87,16 @@ enum { PIC_JPOST_NONE = 0, PIC_JPOST_BINOMIAL = 1, PIC_JPOST_DENOISER = 2 };
  *   bc_x         PIC_BC_PERIODIC or PIC_BC_MOVING_WINDOW.
  *   jpost        current post-processing before the field update.
  *   tile[3]      cells per particle tile of the fused step (0 = default 8).
- *   sort_interval steps between cell sorts in pic_step (0 = default). */
+ *   sort_interval steps between cell sorts in pic_step (0 = default 2).
+ *   guard        cells a particle may drift out of its tile and still be
+ *                handled in LDS (0..3; a negative value selects the
+ *                default 1); beyond it the fused step uses global memory
+ *                for that particle.  The tile's LDS footprint
+ *                24 B x prod(T + 2 guard + 5) + 24 B x prod(T + 2 guard + 4)
+ *                must fit in 160 KiB.
+ *   threads      threads per tile workgroup (256, 512 or 1024; 0 = 512).
+ *   interleave   in-tile interleave stride of the sort (0 = default 17,
+ *                1 = plain cell order). */
 typedef struct {
     int32_t n[3];
     int32_t solver;
@@ -98,7 +107,9 @@ typedef struct {
     int32_t jpost;
     int32_t tile[3];
     int32_t sort_interval;
-    int32_t reserved_[3];
+    int32_t guard;
+    int32_t threads;
+    int32_t interleave;
 } pic_grid_desc;
 
 /* Caller-owned FP32 device arrays, each n[0]*n[1]*n[2] values (layout above). */
@@ -129,6 +140,36 @@ typedef struct {
     int64_t n_particles;/* live particles over all species */
     int64_t step;       /* completed steps */
 } pic_diag;
+
+/* Laser pulse launched in +x through the plane x = src_x dx (Section 3.1: a
+ * linearly polarised Gaussian pulse, polarised along y, entering from the
+ * plasma border).  Built from the vector potential
+ *   A_y(t) = a0 env(t) cos(omega0 (t - t_peak)),
+ *   env(t) = exp(-2 ln2 (t - t_peak)^2 / fwhm^2)   (intensity FWHM = fwhm),
+ * with E_y = -dA_y/dt (no DC part even for sub-cycle pulses) and transverse
+ * profile exp(-((y-yc)^2 + (z-zc)^2) / waist^2).  The incident wave
+ * E_y = B_z = e(t - (x - x_src)) f(y,z) enters through total-field /
+ * scattered-field corrections on the B_z plane behind and the E_y plane on
+ * the source, applied while t <= t_end and the window has not moved.
+ * Units: a0 in m_e c/e, omega0 in w_pe, lengths c/w_pe, times 1/w_pe. */
+typedef struct {
+    double a0, omega0, waist, fwhm, t_peak, t_end, yc, zc;
+    int32_t src_x;
+    int32_t pad_;
+} pic_laser_desc;
+
+/* Cold electron plasma of a species, loaded on a regular sub-cell lattice of
+ * ppc[0] x ppc[1] x ppc[2] particles per cell at offsets (k + 1/2)/ppc_d.
+ * Density along the lab-frame x (in cells): 0 before x_start, rising
+ * linearly over `ramp` cells, then n_plateau (in n0); each particle's weight
+ * is n(x_lab)/ppc at its own lab position; none is loaded where n = 0.
+ * Particle tag: ((X ny + j) nz + k) ppc + s (mod 2^31), X the lab cell,
+ * (j, k) the transverse cell, s the lattice slot. */
+typedef struct {
+    double x_start, ramp, n_plateau;
+    int32_t ppc[3];
+    int32_t pad_;
+} pic_plasma_desc;
 
 typedef struct pic_ctx pic_ctx;
 
@@ -198,6 +239,35 @@ pic_status pic_reduce(pic_ctx *ctx, pic_diag *host_out);
 
 /* Wait for queued work; report device-side errors. */
 pic_status pic_sync(pic_ctx *ctx);
+
+/* Laser source (host struct, copied; NULL removes it).  src_x must lie in
+ * [1, n[0] - 1); in moving-window mode the window must not start moving
+ * before t_end (checked by pic_set_window and here). */
+pic_status pic_set_laser(pic_ctx *ctx, const pic_laser_desc *laser);
+
+/* Plasma profile of a species (host struct, copied), used by
+ * pic_inject_plasma and by the moving window's injection of each newly
+ * covered slab. */
+pic_status pic_set_plasma(pic_ctx *ctx, int32_t species, const pic_plasma_desc *plasma);
+
+/* Append the species' cold plasma of window cells x in [x_begin, x_end) (all
+ * y, z) at the current window position.  Fails with PIC_ENOMEM if the
+ * species capacity could be exceeded (host-side bound); particles land
+ * outside the tile ranges until the next sort.  Asynchronous. */
+pic_status pic_inject_plasma(pic_ctx *ctx, int32_t species, int32_t x_begin, int32_t x_end);
+
+/* Moving window (desc.bc_x = PIC_BC_MOVING_WINDOW): after every step whose
+ * index + 1 >= start_step, the window advances one cell in +x at c (c dt =
+ * dx is required for this): the plane leaving at the back becomes the new
+ * leading plane with zero fields, and each species with a plasma profile
+ * gets the plasma of the newly covered cells loaded at window cell
+ * n[0] - 4.  Particles outside window cells [3, n[0] - 4] are removed (their
+ * shapes would reach across the window's ends). */
+pic_status pic_set_window(pic_ctx *ctx, int64_t start_step);
+
+/* Cells the window has moved and the storage x index of window cell 0
+ * (host outputs). */
+pic_status pic_window_state(pic_ctx *ctx, int64_t *shift, int32_t *origin);
 
 /* Text of the sticky error (never NULL). */
 const char *pic_last_error(const pic_ctx *ctx);

@@ -507,3 +507,130 @@ int ora_step(const ora_grid *g, int64_t np, double *x, double *u, const double *
         if (!isfinite(E[f]) || !isfinite(B[f])) st = ORA_ENONFINITE;
     return st;
 }
+
+/* ------------------------------------------------------------------ */
+/* laser-wakefield boundaries: laser source, moving window, plasma     */
+
+/* Linearly polarised (E along y) Gaussian pulse entering through the plane
+ * x = src_x dx, travelling in +x.  It is built from the vector potential
+ * A_y(t) = a0 env(t) cos(w0 (t - t_peak)), env = exp(-2 ln2 (t - t_peak)^2 / fwhm^2)
+ * (intensity FWHM = fwhm), so E_y = -dA_y/dt has no DC part; transverse
+ * profile exp(-((y-yc)^2 + (z-zc)^2) / waist^2).  The incident wave is
+ * E_y(x,t) = B_z(x,t) = e(t - (x - x_src)) f(y,z). */
+typedef struct {
+    double a0, omega0, waist, fwhm, t_peak, t_end, yc, zc;
+    int64_t src_x;
+} ora_laser;
+
+double ora_laser_e(const ora_laser *L, double t) {
+    double tau = t - L->t_peak;
+    double k = 2.0 * log(2.0) / (L->fwhm * L->fwhm);
+    double env = exp(-k * tau * tau);
+    double denv = -2.0 * k * tau * env;
+    double ph = L->omega0 * tau;
+    /* -d/dt [a0 env cos(ph)] */
+    return -L->a0 * (denv * cos(ph) - env * L->omega0 * sin(ph));
+}
+
+double ora_laser_profile(const ora_laser *L, double y, double z) {
+    double r2 = (y - L->yc) * (y - L->yc) + (z - L->zc) * (z - L->zc);
+    return exp(-r2 / (L->waist * L->waist));
+}
+
+/* Total-field / scattered-field injection on the source plane: x >= x_src
+ * holds the total field, x < x_src only what scatters back.  The B_z half
+ * step behind the plane sees the incident E_y(x_src, t) subtracted:
+ * B_z(src_x - 1/2) += h e(t) f / dx.  The E_y step on the plane sees the
+ * incident B_z(x_src - dx/2, t_half) added: E_y(src_x) += dt e(t_half + dx/2) f / dx. */
+void ora_laser_b_correction(const ora_grid *g, const ora_laser *L, double *B, double h, double t) {
+    int64_t nc = ncell(g);
+    int64_t i = L->src_x - 1;
+    if (i < 0 || i >= g->n[0]) return;
+    double e = ora_laser_e(L, t);
+    for (int64_t k = 0; k < g->n[2]; ++k)
+        for (int64_t j = 0; j < g->n[1]; ++j) {
+            double f = ora_laser_profile(L, (j + 0.5) * g->d[1], k * g->d[2]);
+            B[2 * nc + i + g->n[0] * (j + g->n[1] * k)] += h * e * f / g->d[0];
+        }
+}
+
+void ora_laser_e_correction(const ora_grid *g, const ora_laser *L, double *E, double t_half) {
+    int64_t nc = ncell(g);
+    int64_t i = L->src_x;
+    if (i < 0 || i >= g->n[0]) return;
+    double b = ora_laser_e(L, t_half + 0.5 * g->d[0]);
+    for (int64_t k = 0; k < g->n[2]; ++k)
+        for (int64_t j = 0; j < g->n[1]; ++j) {
+            double f = ora_laser_profile(L, (j + 0.5) * g->d[1], k * g->d[2]);
+            E[nc + i + g->n[0] * (j + g->n[1] * k)] += g->dt * b * f / g->d[0];
+        }
+}
+
+/* Field step of the step that starts at time t (E^n at t = n dt), with the
+ * laser source applied when L is non-NULL. */
+void ora_field_step_laser(const ora_grid *g, double *E, double *B, const double *J, const ora_laser *L,
+                          double t) {
+    b_half(g, E, B, 0.5 * g->dt);
+    if (L) ora_laser_b_correction(g, L, B, 0.5 * g->dt, t);
+    e_full(g, E, B, J);
+    if (L) ora_laser_e_correction(g, L, E, t + 0.5 * g->dt);
+    b_half(g, E, B, 0.5 * g->dt);
+    if (L) ora_laser_b_correction(g, L, B, 0.5 * g->dt, t + g->dt);
+}
+
+/* Moving window, one cell: every field moves one cell toward -x (the plane
+ * at x index 0 leaves the box) and the new leading plane is vacuum. */
+void ora_window_shift(const ora_grid *g, double *E, double *B) {
+    int64_t nc = ncell(g), nx = g->n[0];
+    for (int comp = 0; comp < 6; ++comp) {
+        double *F = comp < 3 ? E + comp * nc : B + (comp - 3) * nc;
+        for (int64_t k = 0; k < g->n[2]; ++k)
+            for (int64_t j = 0; j < g->n[1]; ++j) {
+                double *row = F + nx * (j + g->n[1] * k);
+                for (int64_t i = 0; i + 1 < nx; ++i) row[i] = row[i + 1];
+                row[nx - 1] = 0.0;
+            }
+    }
+}
+
+/* Electron density profile along the lab-frame x (in cells): zero before
+ * x_start, a linear ramp over `ramp` cells, then the plateau n_plateau. */
+typedef struct {
+    double x_start, ramp, n_plateau;
+    int32_t ppc[3];
+} ora_plasma;
+
+double ora_density(const ora_plasma *P, double x_cells) {
+    if (x_cells < P->x_start) return 0.0;
+    if (P->ramp > 0.0 && x_cells < P->x_start + P->ramp) return P->n_plateau * (x_cells - P->x_start) / P->ramp;
+    return P->n_plateau;
+}
+
+/* Cold plasma loading of window cells [xb, xe) when the window has moved by
+ * `shift` cells: ppc[0] x ppc[1] x ppc[2] particles per cell on the sub-cell
+ * lattice (k + 1/2)/ppc_d, weight n(x_lab)/ppc evaluated at each particle's
+ * lab position, none where n = 0.  Tag: ((X ny + j) nz + k) ppc + s (mod 2^31),
+ * X the lab cell.  Writes window positions x[3][cap], weights, tags; returns
+ * the number loaded (at most cap). */
+int64_t ora_inject(const ora_grid *g, const ora_plasma *P, int64_t shift, int64_t xb, int64_t xe, double *x,
+                   double *w, int32_t *id, int64_t cap) {
+    int64_t m = 0;
+    int64_t ppc = (int64_t)P->ppc[0] * P->ppc[1] * P->ppc[2];
+    for (int64_t i = xb; i < xe; ++i)
+        for (int64_t j = 0; j < g->n[1]; ++j)
+            for (int64_t k = 0; k < g->n[2]; ++k)
+                for (int64_t s = 0; s < ppc; ++s) {
+                    int64_t sx = s % P->ppc[0], sy = (s / P->ppc[0]) % P->ppc[1], sz = s / (P->ppc[0] * P->ppc[1]);
+                    double ox = (sx + 0.5) / P->ppc[0], oy = (sy + 0.5) / P->ppc[1], oz = (sz + 0.5) / P->ppc[2];
+                    double n = ora_density(P, (double)(shift + i) + ox);
+                    if (!(n > 0.0)) continue;
+                    if (m >= cap) return m;
+                    x[m] = (i + ox) * g->d[0];
+                    x[cap + m] = (j + oy) * g->d[1];
+                    x[2 * cap + m] = (k + oz) * g->d[2];
+                    w[m] = n / (double)ppc;
+                    id[m] = (int32_t)((((shift + i) * g->n[1] + j) * g->n[2] + k) * ppc + s) & 0x7fffffff;
+                    ++m;
+                }
+    return m;
+}

@@ -209,6 +209,129 @@ def diag(g: OraGrid, u, w, E, B, J=None, q=-1.0, m=1.0):
     return {"charge": out[0], "e_field": out[1], "e_kin": out[2], "max_abs_J": out[3]}
 
 
+class OraLaser(ctypes.Structure):
+    _fields_ = [("a0", ctypes.c_double), ("omega0", ctypes.c_double), ("waist", ctypes.c_double),
+                ("fwhm", ctypes.c_double), ("t_peak", ctypes.c_double), ("t_end", ctypes.c_double),
+                ("yc", ctypes.c_double), ("zc", ctypes.c_double), ("src_x", ctypes.c_int64)]
+
+
+class OraPlasma(ctypes.Structure):
+    _fields_ = [("x_start", ctypes.c_double), ("ramp", ctypes.c_double), ("n_plateau", ctypes.c_double),
+                ("ppc", ctypes.c_int32 * 3)]
+
+
+def _lwfa_sigs():
+    L = lib()
+    G, LP, PP = ctypes.POINTER(OraGrid), ctypes.POINTER(OraLaser), ctypes.POINTER(OraPlasma)
+    i64, dbl = ctypes.c_int64, ctypes.c_double
+    sig = {
+        "ora_laser_e": (dbl, [LP, dbl]),
+        "ora_laser_profile": (dbl, [LP, dbl, dbl]),
+        "ora_field_step_laser": (None, [G, _dp, _dp, _dp, LP, dbl]),
+        "ora_window_shift": (None, [G, _dp, _dp]),
+        "ora_density": (dbl, [PP, dbl]),
+        "ora_inject": (i64, [G, PP, i64, i64, i64, _dp, _dp, ctypes.POINTER(ctypes.c_int32), i64]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    return L
+
+
+def make_laser(a0, omega0, waist, fwhm, t_peak, t_end, yc, zc, src_x) -> OraLaser:
+    return OraLaser(float(a0), float(omega0), float(waist), float(fwhm), float(t_peak), float(t_end), float(yc),
+                    float(zc), int(src_x))
+
+
+def make_plasma(x_start, ramp, n_plateau, ppc=(2, 2, 2)) -> OraPlasma:
+    p = OraPlasma(float(x_start), float(ramp), float(n_plateau))
+    for a in range(3):
+        p.ppc[a] = int(ppc[a])
+    return p
+
+
+def laser_e(L: OraLaser, t: float) -> float:
+    return _lwfa_sigs().ora_laser_e(ctypes.byref(L), float(t))
+
+
+def laser_profile(L: OraLaser, y: float, z: float) -> float:
+    return _lwfa_sigs().ora_laser_profile(ctypes.byref(L), float(y), float(z))
+
+
+def density(P: OraPlasma, x_cells: float) -> float:
+    return _lwfa_sigs().ora_density(ctypes.byref(P), float(x_cells))
+
+
+def field_step_laser(g: OraGrid, E, B, J, L: OraLaser, t: float):
+    E, B = f64(E).copy(), f64(B).copy()
+    Jp = _p(f64(J)) if J is not None else None
+    Lp = ctypes.byref(L) if L is not None else None
+    _lwfa_sigs().ora_field_step_laser(ctypes.byref(g), _p(E), _p(B), Jp, Lp, float(t))
+    return E, B
+
+
+def window_shift(g: OraGrid, E, B):
+    E, B = f64(E).copy(), f64(B).copy()
+    _lwfa_sigs().ora_window_shift(ctypes.byref(g), _p(E), _p(B))
+    return E, B
+
+
+def inject(g: OraGrid, P: OraPlasma, shift: int, xb: int, xe: int):
+    """Cold lattice plasma of window cells [xb, xe): (x[3, m] window positions, w[m], id[m])."""
+    ppc = P.ppc[0] * P.ppc[1] * P.ppc[2]
+    cap = max(1, (xe - xb) * int(g.n[1]) * int(g.n[2]) * ppc)
+    x = np.zeros((3, cap))
+    w = np.zeros(cap)
+    ids = np.zeros(cap, dtype=np.int32)
+    m = _lwfa_sigs().ora_inject(ctypes.byref(g), ctypes.byref(P), int(shift), int(xb), int(xe), _p(x), _p(w),
+                                ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), cap)
+    return x[:, :m].copy(), w[:m].copy(), ids[:m].copy()
+
+
+def run_lwfa(g: OraGrid, P: OraPlasma, L: OraLaser, nsteps: int, window_start: int, kill_lo: int = 3,
+             inject_hi: int = 3, jpost: int = 0, q=-1.0, m=1.0):
+    """Moving-window laser-wakefield run in window coordinates (c = 1, c dt = dx).
+
+    Start: vacuum fields, plasma loaded over window cells [0, nx - inject_hi).
+    Each step: push, deposit, optional binomial filter, field step with the
+    laser source while the window has not moved; then, from step
+    `window_start` on, the window moves one cell (fields shift, the leading
+    plane is cleared and the plasma of the newly covered lab cell is loaded
+    at window cell nx - 1 - inject_hi).  After every step particles outside
+    window cells [kill_lo, nx - 1 - inject_hi] are removed (their shapes
+    would reach past the window's ends).  Returns dict(x, u, w, id, E, B, J, shift).
+    """
+    nx = int(g.n[0])
+    x, w, ids = inject(g, P, 0, 0, nx - inject_hi)
+    u = np.zeros_like(x)
+    E = zeros_field(g)
+    B = zeros_field(g)
+    shift = 0
+    J = zeros_field(g)
+    for n in range(nsteps):
+        t = n * g.dt
+        x0 = x.copy()
+        xw, u, x1 = push(g, x, u, E, B, q, m)
+        J = deposit(g, x0, x1, w, q)
+        if jpost == 1:
+            J = binomial(g, J)
+        E, B = field_step_laser(g, E, B, J, L if (shift == 0 and t <= L.t_end) else None, t)
+        x = xw
+        if n + 1 >= window_start:
+            E, B = window_shift(g, E, B)
+            shift += 1
+            x[0] -= g.d[0]
+            xn, wn, idn = inject(g, P, shift, nx - 1 - inject_hi, nx - inject_hi)
+            x = np.concatenate([x, xn], axis=1)
+            u = np.concatenate([u, np.zeros_like(xn)], axis=1)
+            w = np.concatenate([w, wn])
+            ids = np.concatenate([ids, idn])
+        keep = (x[0] >= kill_lo * g.d[0]) & (x[0] < (nx - inject_hi) * g.d[0])
+        x, u, w, ids = x[:, keep], u[:, keep], w[keep], ids[keep]
+    return {"x": x, "u": u, "w": w, "id": ids, "E": E, "B": B, "J": J, "shift": shift}
+
+
 def step(g: OraGrid, x, u, w, E, B, q=-1.0, m=1.0, jpost: int = 0):
     """One PIC step in place on copies.  Returns dict(x, u, E, B, J, x_prev)."""
     x, u, E, B, w = f64(x).copy(), f64(u).copy(), f64(E).copy(), f64(B).copy(), f64(w)

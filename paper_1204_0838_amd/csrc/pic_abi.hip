@@ -19,21 +19,46 @@ namespace {
 constexpr int kMaxSpecies = 8;
 constexpr size_t kAlign = 256;
 constexpr int kKillMargin = 3;   // window cells behind which particles are removed
+constexpr size_t kMaxLds = 160 * 1024;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Resolved tiling parameters of a descriptor (defaults applied).
+struct Tiling {
+    TileGeom t;
+    int guard, threads, interleave, sort_interval;
+};
+
+Tiling tiling_of(const pic_grid_desc* d) {
+    Tiling r;
+    for (int a = 0; a < 3; ++a) {
+        int T = d->tile[a] > 0 ? d->tile[a] : 8;
+        if (T > d->n[a]) T = d->n[a];
+        r.t.T[a] = T;
+        r.t.nt[a] = (d->n[a] + T - 1) / T;
+    }
+    r.t.ntiles = r.t.nt[0] * r.t.nt[1] * r.t.nt[2];
+    r.t.tcells = r.t.T[0] * r.t.T[1] * r.t.T[2];
+    r.guard = d->guard < 0 ? 1 : d->guard;
+    r.threads = d->threads > 0 ? d->threads : 512;
+    r.interleave = d->interleave > 0 ? d->interleave : 17;
+    r.sort_interval = d->sort_interval > 0 ? d->sort_interval : 2;
+    return r;
+}
 
 // Device workspace carve-up.  Per-particle arrays have max_particles entries;
 // species take consecutive sub-ranges of them.
 struct Layout {
     size_t acc, jtmp, rho, small, prev_cell, prev_off, alt_cell, alt_off, alt_u, alt_w, alt_id, sort_rank, hist,
-        blocks, total;
+        sums, stride, total;
 };
 
 // small block: err flags, per-species counts, reduction results
 struct Small {
     int err;
     int pad0;
-    int count[kMaxSpecies];
+    int count[kMaxSpecies];    // live + removed-but-not-yet-dropped particles
+    int sorted[kMaxSpecies];   // particles covered by the tile ranges of the last sort
     double red[4];
     unsigned long long live;
     unsigned long long contmax;
@@ -41,7 +66,10 @@ struct Small {
     int pad1;
 };
 
-Layout layout(int64_t ncell, int64_t maxp) {
+Layout layout(const pic_grid_desc* d, int64_t maxp) {
+    const int64_t ncell = (int64_t)d->n[0] * d->n[1] * d->n[2];
+    const Tiling tl = tiling_of(d);
+    const int64_t nkeys = (int64_t)tl.t.ntiles * tl.t.tcells;
     Layout L;
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -61,8 +89,9 @@ Layout layout(int64_t ncell, int64_t maxp) {
     L.alt_w = take((size_t)maxp * 4);
     L.alt_id = take((size_t)maxp * 4);
     L.sort_rank = take((size_t)maxp * 4);
-    L.hist = take(((size_t)ncell + 1) * 4);
-    L.blocks = take((((size_t)ncell + 1023) / 1024 + 1) * 4 + 4096);
+    L.hist = take(((size_t)nkeys + 1) * 4);
+    L.sums = take((((size_t)nkeys + 1 + 1023) / 1024 + 1) * 4);
+    L.stride = take((size_t)tl.t.ntiles * 4);
     L.total = o;
     return L;
 }
@@ -72,8 +101,11 @@ struct Species {
     pic_species_bufs cur;    // arrays holding the current data (user's or the workspace copy)
     pic_species_bufs alt;    // the other set
     int64_t base;            // offset into per-particle workspace arrays
-    int64_t bound;           // host upper bound of the live count
-    bool prev_valid;
+    int64_t bound;           // host upper bound of the particle count
+    int64_t loose;           // host upper bound of particles appended since the last sort
+    int64_t sort_step;       // step of the last sort
+    bool sorted;             // tile ranges valid
+    bool prev_valid;         // x^n of the last split gather_push kept
 };
 
 }  // namespace
@@ -87,11 +119,19 @@ struct pic_ctx {
     int64_t maxp;
     int64_t pused;
     Layout L;
+    Tiling tl;
     Geom g;
     PDCoef pd;
     std::vector<Species> sp;
     int64_t step;
     std::string err;
+    // laser source and moving window
+    bool has_laser = false;
+    pic_laser_desc laser;
+    int64_t window_start = INT64_MAX;
+    int64_t shift = 0;
+    bool has_plasma[kMaxSpecies] = {};
+    PlasmaDev plasma[kMaxSpecies];
 };
 
 namespace {
@@ -110,6 +150,12 @@ pic_status fail(pic_ctx* c, pic_status st, const char* fmt, ...) {
     do {                                                                                            \
         hipError_t e_ = (expr);                                                                     \
         if (e_ != hipSuccess) return fail(ctx, PIC_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+#define PICCHK(expr)                      \
+    do {                                  \
+        pic_status s_ = (expr);           \
+        if (s_ != PIC_OK) return s_;      \
     } while (0)
 
 pic_status validate(const pic_grid_desc* d, char* msg, size_t len) {
@@ -131,6 +177,13 @@ pic_status validate(const pic_grid_desc* d, char* msg, size_t len) {
     for (int a = 0; a < 3; ++a)
         if (d->tile[a] < 0 || (d->tile[a] > 0 && d->tile[a] > d->n[a])) return bad("tile larger than the grid");
     if (d->sort_interval < 0) return bad("negative sort interval");
+    if (d->guard > 3) return bad("tile guard above 3 cells");
+    if (d->threads != 0 && d->threads != 256 && d->threads != 512 && d->threads != 1024)
+        return bad("threads per tile must be 256, 512 or 1024");
+    if (d->interleave < 0) return bad("negative interleave");
+    const Tiling tl = tiling_of(d);
+    if ((int64_t)tl.t.ntiles * tl.t.tcells >= (1ll << 31)) return bad("tile key space exceeds 2^31");
+    if (tile_lds_bytes(tl.t, tl.guard) > kMaxLds) return bad("tile and guard exceed the 160 KiB of LDS");
     if (d->solver == PIC_SOLVER_YEE) {
         double s = 0.0;
         for (int a = 0; a < 3; ++a) s += 1.0 / (d->d[a] * d->d[a]);
@@ -174,19 +227,21 @@ void pd_coefficients(const pic_grid_desc* d, PDCoef* c) {
 
 Small* small_of(pic_ctx* c) { return reinterpret_cast<Small*>(c->ws + c->L.small); }
 
-SpeciesDev dev_of(const pic_ctx* c, const Species& s) {
+SpeciesDev dev_from(const pic_ctx* c, const Species& s, const pic_species_bufs& b) {
     SpeciesDev d;
-    d.cell = s.cur.cell;
+    d.cell = b.cell;
     for (int a = 0; a < 3; ++a) {
-        d.off[a] = s.cur.off[a];
-        d.u[a] = s.cur.u[a];
+        d.off[a] = b.off[a];
+        d.u[a] = b.u[a];
     }
-    d.w = s.cur.w;
-    d.id = s.cur.id;
+    d.w = b.w;
+    d.id = b.id;
     d.qmh = (float)(s.user.q * c->desc.dt / (2.0 * s.user.m));
     d.mq = (float)(-s.user.q);
     return d;
 }
+
+SpeciesDev dev_of(const pic_ctx* c, const Species& s) { return dev_from(c, s, s.cur); }
 
 PrevDev prev_of(pic_ctx* c, const Species& s) {
     PrevDev p;
@@ -206,6 +261,7 @@ FieldPtrs fields_of(pic_ctx* c) {
 }
 
 unsigned long long* acc_of(pic_ctx* c) { return reinterpret_cast<unsigned long long*>(c->ws + c->L.acc); }
+int* hist_of(pic_ctx* c) { return reinterpret_cast<int*>(c->ws + c->L.hist); }
 
 void jtmp_of(pic_ctx* c, float* out[3]) {
     for (int a = 0; a < 3; ++a) out[a] = reinterpret_cast<float*>(c->ws + c->L.jtmp) + (size_t)a * c->g.ncell;
@@ -230,18 +286,125 @@ pic_status device_errors(pic_ctx* c) {
         HIPCHK(c, hipMemsetAsync(&small_of(c)->err, 0, sizeof(int), c->stream));
         if (flags & ERR_NONFINITE) return fail(c, PIC_ENONFINITE, "non-finite momentum on the device");
         if (flags & ERR_CFL) return fail(c, PIC_ECFL, "a particle moved one cell or more in a step");
-        if (flags & ERR_OVERFLOW) return fail(c, PIC_EOVERFLOW, "tile or capacity overflow on the device");
+        if (flags & ERR_OVERFLOW) return fail(c, PIC_EOVERFLOW, "invalid cell index or capacity overflow on the device");
     }
     return PIC_OK;
 }
 
+// Incident laser field on the source plane: e(t) = -d/dt [a0 env(t) cos(w0 (t - t_peak))],
+// env = exp(-2 ln2 (t - t_peak)^2 / fwhm^2).
+double laser_e(const pic_laser_desc& L, double t) {
+    const double tau = t - L.t_peak;
+    const double k = 2.0 * log(2.0) / (L.fwhm * L.fwhm);
+    const double env = exp(-k * tau * tau);
+    const double denv = -2.0 * k * tau * env;
+    const double ph = L.omega0 * tau;
+    return L.a0 * (env * L.omega0 * sin(ph) - denv * cos(ph));
+}
+
+// Total-field/scattered-field correction of one field plane: B_z behind the
+// source gets + h e(t) f / dx, E_y on the source gets + dt e(t + dx/2) f / dx.
+pic_status laser_plane(pic_ctx* c, bool e_plane, double h, double t) {
+    const pic_laser_desc& L = c->laser;
+    const double amp = e_plane ? laser_e(L, t + 0.5 * c->desc.d[0]) : laser_e(L, t);
+    const int ix = e_plane ? L.src_x : L.src_x - 1;
+    float* F = e_plane ? c->f.E[1] : c->f.B[2];
+    HIPCHK(c, launch_laser_plane(c->g, F, ix, h * amp / c->desc.d[0], L.yc, L.zc, L.waist, c->desc.d[1],
+                                 c->desc.d[2], c->stream));
+    return PIC_OK;
+}
+
+// Field update of the step that starts at t = step dt: B half step, E step,
+// B half step (Section 2, eq. 2.1), with the laser source while it is active.
 pic_status field_update(pic_ctx* c, float* const Juse[3]) {
     FieldPtrs f = fields_of(c);
     const int pd = c->desc.solver == PIC_SOLVER_PD;
-    HIPCHK(c, launch_bhalf(c->g, pd, c->pd, f.E, f.B, (float)(0.5 * c->desc.dt), c->stream));
+    const double dt = c->desc.dt, t = c->step * dt;
+    const bool laser = c->has_laser && c->shift == 0 && t <= c->laser.t_end;
+    HIPCHK(c, launch_bhalf(c->g, pd, c->pd, f.E, f.B, (float)(0.5 * dt), c->stream));
+    if (laser) PICCHK(laser_plane(c, false, 0.5 * dt, t));
     HIPCHK(c, launch_efull(c->g, f.E, f.B, Juse, c->stream));
-    HIPCHK(c, launch_bhalf(c->g, pd, c->pd, f.E, f.B, (float)(0.5 * c->desc.dt), c->stream));
+    if (laser) PICCHK(laser_plane(c, true, dt, t + 0.5 * dt));
+    HIPCHK(c, launch_bhalf(c->g, pd, c->pd, f.E, f.B, (float)(0.5 * dt), c->stream));
+    if (laser) PICCHK(laser_plane(c, false, 0.5 * dt, t + dt));
     return PIC_OK;
+}
+
+// Exact particle count of a species (synchronises); refreshes the host bounds.
+pic_status refresh_bound(pic_ctx* c, int32_t s) {
+    int v[2] = {0, 0};
+    HIPCHK(c, hipMemcpyAsync(&v[0], &small_of(c)->count[s], sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(&v[1], &small_of(c)->sorted[s], sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    Species& sp = c->sp[s];
+    sp.bound = v[0];
+    if (sp.sorted) sp.loose = v[0] - v[1] > 0 ? v[0] - v[1] : 0;
+    return PIC_OK;
+}
+
+pic_status inject_slab(pic_ctx* c, int32_t s, int32_t xb, int32_t xe) {
+    Species& sp = c->sp[s];
+    const PlasmaDev& P = c->plasma[s];
+    const int64_t most = (int64_t)(xe - xb) * c->g.n[1] * c->g.n[2] * P.ppc[0] * P.ppc[1] * P.ppc[2];
+    if (most <= 0) return PIC_OK;
+    if (sp.bound + most > sp.user.capacity) {
+        PICCHK(refresh_bound(c, s));
+        if (sp.bound + most > sp.user.capacity)
+            return fail(c, PIC_ENOMEM, "species %d: %lld particles plus up to %lld injected exceed capacity %lld", s,
+                        (long long)sp.bound, (long long)most, (long long)sp.user.capacity);
+    }
+    HIPCHK(c, launch_inject(c->g, P, dev_of(c, sp), (long long)c->shift, xb, xe, &small_of(c)->count[s],
+                            (int)sp.user.capacity, &small_of(c)->err, c->stream));
+    sp.bound += most;
+    sp.loose += most;
+    return PIC_OK;
+}
+
+// End of a step: count it; move the window one cell when it is due.
+pic_status end_step(pic_ctx* c) {
+    c->step += 1;
+    if (!c->g.window || c->step < c->window_start) return PIC_OK;
+    HIPCHK(c, launch_clear_plane(c->g, fields_of(c), c->g.origin, c->stream));
+    c->g.origin = c->g.origin + 1 == c->g.n[0] ? 0 : c->g.origin + 1;
+    c->shift += 1;
+    const int slab = c->g.n[0] - 1 - c->g.kill_hi;
+    for (int32_t s = 0; s < (int32_t)c->sp.size(); ++s)
+        if (c->has_plasma[s]) PICCHK(inject_slab(c, s, slab, slab + 1));
+    return PIC_OK;
+}
+
+pic_status sort_species(pic_ctx* c, int32_t s) {
+    Species& sp = c->sp[s];
+    Small* sm = small_of(c);
+    int* rank = reinterpret_cast<int*>(c->ws + c->L.sort_rank) + sp.base;
+    HIPCHK(c, launch_sort(c->g, c->tl.t, dev_from(c, sp, sp.cur), dev_from(c, sp, sp.alt), &sm->count[s],
+                          &sm->sorted[s], (int)sp.bound, hist_of(c), rank, reinterpret_cast<int*>(c->ws + c->L.sums),
+                          reinterpret_cast<int*>(c->ws + c->L.stride), c->tl.interleave, c->stream));
+    std::swap(sp.cur, sp.alt);
+    sp.sorted = true;
+    sp.sort_step = c->step;
+    sp.loose = 0;
+    sp.prev_valid = false;
+    return PIC_OK;
+}
+
+// Current post-processing and field update of one production step.
+pic_status finish_step(pic_ctx* c) {
+    double sc[3];
+    jscale(c, sc);
+    float* Juse[3] = {c->f.J[0], c->f.J[1], c->f.J[2]};
+    if (c->desc.jpost == PIC_JPOST_BINOMIAL) {
+        float* tmp[3];
+        jtmp_of(c, tmp);
+        HIPCHK(c, launch_jfinal(c->g, acc_of(c), tmp, sc, 1, c->stream));
+        HIPCHK(c, launch_binomial(c->g, tmp, c->f.J, c->stream));
+    } else if (c->desc.jpost == PIC_JPOST_NONE) {
+        HIPCHK(c, launch_jfinal(c->g, acc_of(c), c->f.J, sc, 1, c->stream));
+    } else {
+        return fail(c, PIC_EINVAL, "denoiser weights not set");
+    }
+    PICCHK(field_update(c, Juse));
+    return end_step(c);
 }
 
 }  // namespace
@@ -250,8 +413,7 @@ extern "C" {
 
 size_t pic_workspace_bytes(const pic_grid_desc* desc, int64_t max_particles) {
     if (validate(desc, nullptr, 0) != PIC_OK || max_particles < 0) return 0;
-    const int64_t ncell = (int64_t)desc->n[0] * desc->n[1] * desc->n[2];
-    return layout(ncell, max_particles > 0 ? max_particles : 1).total;
+    return layout(desc, max_particles > 0 ? max_particles : 1).total;
 }
 
 pic_status pic_validate_grid(const pic_grid_desc* desc, char* msg, size_t msg_len) {
@@ -271,7 +433,7 @@ pic_status pic_init_grid(pic_ctx** out, const pic_grid_desc* desc, const pic_fie
     if ((reinterpret_cast<uintptr_t>(workspace) & (kAlign - 1)) != 0) return PIC_EINVAL;
     const int64_t ncell = (int64_t)desc->n[0] * desc->n[1] * desc->n[2];
     const int64_t maxp = max_particles > 0 ? max_particles : 1;
-    Layout L = layout(ncell, maxp);
+    Layout L = layout(desc, maxp);
     if (workspace_bytes < L.total) return PIC_ENOMEM;
     pic_ctx* c = new (std::nothrow) pic_ctx();
     if (!c) return PIC_ENOMEM;
@@ -283,6 +445,7 @@ pic_status pic_init_grid(pic_ctx** out, const pic_grid_desc* desc, const pic_fie
     c->maxp = maxp;
     c->pused = 0;
     c->L = L;
+    c->tl = tiling_of(desc);
     c->step = 0;
     Geom& g = c->g;
     for (int a = 0; a < 3; ++a) {
@@ -295,6 +458,7 @@ pic_status pic_init_grid(pic_ctx** out, const pic_grid_desc* desc, const pic_fie
     g.window = desc->bc_x == PIC_BC_MOVING_WINDOW;
     g.origin = 0;
     g.kill_lo = kKillMargin;
+    g.kill_hi = kKillMargin;
     g.dt = (float)desc->dt;
     pd_coefficients(desc, &c->pd);
     hipError_t e = hipMemsetAsync(c->ws + L.acc, 0, 3 * (size_t)ncell * 8, c->stream);
@@ -324,6 +488,9 @@ pic_status pic_init_species(pic_ctx* c, const pic_species_bufs* bufs, int64_t n,
     s.cur = *bufs;
     s.base = c->pused;
     s.bound = n;
+    s.loose = 0;
+    s.sort_step = 0;
+    s.sorted = false;
     s.prev_valid = false;
     const size_t stride = align_up((size_t)c->maxp * 4);
     s.alt = *bufs;
@@ -335,8 +502,9 @@ pic_status pic_init_species(pic_ctx* c, const pic_species_bufs* bufs, int64_t n,
     s.alt.w = reinterpret_cast<float*>(c->ws + c->L.alt_w) + s.base;
     s.alt.id = reinterpret_cast<int32_t*>(c->ws + c->L.alt_id) + s.base;
     const int idx = (int)c->sp.size();
-    int cnt = (int)n;
-    HIPCHK(c, hipMemcpyAsync(&small_of(c)->count[idx], &cnt, sizeof(int), hipMemcpyHostToDevice, c->stream));
+    int cnt[2] = {(int)n, 0};
+    HIPCHK(c, hipMemcpyAsync(&small_of(c)->count[idx], &cnt[0], sizeof(int), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(&small_of(c)->sorted[idx], &cnt[1], sizeof(int), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->pused += bufs->capacity;
     c->sp.push_back(s);
@@ -345,8 +513,7 @@ pic_status pic_init_species(pic_ctx* c, const pic_species_bufs* bufs, int64_t n,
 }
 
 pic_status pic_gather_push(pic_ctx* c, int32_t s) {
-    pic_status st = check_species(c, s);
-    if (st != PIC_OK) return st;
+    PICCHK(check_species(c, s));
     Species& sp = c->sp[s];
     HIPCHK(c, launch_gather_push(c->g, fields_of(c), dev_of(c, sp), prev_of(c, sp), &small_of(c)->count[s],
                                  (int)sp.bound, &small_of(c)->err, c->stream));
@@ -355,8 +522,7 @@ pic_status pic_gather_push(pic_ctx* c, int32_t s) {
 }
 
 pic_status pic_deposit(pic_ctx* c, int32_t s) {
-    pic_status st = check_species(c, s);
-    if (st != PIC_OK) return st;
+    PICCHK(check_species(c, s));
     Species& sp = c->sp[s];
     if (!sp.prev_valid) return fail(c, PIC_ESTATE, "deposit needs a preceding gather_push");
     HIPCHK(c, launch_deposit(c->g, dev_of(c, sp), prev_of(c, sp), &small_of(c)->count[s], (int)sp.bound, acc_of(c),
@@ -379,64 +545,46 @@ pic_status pic_field_step(pic_ctx* c) {
     } else if (c->desc.jpost == PIC_JPOST_DENOISER) {
         return fail(c, PIC_EINVAL, "denoiser weights not set");
     }
-    pic_status st = field_update(c, Juse);
-    if (st != PIC_OK) return st;
+    PICCHK(field_update(c, Juse));
     HIPCHK(c, launch_zero_u64(acc_of(c), 3 * (int64_t)c->g.ncell, c->stream));
-    c->step += 1;
-    return PIC_OK;
+    return end_step(c);
 }
 
 pic_status pic_step(pic_ctx* c, int32_t nsteps) {
     if (!c || nsteps < 0) return PIC_EINVAL;
-    double sc[3];
-    jscale(c, sc);
     for (int32_t it = 0; it < nsteps; ++it) {
         for (int32_t s = 0; s < (int32_t)c->sp.size(); ++s) {
             Species& sp = c->sp[s];
-            HIPCHK(c, launch_gather_push(c->g, fields_of(c), dev_of(c, sp), prev_of(c, sp), &small_of(c)->count[s],
-                                         (int)sp.bound, &small_of(c)->err, c->stream));
-            HIPCHK(c, launch_deposit(c->g, dev_of(c, sp), prev_of(c, sp), &small_of(c)->count[s], (int)sp.bound,
-                                     acc_of(c), c->stream));
-            sp.prev_valid = true;
+            if (!sp.sorted || c->step - sp.sort_step >= c->tl.sort_interval) PICCHK(sort_species(c, s));
+            Small* sm = small_of(c);
+            HIPCHK(c, launch_pic_tile(c->g, c->tl.t, c->tl.guard, c->tl.threads, fields_of(c), dev_of(c, sp),
+                                      hist_of(c), acc_of(c), &sm->err, c->stream));
+            HIPCHK(c, launch_push_deposit_range(c->g, fields_of(c), dev_of(c, sp), &sm->sorted[s], &sm->count[s],
+                                                (int)sp.loose, acc_of(c), &sm->err, c->stream));
+            sp.prev_valid = false;
         }
-        float* Juse[3] = {c->f.J[0], c->f.J[1], c->f.J[2]};
-        if (c->desc.jpost == PIC_JPOST_BINOMIAL) {
-            float* tmp[3];
-            jtmp_of(c, tmp);
-            HIPCHK(c, launch_jfinal(c->g, acc_of(c), tmp, sc, 1, c->stream));
-            HIPCHK(c, launch_binomial(c->g, tmp, c->f.J, c->stream));
-        } else if (c->desc.jpost == PIC_JPOST_NONE) {
-            HIPCHK(c, launch_jfinal(c->g, acc_of(c), c->f.J, sc, 1, c->stream));
-        } else {
-            return fail(c, PIC_EINVAL, "denoiser weights not set");
-        }
-        pic_status st = field_update(c, Juse);
-        if (st != PIC_OK) return st;
-        c->step += 1;
+        PICCHK(finish_step(c));
     }
     return PIC_OK;
 }
 
 pic_status pic_sort(pic_ctx* c, int32_t s) {
-    pic_status st = check_species(c, s);
-    if (st != PIC_OK) return st;
-    return fail(c, PIC_EINVAL, "sort not available");
+    PICCHK(check_species(c, s));
+    return sort_species(c, s);
 }
 
 pic_status pic_species_view(pic_ctx* c, int32_t s, pic_species_bufs* out, int64_t* n_live) {
-    pic_status st = check_species(c, s);
-    if (st != PIC_OK) return st;
+    PICCHK(check_species(c, s));
     int cnt = 0;
     HIPCHK(c, hipMemcpyAsync(&cnt, &small_of(c)->count[s], sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    st = device_errors(c);
+    pic_status st = device_errors(c);
     if (out) *out = c->sp[s].cur;
     if (n_live) *n_live = cnt;
     return st;
 }
 
 pic_status pic_continuity(pic_ctx* c, int32_t s, double* resid, double* max_abs_j) {
-    pic_status st = check_species(c, s);
-    if (st != PIC_OK) return st;
+    PICCHK(check_species(c, s));
     Species& sp = c->sp[s];
     if (!sp.prev_valid) return fail(c, PIC_ESTATE, "continuity needs a preceding gather_push and deposit");
     double* rho = reinterpret_cast<double*>(c->ws + c->L.rho);
@@ -503,6 +651,68 @@ pic_status pic_sync(pic_ctx* c) {
     if (!c) return PIC_EINVAL;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return device_errors(c);
+}
+
+pic_status pic_set_laser(pic_ctx* c, const pic_laser_desc* L) {
+    if (!c) return PIC_EINVAL;
+    if (!L) {
+        c->has_laser = false;
+        return PIC_OK;
+    }
+    if (L->src_x < 1 || L->src_x >= c->g.n[0] - 1) return fail(c, PIC_EINVAL, "laser source plane outside [1, nx-1)");
+    if (!(L->fwhm > 0.0) || !(L->waist > 0.0) || !isfinite(L->a0) || !isfinite(L->omega0) || !isfinite(L->t_peak) ||
+        !isfinite(L->t_end))
+        return fail(c, PIC_EINVAL, "invalid laser parameters");
+    if (c->g.window && c->window_start != INT64_MAX && L->t_end > c->window_start * c->desc.dt)
+        return fail(c, PIC_EINVAL, "the window would move while the laser source is active");
+    c->laser = *L;
+    c->has_laser = true;
+    return PIC_OK;
+}
+
+pic_status pic_set_plasma(pic_ctx* c, int32_t s, const pic_plasma_desc* P) {
+    PICCHK(check_species(c, s));
+    if (!P) {
+        c->has_plasma[s] = false;
+        return PIC_OK;
+    }
+    for (int a = 0; a < 3; ++a)
+        if (P->ppc[a] < 1 || P->ppc[a] > 16) return fail(c, PIC_EINVAL, "lattice particles per cell outside 1..16");
+    if (!(P->ramp >= 0.0) || !isfinite(P->x_start) || !(P->n_plateau >= 0.0) || !isfinite(P->n_plateau))
+        return fail(c, PIC_EINVAL, "invalid plasma profile");
+    PlasmaDev& d = c->plasma[s];
+    d.x_start = P->x_start;
+    d.ramp = P->ramp;
+    d.n_plateau = P->n_plateau;
+    for (int a = 0; a < 3; ++a) d.ppc[a] = P->ppc[a];
+    c->has_plasma[s] = true;
+    return PIC_OK;
+}
+
+pic_status pic_inject_plasma(pic_ctx* c, int32_t s, int32_t xb, int32_t xe) {
+    PICCHK(check_species(c, s));
+    if (!c->has_plasma[s]) return fail(c, PIC_ESTATE, "species %d has no plasma profile", s);
+    if (xb < 0 || xe > c->g.n[0] || xb > xe) return fail(c, PIC_EINVAL, "slab outside the grid");
+    return inject_slab(c, s, xb, xe);
+}
+
+pic_status pic_set_window(pic_ctx* c, int64_t start_step) {
+    if (!c) return PIC_EINVAL;
+    if (!c->g.window) return fail(c, PIC_ESTATE, "the grid has no moving window (bc_x)");
+    if (fabs(c->desc.dt - c->desc.d[0]) > 1e-12 * c->desc.d[0])
+        return fail(c, PIC_EINVAL, "a window moving one cell per step at c needs c dt = dx");
+    if (start_step < 0) return fail(c, PIC_EINVAL, "negative start step");
+    if (c->has_laser && c->laser.t_end > start_step * c->desc.dt)
+        return fail(c, PIC_EINVAL, "the window would move while the laser source is active");
+    c->window_start = start_step;
+    return PIC_OK;
+}
+
+pic_status pic_window_state(pic_ctx* c, int64_t* shift, int32_t* origin) {
+    if (!c) return PIC_EINVAL;
+    if (shift) *shift = c->shift;
+    if (origin) *origin = c->g.origin;
+    return PIC_OK;
 }
 
 const char* pic_last_error(const pic_ctx* c) {

@@ -25,9 +25,19 @@ struct Geom {
     int window;    // 1: x is a moving-window circular buffer
     int origin;    // storage x index of window cell 0
     int kill_lo;   // window mode: particles in window cells < kill_lo are removed
+    int kill_hi;   // window mode: particles in window cells > n[0] - 1 - kill_hi are removed
     float dt;
     float dtd[3];  // dt / d  (converts velocity to cells per step)
     float inv_d[3];
+};
+
+// Particle tiles: T cells per tile along each axis, nt tiles per axis (the
+// last tile of an axis may be ragged), tcells = T[0]*T[1]*T[2] key slots per tile.
+struct TileGeom {
+    int T[3];
+    int nt[3];
+    int ntiles;
+    int tcells;
 };
 
 // Stencil coefficients of the transverse smoothing S_d (perfect dispersion).
@@ -54,6 +64,18 @@ struct PrevDev {
 
 // device error flags (bit set)
 enum { ERR_CFL = 1, ERR_NONFINITE = 2, ERR_OVERFLOW = 4 };
+
+// round(x * 2^20) as int64, round-half-even, for |x| < 2^31 (x is a current
+// contribution already scaled by 2^20, so the result is round(v * 2^40)).
+// Split exactly: h = rint(x) (|x - h| <= 1/2, so x - h is exact), x 2^20 =
+// h 2^20 + (x - h) 2^20 with only the last term rounded.  About ten VALU
+// instructions instead of a general float -> int64 conversion.
+__device__ __forceinline__ long long to_fix20(float x) {
+    const float h = rintf(x);
+    const int hi = (int)h;
+    const int lo = (int)rintf((x - h) * 0x1p20f);
+    return ((long long)hi << 20) + (long long)lo;
+}
 
 __device__ __forceinline__ int wrapi(int i, int n) {
     // i in [-n, 2n)

@@ -14,6 +14,19 @@ struct FieldPtrs {
     float* B[3];
 };
 
+// plasma profile (see pic_plasma_desc)
+struct PlasmaDev {
+    double x_start, ramp, n_plateau;
+    int ppc[3];
+};
+
+// window / injection / laser kernels (pic_window.hip)
+hipError_t launch_clear_plane(const Geom& g, const FieldPtrs& f, int ix, hipStream_t st);
+hipError_t launch_inject(const Geom& g, const PlasmaDev& P, const SpeciesDev& s, long long shift, int xb, int xe,
+                         int* d_count, int capacity, int* d_err, hipStream_t st);
+hipError_t launch_laser_plane(const Geom& g, float* F, int ix, double coef, double yc, double zc, double waist,
+                              double dy, double dz, hipStream_t st);
+
 // particle kernels (pic_particles.hip)
 hipError_t launch_gather_push(const Geom& g, const FieldPtrs& f, const SpeciesDev& s, const PrevDev& prev,
                               const int* d_count, int max_count, int* d_err, hipStream_t st);
@@ -21,6 +34,19 @@ hipError_t launch_deposit(const Geom& g, const SpeciesDev& s, const PrevDev& pre
                           int max_count, unsigned long long* acc, hipStream_t st);
 hipError_t launch_jfinal(const Geom& g, unsigned long long* acc, float* const J[3], const double scale[3],
                          int zero_acc, hipStream_t st);
+
+// sort (pic_sort.hip): src -> dst, new count into d_count and d_sorted
+hipError_t launch_sort(const Geom& g, const TileGeom& t, const SpeciesDev& src, const SpeciesDev& dst,
+                       int* d_count, int* d_sorted, int max_count, int* hist, int* rank, int* sums, int* stride,
+                       int interleave, hipStream_t st);
+
+// fused tile kernel (pic_tile.hip)
+size_t tile_lds_bytes(const TileGeom& t, int guard);
+hipError_t launch_pic_tile(const Geom& g, const TileGeom& t, int guard, int threads, const FieldPtrs& f,
+                           const SpeciesDev& s, const int* off, unsigned long long* acc, int* d_err, hipStream_t st);
+hipError_t launch_push_deposit_range(const Geom& g, const FieldPtrs& f, const SpeciesDev& s, const int* d_begin,
+                                     const int* d_count, int max_n, unsigned long long* acc, int* d_err,
+                                     hipStream_t st);
 
 // field kernels (pic_fields.hip)
 hipError_t launch_bhalf(const Geom& g, int pd, const PDCoef& c, float* const E[3], float* const B[3], float h,

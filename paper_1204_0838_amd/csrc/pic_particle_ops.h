@@ -15,12 +15,13 @@ __device__ __forceinline__ void decompose(const Geom& g, int cell, int c[3]) {
     c[2] = cz;
 }
 
-// Moving window: particles that fall behind the trailing kill margin are removed.
+// Moving window: particles outside window cells [kill_lo, n - 1 - kill_hi] are
+// removed (their cubic shapes would reach across the window's ends).
 __device__ __forceinline__ bool window_killed(const Geom& g, int cx) {
     if (!g.window) return false;
     int xw = cx - g.origin;
     if (xw < 0) xw += g.n[0];
-    return xw < g.kill_lo;
+    return xw < g.kill_lo || xw > g.n[0] - 1 - g.kill_hi;
 }
 
 // Shift between two cell indices along a periodic axis, mapped to (-n/2, n/2].
@@ -69,12 +70,19 @@ __device__ __forceinline__ int push_move(const Geom& g, float qmh, const float E
     return flags;
 }
 
+// True unless the particle kept its cell and offsets (then its current is zero).
+__device__ __forceinline__ bool moved(const int c0[3], const int c1[3], const float o0[3], const float o1[3]) {
+    return (c0[0] != c1[0]) | (c0[1] != c1[1]) | (c0[2] != c1[2]) | (o0[0] != o1[0]) | (o0[1] != o1[1]) |
+           (o0[2] != o1[2]);
+}
+
 // Esirkepov current of one particle: for component x,
 //   J_x[a][b][c] += (-q w) * P_x[a] * (M_y[b] M_z[c] + dS_y[b] dS_z[c] / 12)
 // with P_x the running sum of dS_x along x and M = S0 + dS/2 (this product form
 // equals dS_x (S0y S0z + dSy S0z/2 + S0y dSz/2 + dSy dSz/3) summed along x).
-// Emit::add(comp, jx, jy, jz, value) receives each non-trivial contribution,
-// (jx, jy, jz) being union-node indices 0..4 along x, y, z.
+// Emit::add(comp, jx, jy, jz, value) receives each contribution scaled by
+// 2^20 (exact), (jx, jy, jz) being union-node indices 0..4 along x, y, z.
+// Callers skip particles that did not move (every contribution is zero).
 template <class Emit>
 __device__ __forceinline__ void esirkepov(const Axis5 A[3], float qw, Emit& em) {
     float M[3][5];
@@ -98,7 +106,7 @@ __device__ __forceinline__ void esirkepov(const Axis5 A[3], float qw, Emit& em) 
             for (int b = 0; b < 5; ++b) {
                 if (b >= lb) continue;
                 const float Y = fmaf(A[t1].dS[b] * A[t2].dS[cc], 1.0f / 12.0f, M[t1][b] * M[t2][cc]);
-                const float qy = qw * Y;
+                const float qy = (qw * Y) * 0x1p20f;
 #pragma unroll
                 for (int a = 0; a < 4; ++a) {
                     if (a >= la) continue;

@@ -57,9 +57,7 @@ struct GlobalEmit {
     int ncell;
     int X[5], Y[5], Z[5];
     __device__ __forceinline__ void add(int comp, int jx, int jy, int jz, float v) const {
-        const long long iv = __float2ll_rn(v * PIC_FIX_SCALE);
-        if (iv != 0)
-            atomicAdd(acc + ((size_t)comp * ncell + X[jx] + Y[jy] + Z[jz]), (unsigned long long)iv);
+        atomicAdd(acc + ((size_t)comp * ncell + X[jx] + Y[jy] + Z[jz]), (unsigned long long)to_fix20(v));
     }
 };
 
@@ -73,6 +71,9 @@ __global__ void __launch_bounds__(256) k_deposit(Geom g, SpeciesDev s, PrevDev p
     int c0[3], c1[3];
     decompose(g, cell0, c0);
     decompose(g, cell1, c1);
+    const float o0[3] = {prev.off[0][p], prev.off[1][p], prev.off[2][p]};
+    const float o1[3] = {s.off[0][p], s.off[1][p], s.off[2][p]};
+    if (!moved(c0, c1, o0, o1)) return;
     Axis5 A[3];
     GlobalEmit em;
     em.acc = acc;
@@ -81,7 +82,7 @@ __global__ void __launch_bounds__(256) k_deposit(Geom g, SpeciesDev s, PrevDev p
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const int di = unwrap_shift(c1[d] - c0[d], g.n[d]);
-        axis5(di, prev.off[d][p], s.off[d][p], A[d]);
+        axis5(di, o0[d], o1[d], A[d]);
         int* dst = d == 0 ? em.X : (d == 1 ? em.Y : em.Z);
 #pragma unroll
         for (int j = 0; j < 5; ++j) dst[j] = wrapi(c0[d] + A[d].base + j, g.n[d]) * stride[d];

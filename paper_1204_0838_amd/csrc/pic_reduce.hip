@@ -24,7 +24,7 @@ __device__ __forceinline__ double wave_maxd(double v) {
     return v;
 }
 
-__global__ void __launch_bounds__(256) k_diag_particles(const int* __restrict__ cell, const float* __restrict__ ux,
+__global__ void __launch_bounds__(256) k_diag_particles(Geom g, const int* __restrict__ cell, const float* __restrict__ ux,
                                                         const float* __restrict__ uy, const float* __restrict__ uz,
                                                         const float* __restrict__ w, const int* __restrict__ d_count,
                                                         double qdv, double mdv, double* out,
@@ -33,7 +33,9 @@ __global__ void __launch_bounds__(256) k_diag_particles(const int* __restrict__ 
     double q = 0.0, k = 0.0;
     unsigned long long live = 0;
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
-        if (cell[p] < 0) continue;
+        const int cl = cell[p];
+        if ((unsigned)cl >= (unsigned)g.ncell) continue;
+        if (g.window && window_killed(g, cl % g.n[0])) continue;   // removed at the next step
         const double a = ux[p], b = uy[p], c = uz[p];
         const double u2 = a * a + b * b + c * c;
         q += qdv * (double)w[p];
@@ -140,9 +142,8 @@ static int grid_for(int64_t n) {
 hipError_t launch_diag_particles(const Geom& g, const SpeciesDev& s, double q, double m, double dv,
                                  const int* d_count, int max_count, double* out, unsigned long long* cnt,
                                  hipStream_t st) {
-    (void)g;
     if (max_count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_diag_particles, dim3(grid_for(max_count)), dim3(256), 0, st, s.cell, s.u[0], s.u[1], s.u[2],
+    hipLaunchKernelGGL(k_diag_particles, dim3(grid_for(max_count)), dim3(256), 0, st, g, s.cell, s.u[0], s.u[1], s.u[2],
                        s.w, d_count, q * dv, m * dv, out, cnt);
     return hipGetLastError();
 }

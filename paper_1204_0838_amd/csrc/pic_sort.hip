@@ -1,0 +1,199 @@
+// Counting sort of particles into tiles of Tx x Ty x Tz cells.
+//
+// Key of a particle = tile-major cell index: tile * Tcells + local cell.  A
+// histogram over keys (int atomics; the returned value is the particle's rank
+// within its cell), an exclusive scan of the histogram and a scatter place
+// every tile's particles contiguously, grouped by cell.  Removed particles
+// (cell < 0) are dropped.  Inside each tile the scatter applies the
+// permutation j -> j * s mod n_t (s = G^-1 mod n_t, G coprime to n_t), so that
+// consecutive particles in memory -- the lanes of one wavefront in the tiled
+// kernel -- come from cell-sorted positions G apart, i.e. from different cells:
+// their LDS current updates then hit different addresses.
+#include "pic_internal.h"
+#include "pic_particle_ops.h"
+
+namespace pic {
+
+__device__ __forceinline__ int tile_key(const TileGeom& t, const int c[3]) {
+    const int tx = c[0] / t.T[0], ty = c[1] / t.T[1], tz = c[2] / t.T[2];
+    const int lx = c[0] - tx * t.T[0], ly = c[1] - ty * t.T[1], lz = c[2] - tz * t.T[2];
+    const int tile = tx + t.nt[0] * (ty + t.nt[1] * tz);
+    return tile * t.tcells + lx + t.T[0] * (ly + t.T[1] * lz);
+}
+
+__global__ void __launch_bounds__(256) k_sort_count(Geom g, TileGeom t, const int* __restrict__ cell,
+                                                    const int* __restrict__ d_count, int* __restrict__ hist,
+                                                    int* __restrict__ rank) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= *d_count) return;
+    const int cl = cell[p];
+    if ((unsigned)cl >= (unsigned)g.ncell) {
+        rank[p] = -1;
+        return;
+    }
+    int c[3];
+    decompose(g, cl, c);
+    if (window_killed(g, c[0])) {
+        rank[p] = -1;
+        return;
+    }
+    rank[p] = atomicAdd(hist + tile_key(t, c), 1);
+}
+
+// Exclusive scan, phase 1: per-block totals of 1024-element blocks.
+__global__ void __launch_bounds__(1024) k_scan_reduce(const int* __restrict__ in, int n, int* __restrict__ sums) {
+    __shared__ int ws[16];
+    const int i = blockIdx.x * 1024 + threadIdx.x;
+    int v = i < n ? in[i] : 0;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int s = 0;
+        for (int k = 0; k < 16; ++k) s += ws[k];
+        sums[blockIdx.x] = s;
+    }
+}
+
+// Block-wide inclusive scan of one value per thread (1024 threads).
+__device__ __forceinline__ int block_scan_incl(int v, int* ws) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(v, o, 64);
+        if (lane >= o) v += y;
+    }
+    if (lane == 63) ws[wv] = v;
+    __syncthreads();
+    if (threadIdx.x < 16) {
+        int s = ws[threadIdx.x];
+        for (int o = 1; o < 16; o <<= 1) {
+            const int y = __shfl_up(s, o, 16);
+            if ((threadIdx.x & 15) >= o) s += y;
+        }
+        ws[16 + threadIdx.x] = s;
+    }
+    __syncthreads();
+    const int add = wv > 0 ? ws[16 + wv - 1] : 0;
+    __syncthreads();
+    return v + add;
+}
+
+// Phase 2: exclusive scan of the block totals by one workgroup; total -> sums[nb].
+__global__ void __launch_bounds__(1024) k_scan_sums(int* __restrict__ sums, int nb) {
+    __shared__ int ws[32];
+    __shared__ int carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < nb; base += 1024) {
+        const int i = base + threadIdx.x;
+        const int v = i < nb ? sums[i] : 0;
+        const int inc = block_scan_incl(v, ws);
+        const int c0 = carry;
+        if (i < nb) sums[i] = c0 + inc - v;
+        __syncthreads();
+        if (threadIdx.x == 1023) carry = c0 + inc;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sums[nb] = carry;
+}
+
+// Phase 3: exclusive scan inside each block plus the block offset; out may alias in.
+__global__ void __launch_bounds__(1024) k_scan_apply(const int* in, int n, const int* __restrict__ sums, int* out) {
+    __shared__ int ws[32];
+    const int i = blockIdx.x * 1024 + threadIdx.x;
+    const int v = i < n ? in[i] : 0;
+    const int inc = block_scan_incl(v, ws);
+    if (i < n) out[i] = sums[blockIdx.x] + inc - v;
+}
+
+// Per tile: particle count n_t and the multiplier s = G^-1 mod n_t of the
+// in-tile interleave (G = smallest value >= G0 coprime to n_t; s = 1 if G0 <= 1).
+__global__ void k_tile_stride(TileGeom t, const int* __restrict__ off, int g0, int* __restrict__ stride) {
+    const int tile = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tile >= t.ntiles) return;
+    const int n = off[(tile + 1) * t.tcells] - off[tile * t.tcells];
+    int s = 1;
+    if (g0 > 1 && n > 2) {
+        int G = g0 % n;
+        if (G < 2) G = 2;
+        for (; G < n; ++G) {   // smallest G >= g0 coprime to n
+            int a = n, b = G;
+            while (b) {
+                const int r = a % b;
+                a = b;
+                b = r;
+            }
+            if (a == 1) break;
+        }
+        if (G >= n) G = 1;
+        // inverse of G modulo n by the extended Euclidean algorithm
+        long long r0 = n, r1 = G, s0 = 0, s1 = 1;
+        while (r1) {
+            const long long q = r0 / r1;
+            long long tmp = r0 - q * r1;
+            r0 = r1;
+            r1 = tmp;
+            tmp = s0 - q * s1;
+            s0 = s1;
+            s1 = tmp;
+        }
+        s = (int)((s0 % n + n) % n);
+        if (s == 0) s = 1;
+    }
+    stride[tile] = s;
+}
+
+__global__ void __launch_bounds__(256) k_sort_scatter(Geom g, TileGeom t, SpeciesDev src, SpeciesDev dst,
+                                                      const int* __restrict__ d_count, const int* __restrict__ rank,
+                                                      const int* __restrict__ off, const int* __restrict__ stride) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= *d_count) return;
+    const int r = rank[p];
+    if (r < 0) return;
+    const int cl = src.cell[p];
+    int c[3];
+    decompose(g, cl, c);
+    const int key = tile_key(t, c);
+    const int tile = key / t.tcells;
+    const int tb = off[tile * t.tcells];
+    const int n = off[(tile + 1) * t.tcells] - tb;
+    const int j = off[key] - tb + r;
+    const int dest = tb + (int)(((long long)j * stride[tile]) % n);
+    dst.cell[dest] = cl;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        dst.off[d][dest] = src.off[d][p];
+        dst.u[d][dest] = src.u[d][p];
+    }
+    dst.w[dest] = src.w[p];
+    dst.id[dest] = src.id[p];
+}
+
+// New live count = total of the histogram.
+__global__ void k_sort_finish(const int* __restrict__ off, int nkeys, int* __restrict__ d_count,
+                              int* __restrict__ d_sorted) {
+    d_count[0] = off[nkeys];
+    d_sorted[0] = off[nkeys];
+}
+
+hipError_t launch_sort(const Geom& g, const TileGeom& t, const SpeciesDev& src, const SpeciesDev& dst,
+                       int* d_count, int* d_sorted, int max_count, int* hist, int* rank, int* sums, int* stride,
+                       int interleave, hipStream_t st) {
+    const int nkeys = t.ntiles * t.tcells;
+    hipError_t e = hipMemsetAsync(hist, 0, ((size_t)nkeys + 1) * sizeof(int), st);
+    if (e != hipSuccess) return e;
+    const int np = max_count > 0 ? max_count : 1;
+    hipLaunchKernelGGL(k_sort_count, dim3((np + 255) / 256), dim3(256), 0, st, g, t, src.cell, d_count, hist, rank);
+    const int n = nkeys + 1;
+    const int nb = (n + 1023) / 1024;
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(1024), 0, st, hist, n, sums);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, sums, nb);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(1024), 0, st, hist, n, sums, hist);
+    hipLaunchKernelGGL(k_tile_stride, dim3((t.ntiles + 255) / 256), dim3(256), 0, st, t, hist, interleave, stride);
+    hipLaunchKernelGGL(k_sort_scatter, dim3((np + 255) / 256), dim3(256), 0, st, g, t, src, dst, d_count, rank, hist,
+                       stride);
+    hipLaunchKernelGGL(k_sort_finish, dim3(1), dim3(1), 0, st, hist, nkeys, d_count, d_sorted);
+    return hipGetLastError();
+}
+
+}  // namespace pic

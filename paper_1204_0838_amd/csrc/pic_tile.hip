@@ -1,0 +1,287 @@
+// Fused gather + push + move + deposit over cell-sorted particle tiles.
+//
+// One workgroup per tile of T[0] x T[1] x T[2] cells.  The workgroup stages
+// E and B of the tile plus a halo of H = guard + 2 cells in LDS, zeroes an
+// int64 current tile covering the tile plus guard + 2 (low) / guard + 3 (high)
+// cells, and then streams its particles (coalesced SoA loads):
+//   particles still within `guard` cells of the tile: gather from LDS,
+//     deposit with LDS 64-bit atomics;
+//   particles that drifted further since the last sort: gather from global
+//     memory and deposit with global atomics (the same arithmetic, in a
+//     separate non-inlined function to keep the hot loop's code small).
+// Finally the non-zero LDS current is added to the global fixed-point
+// accumulator in one atomic pass.  Every value goes through the same device
+// functions as the split kernels, so the fused and split paths agree bit for
+// bit (integer sums are order-independent).
+//
+// Workgroups are mapped to tiles XCD by XCD: consecutive workgroup indices go
+// round-robin over the 8 XCDs, so tile = (b % 8) * ceil(ntiles/8) + b / 8
+// gives each XCD a contiguous range of tiles whose halos share its L2.
+#include "pic_internal.h"
+#include "pic_particle_ops.h"
+
+namespace pic {
+
+struct LdsEmit {
+    unsigned long long* J;   // LDS current tile, 3 components of jr nodes
+    int jr;
+    int X[5], Y[5], Z[5];
+    __device__ __forceinline__ void add(int comp, int jx, int jy, int jz, float v) const {
+        atomicAdd(J + (comp * jr + X[jx] + Y[jy] + Z[jz]), (unsigned long long)to_fix20(v));
+    }
+};
+
+struct GlobalEmitT {
+    unsigned long long* acc;
+    int ncell;
+    int X[5], Y[5], Z[5];
+    __device__ __forceinline__ void add(int comp, int jx, int jy, int jz, float v) const {
+        atomicAdd(acc + ((size_t)comp * ncell + X[jx] + Y[jy] + Z[jz]), (unsigned long long)to_fix20(v));
+    }
+};
+
+__device__ __forceinline__ int xcd_tile(int b, int ntiles) {
+    const int per = (ntiles + 7) / 8;
+    return (b % 8) * per + b / 8;
+}
+
+// One particle (index p, cell coordinates c) through global memory: gather,
+// push, move, store, deposit with global atomics.  Returns error flags.
+__device__ __noinline__ int push_deposit_global(const Geom& g, const FieldPtrs& f, const SpeciesDev& s, int p,
+                                                const int c[3], unsigned long long* acc) {
+    const int gstride[3] = {1, g.n[0], g.nxy};
+    float o[3] = {s.off[0][p], s.off[1][p], s.off[2][p]};
+    const float o0[3] = {o[0], o[1], o[2]};
+    float u[3] = {s.u[0][p], s.u[1][p], s.u[2][p]};
+    GatherStencil st;
+    gather_stencil(o, st);
+    int ii[3][4], ih[3][4];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            ii[d][a] = wrapi(c[d] - 1 + a, g.n[d]) * gstride[d];
+            ih[d][a] = wrapi(c[d] + st.hb[d] + a, g.n[d]) * gstride[d];
+        }
+    float E[3], B[3];
+    gather_fields(f.E, f.B, ii, ih, st, E, B);
+    int c1[3] = {c[0], c[1], c[2]};
+    const int errs = push_move(g, s.qmh, E, B, u, o, c1);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        s.u[d][p] = u[d];
+        s.off[d][p] = o[d];
+    }
+    s.cell[p] = c1[0] + g.n[0] * (c1[1] + g.n[1] * c1[2]);
+    if (!moved(c, c1, o0, o)) return errs;
+    Axis5 A[3];
+    GlobalEmitT em;
+    em.acc = acc;
+    em.ncell = g.ncell;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        axis5(unwrap_shift(c1[d] - c[d], g.n[d]), o0[d], o[d], A[d]);
+        int* dst = d == 0 ? em.X : (d == 1 ? em.Y : em.Z);
+#pragma unroll
+        for (int j = 0; j < 5; ++j) dst[j] = wrapi(c[d] + A[d].base + j, g.n[d]) * gstride[d];
+    }
+    esirkepov(A, s.mq * s.w[p], em);
+    return errs;
+}
+
+template <int NT>
+__global__ void __launch_bounds__(NT) k_pic_tile(Geom g, TileGeom t, int guard, FieldPtrs f, SpeciesDev s,
+                                                 const int* __restrict__ off, unsigned long long* __restrict__ acc,
+                                                 int* __restrict__ d_err) {
+    extern __shared__ unsigned long long lds_u64[];
+    const int tile = xcd_tile(blockIdx.x, t.ntiles);
+    if (tile >= t.ntiles) return;
+    const int tz = tile / (t.nt[0] * t.nt[1]);
+    const int tr = tile - tz * t.nt[0] * t.nt[1];
+    const int ty = tr / t.nt[0];
+    const int tx = tr - ty * t.nt[0];
+    const int t0[3] = {tx * t.T[0], ty * t.T[1], tz * t.T[2]};
+    int te[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) te[d] = min(t.T[d], g.n[d] - t0[d]);
+    const int H = guard + 2;
+    // LDS geometry (region sizes use the full tile size T, ragged tiles use part of it)
+    const int fx = t.T[0] + 2 * H, fy = t.T[1] + 2 * H, fz = t.T[2] + 2 * H;
+    const int fr = fx * fy * fz;
+    const int jx = t.T[0] + 2 * guard + 5, jy = t.T[1] + 2 * guard + 5, jz = t.T[2] + 2 * guard + 5;
+    const int jr = jx * jy * jz;
+    unsigned long long* Jl = lds_u64;
+    float* Fl = reinterpret_cast<float*>(lds_u64 + 3 * jr);
+
+    for (int i = threadIdx.x; i < 3 * jr; i += NT) Jl[i] = 0ull;
+    // stage E, B (tile + halo, periodic wrap in storage coordinates)
+    for (int i = threadIdx.x; i < fr; i += NT) {
+        const int lz = i / (fx * fy);
+        const int rr = i - lz * fx * fy;
+        const int ly = rr / fx;
+        const int lx = rr - ly * fx;
+        int gx = t0[0] - H + lx, gy = t0[1] - H + ly, gz = t0[2] - H + lz;
+        gx = ((gx % g.n[0]) + g.n[0]) % g.n[0];
+        gy = ((gy % g.n[1]) + g.n[1]) % g.n[1];
+        gz = ((gz % g.n[2]) + g.n[2]) % g.n[2];
+        const int gi = gx + g.n[0] * (gy + g.n[1] * gz);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            Fl[c * fr + i] = f.E[c][gi];
+            Fl[(3 + c) * fr + i] = f.B[c][gi];
+        }
+    }
+    __syncthreads();
+
+    float* const El[3] = {Fl, Fl + fr, Fl + 2 * fr};
+    float* const Bl[3] = {Fl + 3 * fr, Fl + 4 * fr, Fl + 5 * fr};
+    const int fstride[3] = {1, fx, fx * fy};
+    const int jstride[3] = {1, jx, jx * jy};
+    const int pb = off[tile * t.tcells];
+    const int pe = off[(tile + 1) * t.tcells];
+    int errs = 0;
+    for (int p = pb + threadIdx.x; p < pe; p += NT) {
+        const int cell = s.cell[p];
+        if ((unsigned)cell >= (unsigned)g.ncell) continue;
+        int c[3];
+        decompose(g, cell, c);
+        if (window_killed(g, c[0])) {
+            s.cell[p] = -1;
+            continue;
+        }
+        int lc[3];
+        bool inside = true;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            int l = c[d] - t0[d];
+            if (l >= te[d] + guard) l -= g.n[d];
+            if (l < -guard) l += g.n[d];
+            lc[d] = l;
+            inside = inside && l >= -guard && l < te[d] + guard;
+        }
+        if (!inside) {
+            errs |= push_deposit_global(g, f, s, p, c, acc);
+            continue;
+        }
+        float o[3] = {s.off[0][p], s.off[1][p], s.off[2][p]};
+        const float o0[3] = {o[0], o[1], o[2]};
+        float u[3] = {s.u[0][p], s.u[1][p], s.u[2][p]};
+        const float wq = s.mq * s.w[p];
+        GatherStencil st;
+        gather_stencil(o, st);
+        float E[3], B[3];
+        {
+            int ii[3][4], ih[3][4];
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    ii[d][a] = (lc[d] + H - 1 + a) * fstride[d];
+                    ih[d][a] = (lc[d] + H + st.hb[d] + a) * fstride[d];
+                }
+            gather_fields(El, Bl, ii, ih, st, E, B);
+        }
+        int c1[3] = {c[0], c[1], c[2]};
+        errs |= push_move(g, s.qmh, E, B, u, o, c1);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            s.u[d][p] = u[d];
+            s.off[d][p] = o[d];
+        }
+        s.cell[p] = c1[0] + g.n[0] * (c1[1] + g.n[1] * c1[2]);
+        if (!moved(c, c1, o0, o)) continue;   // every contribution would be zero
+        Axis5 A[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) axis5(unwrap_shift(c1[d] - c[d], g.n[d]), o0[d], o[d], A[d]);
+        LdsEmit em;
+        em.J = Jl;
+        em.jr = jr;
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            em.X[j] = (lc[0] + guard + 2 + A[0].base + j) * jstride[0];
+            em.Y[j] = (lc[1] + guard + 2 + A[1].base + j) * jstride[1];
+            em.Z[j] = (lc[2] + guard + 2 + A[2].base + j) * jstride[2];
+        }
+        esirkepov(A, wq, em);
+    }
+    if (errs) atomicOr(d_err, errs);
+    __syncthreads();
+    // flush the non-zero LDS current into the global accumulator
+    const int lo = guard + 2;
+    for (int i = threadIdx.x; i < 3 * jr; i += NT) {
+        const unsigned long long v = Jl[i];
+        if (v == 0ull) continue;
+        const int comp = i / jr;
+        const int k = i - comp * jr;
+        const int lz = k / (jx * jy);
+        const int rr = k - lz * jx * jy;
+        const int ly = rr / jx;
+        const int lx = rr - ly * jx;
+        int gx = t0[0] - lo + lx, gy = t0[1] - lo + ly, gz = t0[2] - lo + lz;
+        gx = ((gx % g.n[0]) + g.n[0]) % g.n[0];
+        gy = ((gy % g.n[1]) + g.n[1]) % g.n[1];
+        gz = ((gz % g.n[2]) + g.n[2]) % g.n[2];
+        atomicAdd(acc + ((size_t)comp * g.ncell + gx + g.n[0] * (gy + g.n[1] * gz)), v);
+    }
+}
+
+// Particles appended after the last sort (not in any tile range): the same
+// step through global memory.
+__global__ void __launch_bounds__(256) k_push_deposit_range(Geom g, FieldPtrs f, SpeciesDev s,
+                                                            const int* __restrict__ d_begin,
+                                                            const int* __restrict__ d_count,
+                                                            unsigned long long* __restrict__ acc,
+                                                            int* __restrict__ d_err) {
+    const int p = *d_begin + blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= *d_count) return;
+    const int cell = s.cell[p];
+    if ((unsigned)cell >= (unsigned)g.ncell) return;
+    int c[3];
+    decompose(g, cell, c);
+    if (window_killed(g, c[0])) {
+        s.cell[p] = -1;
+        return;
+    }
+    const int errs = push_deposit_global(g, f, s, p, c, acc);
+    if (errs) atomicOr(d_err, errs);
+}
+
+size_t tile_lds_bytes(const TileGeom& t, int guard) {
+    const size_t H = guard + 2;
+    const size_t fr = (t.T[0] + 2 * H) * (t.T[1] + 2 * H) * (t.T[2] + 2 * H);
+    const size_t jr = (size_t)(t.T[0] + 2 * guard + 5) * (t.T[1] + 2 * guard + 5) * (t.T[2] + 2 * guard + 5);
+    return 3 * jr * 8 + 6 * fr * 4;
+}
+
+template <int NT>
+static hipError_t launch_tile_nt(const Geom& g, const TileGeom& t, int guard, const FieldPtrs& f,
+                                 const SpeciesDev& s, const int* off, unsigned long long* acc, int* d_err,
+                                 hipStream_t st) {
+    const size_t lds = tile_lds_bytes(t, guard);
+    const int nb = ((t.ntiles + 7) / 8) * 8;
+    hipError_t e = hipFuncSetAttribute((const void*)k_pic_tile<NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_pic_tile<NT>, dim3(nb), dim3(NT), lds, st, g, t, guard, f, s, off, acc, d_err);
+    return hipGetLastError();
+}
+
+hipError_t launch_pic_tile(const Geom& g, const TileGeom& t, int guard, int threads, const FieldPtrs& f,
+                           const SpeciesDev& s, const int* off, unsigned long long* acc, int* d_err, hipStream_t st) {
+    switch (threads) {
+        case 256: return launch_tile_nt<256>(g, t, guard, f, s, off, acc, d_err, st);
+        case 1024: return launch_tile_nt<1024>(g, t, guard, f, s, off, acc, d_err, st);
+        default: return launch_tile_nt<512>(g, t, guard, f, s, off, acc, d_err, st);
+    }
+}
+
+hipError_t launch_push_deposit_range(const Geom& g, const FieldPtrs& f, const SpeciesDev& s, const int* d_begin,
+                                     const int* d_count, int max_n, unsigned long long* acc, int* d_err,
+                                     hipStream_t st) {
+    if (max_n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_push_deposit_range, dim3((max_n + 255) / 256), dim3(256), 0, st, g, f, s, d_begin, d_count,
+                       acc, d_err);
+    return hipGetLastError();
+}
+
+}  // namespace pic

@@ -35,7 +35,7 @@ class GridDesc(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32 * 3), ("solver", ctypes.c_int32), ("d", ctypes.c_double * 3),
                 ("dt", ctypes.c_double), ("pd_variant", ctypes.c_int32), ("bc_x", ctypes.c_int32),
                 ("jpost", ctypes.c_int32), ("tile", ctypes.c_int32 * 3), ("sort_interval", ctypes.c_int32),
-                ("reserved_", ctypes.c_int32 * 3)]
+                ("guard", ctypes.c_int32), ("threads", ctypes.c_int32), ("interleave", ctypes.c_int32)]
 
 
 _vp = ctypes.c_void_p
@@ -55,8 +55,25 @@ class Diag(ctypes.Structure):
                 ("max_abs_J", ctypes.c_double), ("n_particles", ctypes.c_int64), ("step", ctypes.c_int64)]
 
 
+class LaserDesc(ctypes.Structure):
+    _fields_ = [("a0", ctypes.c_double), ("omega0", ctypes.c_double), ("waist", ctypes.c_double),
+                ("fwhm", ctypes.c_double), ("t_peak", ctypes.c_double), ("t_end", ctypes.c_double),
+                ("yc", ctypes.c_double), ("zc", ctypes.c_double), ("src_x", ctypes.c_int32),
+                ("pad_", ctypes.c_int32)]
+
+
+class PlasmaDesc(ctypes.Structure):
+    _fields_ = [("x_start", ctypes.c_double), ("ramp", ctypes.c_double), ("n_plateau", ctypes.c_double),
+                ("ppc", ctypes.c_int32 * 3), ("pad_", ctypes.c_int32)]
+
+
 # every symbol the header declares, with its ctypes signature
 _SIGS = {
+    "pic_set_laser": (ctypes.c_int, [_vp, ctypes.POINTER(LaserDesc)]),
+    "pic_set_plasma": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(PlasmaDesc)]),
+    "pic_inject_plasma": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "pic_set_window": (ctypes.c_int, [_vp, ctypes.c_int64]),
+    "pic_window_state": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]),
     "pic_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(GridDesc), ctypes.c_int64]),
     "pic_validate_grid": (ctypes.c_int, [ctypes.POINTER(GridDesc), ctypes.c_char_p, ctypes.c_size_t]),
     "pic_init_grid": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(GridDesc), ctypes.POINTER(FieldBufs), _vp,
@@ -96,7 +113,8 @@ def lib():
     return _lib
 
 
-def make_desc(n, d, dt, solver="yee", bc_x=0, jpost="none", pd_variant=0, tile=(0, 0, 0), sort_interval=0):
+def make_desc(n, d, dt, solver="yee", bc_x=0, jpost="none", pd_variant=0, tile=(0, 0, 0), sort_interval=0,
+              guard=-1, threads=0, interleave=0):
     g = GridDesc()
     for a in range(3):
         g.n[a] = int(n[a])
@@ -108,6 +126,9 @@ def make_desc(n, d, dt, solver="yee", bc_x=0, jpost="none", pd_variant=0, tile=(
     g.jpost = JPOST[jpost] if isinstance(jpost, str) else int(jpost)
     g.pd_variant = int(pd_variant)
     g.sort_interval = int(sort_interval)
+    g.guard = int(guard)
+    g.threads = int(threads)
+    g.interleave = int(interleave)
     return g
 
 
@@ -134,8 +155,9 @@ class Simulation:
     """
 
     def __init__(self, n, d, dt, solver="yee", bc_x=0, jpost="none", pd_variant=0, tile=(0, 0, 0),
-                 sort_interval=0, max_particles=0, device="cuda:0", stream=None):
-        self.desc = make_desc(n, d, dt, solver, bc_x, jpost, pd_variant, tile, sort_interval)
+                 sort_interval=0, guard=-1, threads=0, interleave=0, max_particles=0, device="cuda:0", stream=None):
+        self.desc = make_desc(n, d, dt, solver, bc_x, jpost, pd_variant, tile, sort_interval, guard, threads,
+                              interleave)
         st, msg = validate(self.desc)
         if st != PIC_OK:
             raise PicError(st, msg)
@@ -216,6 +238,40 @@ class Simulation:
     def add_particles(self, p, capacity=None):
         """Register an ``inputs.Particles`` set."""
         return self.add_species(p.cell, p.off, p.u, p.w, p.id, p.q, p.m, capacity)
+
+    def add_empty_species(self, capacity, q=-1.0, m=1.0):
+        """Register a species with no particles yet (filled by plasma injection)."""
+        z = np.zeros(0, np.int32)
+        zf = np.zeros((3, 0), np.float32)
+        return self.add_species(z, zf, zf, np.zeros(0, np.float32), z, q, m, capacity)
+
+    # ------------------------------------------------------------ laser-wakefield boundaries
+    def set_laser(self, a0, omega0, waist, fwhm, t_peak, t_end, yc, zc, src_x):
+        L = LaserDesc(float(a0), float(omega0), float(waist), float(fwhm), float(t_peak), float(t_end), float(yc),
+                      float(zc), int(src_x), 0)
+        self._check(lib().pic_set_laser(self.handle, ctypes.byref(L)))
+
+    def set_plasma(self, s, x_start, ramp, n_plateau, ppc=(2, 2, 2)):
+        P = PlasmaDesc(float(x_start), float(ramp), float(n_plateau))
+        for a in range(3):
+            P.ppc[a] = int(ppc[a])
+        self._check(lib().pic_set_plasma(self.handle, s, ctypes.byref(P)))
+
+    def inject_plasma(self, s, x_begin, x_end):
+        self._check(lib().pic_inject_plasma(self.handle, s, int(x_begin), int(x_end)))
+
+    def set_window(self, start_step):
+        self._check(lib().pic_set_window(self.handle, int(start_step)))
+
+    def window_state(self):
+        sh, org = ctypes.c_int64(), ctypes.c_int32()
+        self._check(lib().pic_window_state(self.handle, ctypes.byref(sh), ctypes.byref(org)))
+        return sh.value, org.value
+
+    def fields_window_order(self):
+        """E, B, J as numpy arrays rolled so that x index 0 is the window's trailing cell."""
+        _, org = self.window_state()
+        return tuple(np.roll(t.cpu().numpy(), -org, axis=3) for t in (self.E, self.B, self.J))
 
     # ------------------------------------------------------------ the cycle
     def gather_push(self, s=0):

@@ -1,0 +1,89 @@
+"""The production path (cell sort + fused LDS-tiled gather/push/deposit) against
+the split kernels: identical results bit for bit, whatever the tile shape,
+guard, in-tile interleave or sort interval (integer current sums make the
+result independent of particle order and of which path handled a particle)."""
+import numpy as np
+import pytest
+
+from paper_1204_0838_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1204_0838_amd import pic  # noqa: E402
+
+
+def _pair(grid, pl, **kw):
+    a = pic.Simulation(grid.n, grid.d, grid.dt, solver=grid.solver, max_particles=pl.count, **kw)
+    b = pic.Simulation(grid.n, grid.d, grid.dt, solver=grid.solver, max_particles=pl.count)
+    a.add_particles(pl)
+    b.add_particles(pl)
+    return a, b
+
+
+def _assert_same(a, b):
+    for fa, fb in ((a.E, b.E), (a.B, b.B), (a.J, b.J)):
+        assert torch.equal(fa, fb)
+    pa, pb = a.particles_host(0), b.particles_host(0)
+    assert pa["id"].shape == pb["id"].shape
+    ia, ib = np.argsort(pa["id"]), np.argsort(pb["id"])
+    assert np.array_equal(pa["id"][ia], pb["id"][ib])
+    assert np.array_equal(pa["u"][:, ia], pb["u"][:, ib])
+    assert np.array_equal(pa["off"][:, ia], pb["off"][:, ib])
+    assert np.array_equal(pa["cell"][ia], pb["cell"][ib])
+
+
+CASES = [
+    dict(tile=(8, 8, 8), guard=1, interleave=17, sort_interval=2, threads=512),
+    dict(tile=(4, 4, 4), guard=0, interleave=1, sort_interval=3, threads=256),
+    dict(tile=(8, 4, 4), guard=2, interleave=5, sort_interval=1, threads=1024),
+    dict(tile=(5, 3, 7), guard=1, interleave=17, sort_interval=4, threads=512),
+]
+
+
+@pytest.mark.parametrize("kw", CASES, ids=lambda k: "t{}g{}i{}s{}".format(k["tile"][0], k["guard"],
+                                                                         k["interleave"], k["sort_interval"]))
+def test_fused_step_equals_split_bit_exact_yee(kw):
+    grid = inputs.Grid(n=(13, 10, 9), d=(0.3, 0.25, 0.35), dt=0.1)
+    pl = inputs.uniform_random_plasma(grid, ppc=6, seed=41, temperature_ev=30000.0, ux_amp=0.1)
+    a, b = _pair(grid, pl, **kw)
+    a.step(6)
+    for _ in range(6):
+        b.gather_push(0)
+        b.deposit(0)
+        b.field_step()
+    _assert_same(a, b)
+
+
+def test_fused_step_equals_split_bit_exact_pd_larger():
+    grid = inputs.Grid(n=(40, 24, 20), d=(0.25, 0.5, 0.5), dt=0.25, solver="pd")
+    pl = inputs.uniform_random_plasma(grid, ppc=8, seed=43, temperature_ev=100000.0, ux_amp=0.3)
+    a, b = _pair(grid, pl, tile=(8, 8, 8), guard=1, interleave=17, sort_interval=2)
+    a.step(5)
+    for _ in range(5):
+        b.gather_push(0)
+        b.deposit(0)
+        b.field_step()
+    _assert_same(a, b)
+
+
+def test_sort_groups_particles_by_tile_and_keeps_them():
+    grid = inputs.Grid(n=(24, 16, 12), d=(0.25, 0.5, 0.5), dt=0.25, solver="pd")
+    pl = inputs.uniform_random_plasma(grid, ppc=4, seed=44)
+    T = (8, 4, 6)
+    sim = pic.Simulation(grid.n, grid.d, grid.dt, solver="pd", tile=T, max_particles=pl.count)
+    sim.add_particles(pl)
+    sim.sort(0)
+    got = sim.particles_host(0)
+    assert np.array_equal(np.sort(got["id"]), np.sort(pl.id))
+    order = np.argsort(got["id"])
+    assert np.array_equal(got["cell"][order], pl.cell)
+    assert np.array_equal(got["off"][:, order], pl.off)
+    c = got["cell"].astype(np.int64)
+    nx, ny, _ = grid.n
+    tx, ty, tz = (c % nx) // T[0], ((c // nx) % ny) // T[1], (c // (nx * ny)) // T[2]
+    tile = tx + 3 * (ty + 4 * tz)
+    assert np.all(np.diff(tile) >= 0)   # tiles are contiguous and in order
