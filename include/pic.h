@@ -95,8 +95,10 @@ enum { PIC_JPOST_NONE = 0, PIC_JPOST_BINOMIAL = 1, PIC_JPOST_DENOISER = 2 };
  *                24 B x prod(T + 2 guard + 5) + 24 B x prod(T + 2 guard + 4)
  *                must fit in 160 KiB.
  *   threads      threads per tile workgroup (256, 512 or 1024; 0 = 512).
- *   interleave   in-tile interleave stride of the sort (0 = default 17,
- *                1 = plain cell order). */
+ *   interleave   depth D of the sort's in-tile block transpose: each full
+ *                block of 64 D cell-sorted particles is stored D x 64
+ *                transposed so a wavefront's lanes hold different cells
+ *                (0 = default 8, 1 = plain cell order). */
 typedef struct {
     int32_t n[3];
     int32_t solver;
@@ -170,6 +172,19 @@ typedef struct {
     int32_t ppc[3];
     int32_t pad_;
 } pic_plasma_desc;
+
+/* Device time of the phases of pic_step, measured with HIP events on the
+ * context's stream between pic_profile_enable and pic_profile_read
+ * (milliseconds, summed over steps and species). */
+typedef struct {
+    double sort_ms;      /* cell sorts */
+    double tile_ms;      /* fused tiled gather + push + deposit launches */
+    double loose_ms;     /* particles appended since the last sort */
+    double jpost_ms;     /* current read-out and post-processing */
+    double field_ms;     /* B half step, E step, B half step (+ laser source) */
+    double window_ms;    /* window motion and plasma injection */
+    int64_t steps, sorts, tile_launches;
+} pic_profile;
 
 typedef struct pic_ctx pic_ctx;
 
@@ -268,6 +283,15 @@ pic_status pic_set_window(pic_ctx *ctx, int64_t start_step);
 /* Cells the window has moved and the storage x index of window cell 0
  * (host outputs). */
 pic_status pic_window_state(pic_ctx *ctx, int64_t *shift, int32_t *origin);
+
+/* Start (enable != 0) or stop timing the phases of pic_step; starting
+ * clears the accumulated times.  Creates HIP events on first use (host
+ * runtime objects, no device memory). */
+pic_status pic_profile_enable(pic_ctx *ctx, int32_t enable);
+
+/* Accumulated phase times since pic_profile_enable (host output).
+ * Synchronises the stream. */
+pic_status pic_profile_read(pic_ctx *ctx, pic_profile *out);
 
 /* Text of the sticky error (never NULL). */
 const char *pic_last_error(const pic_ctx *ctx);

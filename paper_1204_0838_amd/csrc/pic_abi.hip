@@ -41,7 +41,7 @@ Tiling tiling_of(const pic_grid_desc* d) {
     r.t.tcells = r.t.T[0] * r.t.T[1] * r.t.T[2];
     r.guard = d->guard < 0 ? 1 : d->guard;
     r.threads = d->threads > 0 ? d->threads : 512;
-    r.interleave = d->interleave > 0 ? d->interleave : 17;
+    r.interleave = d->interleave > 0 ? d->interleave : 8;
     r.sort_interval = d->sort_interval > 0 ? d->sort_interval : 2;
     return r;
 }
@@ -132,6 +132,19 @@ struct pic_ctx {
     int64_t shift = 0;
     bool has_plasma[kMaxSpecies] = {};
     PlasmaDev plasma[kMaxSpecies];
+    // phase timing (pic_profile_*)
+    bool prof_on = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    struct Mark {
+        int phase;
+        hipEvent_t a, b;
+    };
+    std::vector<Mark> marks;
+    int64_t prof_steps = 0, prof_sorts = 0, prof_tiles = 0;
+    ~pic_ctx() {
+        for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    }
 };
 
 namespace {
@@ -360,17 +373,44 @@ pic_status inject_slab(pic_ctx* c, int32_t s, int32_t xb, int32_t xe) {
     return PIC_OK;
 }
 
+// Phase timing: an event recorded before and after each timed phase.
+enum { PH_SORT, PH_TILE, PH_LOOSE, PH_JPOST, PH_FIELD, PH_WINDOW, PH_COUNT };
+
+pic_status prof_mark(pic_ctx* c, hipEvent_t* ev) {
+    *ev = nullptr;
+    if (!c->prof_on) return PIC_OK;
+    if (c->ev_used == c->ev_pool.size()) {
+        hipEvent_t e;
+        HIPCHK(c, hipEventCreate(&e));
+        c->ev_pool.push_back(e);
+    }
+    *ev = c->ev_pool[c->ev_used++];
+    HIPCHK(c, hipEventRecord(*ev, c->stream));
+    return PIC_OK;
+}
+
+pic_status prof_end(pic_ctx* c, int phase, hipEvent_t start) {
+    if (!c->prof_on || !start) return PIC_OK;
+    hipEvent_t e;
+    PICCHK(prof_mark(c, &e));
+    c->marks.push_back({phase, start, e});
+    return PIC_OK;
+}
+
 // End of a step: count it; move the window one cell when it is due.
 pic_status end_step(pic_ctx* c) {
     c->step += 1;
+    if (c->prof_on) c->prof_steps += 1;
     if (!c->g.window || c->step < c->window_start) return PIC_OK;
+    hipEvent_t t0;
+    PICCHK(prof_mark(c, &t0));
     HIPCHK(c, launch_clear_plane(c->g, fields_of(c), c->g.origin, c->stream));
     c->g.origin = c->g.origin + 1 == c->g.n[0] ? 0 : c->g.origin + 1;
     c->shift += 1;
     const int slab = c->g.n[0] - 1 - c->g.kill_hi;
     for (int32_t s = 0; s < (int32_t)c->sp.size(); ++s)
         if (c->has_plasma[s]) PICCHK(inject_slab(c, s, slab, slab + 1));
-    return PIC_OK;
+    return prof_end(c, PH_WINDOW, t0);
 }
 
 pic_status sort_species(pic_ctx* c, int32_t s) {
@@ -379,7 +419,7 @@ pic_status sort_species(pic_ctx* c, int32_t s) {
     int* rank = reinterpret_cast<int*>(c->ws + c->L.sort_rank) + sp.base;
     HIPCHK(c, launch_sort(c->g, c->tl.t, dev_from(c, sp, sp.cur), dev_from(c, sp, sp.alt), &sm->count[s],
                           &sm->sorted[s], (int)sp.bound, hist_of(c), rank, reinterpret_cast<int*>(c->ws + c->L.sums),
-                          reinterpret_cast<int*>(c->ws + c->L.stride), c->tl.interleave, c->stream));
+                          c->tl.interleave, c->stream));
     std::swap(sp.cur, sp.alt);
     sp.sorted = true;
     sp.sort_step = c->step;
@@ -393,6 +433,8 @@ pic_status finish_step(pic_ctx* c) {
     double sc[3];
     jscale(c, sc);
     float* Juse[3] = {c->f.J[0], c->f.J[1], c->f.J[2]};
+    hipEvent_t t0, t1;
+    PICCHK(prof_mark(c, &t0));
     if (c->desc.jpost == PIC_JPOST_BINOMIAL) {
         float* tmp[3];
         jtmp_of(c, tmp);
@@ -403,7 +445,10 @@ pic_status finish_step(pic_ctx* c) {
     } else {
         return fail(c, PIC_EINVAL, "denoiser weights not set");
     }
+    PICCHK(prof_end(c, PH_JPOST, t0));
+    PICCHK(prof_mark(c, &t1));
     PICCHK(field_update(c, Juse));
+    PICCHK(prof_end(c, PH_FIELD, t1));
     return end_step(c);
 }
 
@@ -555,12 +600,25 @@ pic_status pic_step(pic_ctx* c, int32_t nsteps) {
     for (int32_t it = 0; it < nsteps; ++it) {
         for (int32_t s = 0; s < (int32_t)c->sp.size(); ++s) {
             Species& sp = c->sp[s];
-            if (!sp.sorted || c->step - sp.sort_step >= c->tl.sort_interval) PICCHK(sort_species(c, s));
+            hipEvent_t t0, t1, t2;
+            if (!sp.sorted || c->step - sp.sort_step >= c->tl.sort_interval) {
+                PICCHK(prof_mark(c, &t0));
+                PICCHK(sort_species(c, s));
+                PICCHK(prof_end(c, PH_SORT, t0));
+                if (c->prof_on) c->prof_sorts += 1;
+            }
             Small* sm = small_of(c);
+            PICCHK(prof_mark(c, &t1));
             HIPCHK(c, launch_pic_tile(c->g, c->tl.t, c->tl.guard, c->tl.threads, fields_of(c), dev_of(c, sp),
                                       hist_of(c), acc_of(c), &sm->err, c->stream));
-            HIPCHK(c, launch_push_deposit_range(c->g, fields_of(c), dev_of(c, sp), &sm->sorted[s], &sm->count[s],
-                                                (int)sp.loose, acc_of(c), &sm->err, c->stream));
+            PICCHK(prof_end(c, PH_TILE, t1));
+            if (c->prof_on) c->prof_tiles += 1;
+            if (sp.loose > 0) {
+                PICCHK(prof_mark(c, &t2));
+                HIPCHK(c, launch_push_deposit_range(c->g, fields_of(c), dev_of(c, sp), &sm->sorted[s],
+                                                    &sm->count[s], (int)sp.loose, acc_of(c), &sm->err, c->stream));
+                PICCHK(prof_end(c, PH_LOOSE, t2));
+            }
             sp.prev_valid = false;
         }
         PICCHK(finish_step(c));
@@ -712,6 +770,39 @@ pic_status pic_window_state(pic_ctx* c, int64_t* shift, int32_t* origin) {
     if (!c) return PIC_EINVAL;
     if (shift) *shift = c->shift;
     if (origin) *origin = c->g.origin;
+    return PIC_OK;
+}
+
+pic_status pic_profile_enable(pic_ctx* c, int32_t enable) {
+    if (!c) return PIC_EINVAL;
+    if (enable) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        c->marks.clear();
+        c->ev_used = 0;
+        c->prof_steps = c->prof_sorts = c->prof_tiles = 0;
+    }
+    c->prof_on = enable != 0;
+    return PIC_OK;
+}
+
+pic_status pic_profile_read(pic_ctx* c, pic_profile* out) {
+    if (!c || !out) return PIC_EINVAL;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double ms[PH_COUNT] = {0, 0, 0, 0, 0, 0};
+    for (const auto& m : c->marks) {
+        float t = 0.0f;
+        HIPCHK(c, hipEventElapsedTime(&t, m.a, m.b));
+        ms[m.phase] += t;
+    }
+    out->sort_ms = ms[PH_SORT];
+    out->tile_ms = ms[PH_TILE];
+    out->loose_ms = ms[PH_LOOSE];
+    out->jpost_ms = ms[PH_JPOST];
+    out->field_ms = ms[PH_FIELD];
+    out->window_ms = ms[PH_WINDOW];
+    out->steps = c->prof_steps;
+    out->sorts = c->prof_sorts;
+    out->tile_launches = c->prof_tiles;
     return PIC_OK;
 }
 

@@ -36,12 +36,14 @@ hipError_t launch_jfinal(const Geom& g, unsigned long long* acc, float* const J[
                          int zero_acc, hipStream_t st);
 
 // sort (pic_sort.hip): src -> dst, new count into d_count and d_sorted
+// depth: in-tile block-transpose depth (1 = plain cell order)
 hipError_t launch_sort(const Geom& g, const TileGeom& t, const SpeciesDev& src, const SpeciesDev& dst,
-                       int* d_count, int* d_sorted, int max_count, int* hist, int* rank, int* sums, int* stride,
-                       int interleave, hipStream_t st);
+                       int* d_count, int* d_sorted, int max_count, int* hist, int* rank, int* sums, int depth,
+                       hipStream_t st);
 
 // fused tile kernel (pic_tile.hip)
 size_t tile_lds_bytes(const TileGeom& t, int guard);
+// off: scanned key histogram of the last sort (tile ranges)
 hipError_t launch_pic_tile(const Geom& g, const TileGeom& t, int guard, int threads, const FieldPtrs& f,
                            const SpeciesDev& s, const int* off, unsigned long long* acc, int* d_err, hipStream_t st);
 hipError_t launch_push_deposit_range(const Geom& g, const FieldPtrs& f, const SpeciesDev& s, const int* d_begin,

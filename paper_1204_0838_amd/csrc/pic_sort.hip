@@ -3,12 +3,17 @@
 // Key of a particle = tile-major cell index: tile * Tcells + local cell.  A
 // histogram over keys (int atomics; the returned value is the particle's rank
 // within its cell), an exclusive scan of the histogram and a scatter place
-// every tile's particles contiguously, grouped by cell.  Removed particles
-// (cell < 0) are dropped.  Inside each tile the scatter applies the
-// permutation j -> j * s mod n_t (s = G^-1 mod n_t, G coprime to n_t), so that
-// consecutive particles in memory -- the lanes of one wavefront in the tiled
-// kernel -- come from cell-sorted positions G apart, i.e. from different cells:
-// their LDS current updates then hit different addresses.
+// every tile's particles contiguously.  Removed particles (cell < 0, or
+// outside a moving window) are dropped.
+//
+// Inside a tile the cell-sorted sequence is stored block-transposed: each full
+// block of 64*D particles (D = the interleave depth) is written as a D x 64
+// transpose, so the 64 lanes of a wavefront that reads the block in order see
+// particles D apart in cell order -- different cells at D >= particles per
+// cell -- and their LDS current atomics rarely hit the same address, while
+// the loads stay coalesced.  For particles that kept their cell since the last
+// sort the scatter is an in-place streaming copy (the same permutation is
+// recomputed from the same key and rank).
 #include "pic_internal.h"
 #include "pic_particle_ops.h"
 
@@ -106,46 +111,9 @@ __global__ void __launch_bounds__(1024) k_scan_apply(const int* in, int n, const
     if (i < n) out[i] = sums[blockIdx.x] + inc - v;
 }
 
-// Per tile: particle count n_t and the multiplier s = G^-1 mod n_t of the
-// in-tile interleave (G = smallest value >= G0 coprime to n_t; s = 1 if G0 <= 1).
-__global__ void k_tile_stride(TileGeom t, const int* __restrict__ off, int g0, int* __restrict__ stride) {
-    const int tile = blockIdx.x * blockDim.x + threadIdx.x;
-    if (tile >= t.ntiles) return;
-    const int n = off[(tile + 1) * t.tcells] - off[tile * t.tcells];
-    int s = 1;
-    if (g0 > 1 && n > 2) {
-        int G = g0 % n;
-        if (G < 2) G = 2;
-        for (; G < n; ++G) {   // smallest G >= g0 coprime to n
-            int a = n, b = G;
-            while (b) {
-                const int r = a % b;
-                a = b;
-                b = r;
-            }
-            if (a == 1) break;
-        }
-        if (G >= n) G = 1;
-        // inverse of G modulo n by the extended Euclidean algorithm
-        long long r0 = n, r1 = G, s0 = 0, s1 = 1;
-        while (r1) {
-            const long long q = r0 / r1;
-            long long tmp = r0 - q * r1;
-            r0 = r1;
-            r1 = tmp;
-            tmp = s0 - q * s1;
-            s0 = s1;
-            s1 = tmp;
-        }
-        s = (int)((s0 % n + n) % n);
-        if (s == 0) s = 1;
-    }
-    stride[tile] = s;
-}
-
 __global__ void __launch_bounds__(256) k_sort_scatter(Geom g, TileGeom t, SpeciesDev src, SpeciesDev dst,
                                                       const int* __restrict__ d_count, const int* __restrict__ rank,
-                                                      const int* __restrict__ off, const int* __restrict__ stride) {
+                                                      const int* __restrict__ off, int depth) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= *d_count) return;
     const int r = rank[p];
@@ -154,11 +122,18 @@ __global__ void __launch_bounds__(256) k_sort_scatter(Geom g, TileGeom t, Specie
     int c[3];
     decompose(g, cl, c);
     const int key = tile_key(t, c);
-    const int tile = key / t.tcells;
-    const int tb = off[tile * t.tcells];
-    const int n = off[(tile + 1) * t.tcells] - tb;
-    const int j = off[key] - tb + r;
-    const int dest = tb + (int)(((long long)j * stride[tile]) % n);
+    int dest = off[key] + r;
+    if (depth > 1) {
+        const int tile = key / t.tcells;
+        const int tb = off[tile * t.tcells];
+        const int blk = 64 * depth;
+        const int nfull = (off[(tile + 1) * t.tcells] - tb) / blk * blk;
+        const int j = dest - tb;
+        if (j < nfull) {
+            const int b0 = j - j % blk, k = j - b0;
+            dest = tb + b0 + (k % depth) * 64 + k / depth;
+        }
+    }
     dst.cell[dest] = cl;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -177,8 +152,8 @@ __global__ void k_sort_finish(const int* __restrict__ off, int nkeys, int* __res
 }
 
 hipError_t launch_sort(const Geom& g, const TileGeom& t, const SpeciesDev& src, const SpeciesDev& dst,
-                       int* d_count, int* d_sorted, int max_count, int* hist, int* rank, int* sums, int* stride,
-                       int interleave, hipStream_t st) {
+                       int* d_count, int* d_sorted, int max_count, int* hist, int* rank, int* sums, int depth,
+                       hipStream_t st) {
     const int nkeys = t.ntiles * t.tcells;
     hipError_t e = hipMemsetAsync(hist, 0, ((size_t)nkeys + 1) * sizeof(int), st);
     if (e != hipSuccess) return e;
@@ -189,9 +164,8 @@ hipError_t launch_sort(const Geom& g, const TileGeom& t, const SpeciesDev& src, 
     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(1024), 0, st, hist, n, sums);
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, sums, nb);
     hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(1024), 0, st, hist, n, sums, hist);
-    hipLaunchKernelGGL(k_tile_stride, dim3((t.ntiles + 255) / 256), dim3(256), 0, st, t, hist, interleave, stride);
     hipLaunchKernelGGL(k_sort_scatter, dim3((np + 255) / 256), dim3(256), 0, st, g, t, src, dst, d_count, rank, hist,
-                       stride);
+                       depth);
     hipLaunchKernelGGL(k_sort_finish, dim3(1), dim3(1), 0, st, hist, nkeys, d_count, d_sorted);
     return hipGetLastError();
 }

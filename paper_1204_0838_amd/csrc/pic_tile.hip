@@ -91,8 +91,8 @@ __device__ __noinline__ int push_deposit_global(const Geom& g, const FieldPtrs& 
 
 template <int NT>
 __global__ void __launch_bounds__(NT) k_pic_tile(Geom g, TileGeom t, int guard, FieldPtrs f, SpeciesDev s,
-                                                 const int* __restrict__ off, unsigned long long* __restrict__ acc,
-                                                 int* __restrict__ d_err) {
+                                                 const int* __restrict__ off,
+                                                 unsigned long long* __restrict__ acc, int* __restrict__ d_err) {
     extern __shared__ unsigned long long lds_u64[];
     const int tile = xcd_tile(blockIdx.x, t.ntiles);
     if (tile >= t.ntiles) return;
@@ -138,10 +138,31 @@ __global__ void __launch_bounds__(NT) k_pic_tile(Geom g, TileGeom t, int guard, 
     const int fstride[3] = {1, fx, fx * fy};
     const int jstride[3] = {1, jx, jx * jy};
     const int pb = off[tile * t.tcells];
-    const int pe = off[(tile + 1) * t.tcells];
+    const int n = off[(tile + 1) * t.tcells] - pb;
     int errs = 0;
-    for (int p = pb + threadIdx.x; p < pe; p += NT) {
-        const int cell = s.cell[p];
+    // software pipeline: the next particle's SoA loads are issued before the
+    // current particle is processed
+    int pn = pb + (int)threadIdx.x, celln = -1;
+    float oxn = 0.f, oyn = 0.f, ozn = 0.f, uxn = 0.f, uyn = 0.f, uzn = 0.f, wn = 0.f;
+    if ((int)threadIdx.x < n) {
+        celln = s.cell[pn];
+        oxn = s.off[0][pn], oyn = s.off[1][pn], ozn = s.off[2][pn];
+        uxn = s.u[0][pn], uyn = s.u[1][pn], uzn = s.u[2][pn];
+        wn = s.w[pn];
+    }
+    for (int q = threadIdx.x; q < n; q += NT) {
+        const int p = pn;
+        const int cell = celln;
+        float o[3] = {oxn, oyn, ozn};
+        float u[3] = {uxn, uyn, uzn};
+        const float wq = s.mq * wn;
+        if (q + NT < n) {
+            pn = p + NT;
+            celln = s.cell[pn];
+            oxn = s.off[0][pn], oyn = s.off[1][pn], ozn = s.off[2][pn];
+            uxn = s.u[0][pn], uyn = s.u[1][pn], uzn = s.u[2][pn];
+            wn = s.w[pn];
+        }
         if ((unsigned)cell >= (unsigned)g.ncell) continue;
         int c[3];
         decompose(g, cell, c);
@@ -163,10 +184,7 @@ __global__ void __launch_bounds__(NT) k_pic_tile(Geom g, TileGeom t, int guard, 
             errs |= push_deposit_global(g, f, s, p, c, acc);
             continue;
         }
-        float o[3] = {s.off[0][p], s.off[1][p], s.off[2][p]};
         const float o0[3] = {o[0], o[1], o[2]};
-        float u[3] = {s.u[0][p], s.u[1][p], s.u[2][p]};
-        const float wq = s.mq * s.w[p];
         GatherStencil st;
         gather_stencil(o, st);
         float E[3], B[3];
@@ -255,8 +273,8 @@ size_t tile_lds_bytes(const TileGeom& t, int guard) {
 
 template <int NT>
 static hipError_t launch_tile_nt(const Geom& g, const TileGeom& t, int guard, const FieldPtrs& f,
-                                 const SpeciesDev& s, const int* off, unsigned long long* acc, int* d_err,
-                                 hipStream_t st) {
+                                 const SpeciesDev& s, const int* off, unsigned long long* acc,
+                                 int* d_err, hipStream_t st) {
     const size_t lds = tile_lds_bytes(t, guard);
     const int nb = ((t.ntiles + 7) / 8) * 8;
     hipError_t e = hipFuncSetAttribute((const void*)k_pic_tile<NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -267,7 +285,8 @@ static hipError_t launch_tile_nt(const Geom& g, const TileGeom& t, int guard, co
 }
 
 hipError_t launch_pic_tile(const Geom& g, const TileGeom& t, int guard, int threads, const FieldPtrs& f,
-                           const SpeciesDev& s, const int* off, unsigned long long* acc, int* d_err, hipStream_t st) {
+                           const SpeciesDev& s, const int* off, unsigned long long* acc,
+                           int* d_err, hipStream_t st) {
     switch (threads) {
         case 256: return launch_tile_nt<256>(g, t, guard, f, s, off, acc, d_err, st);
         case 1024: return launch_tile_nt<1024>(g, t, guard, f, s, off, acc, d_err, st);

@@ -67,8 +67,16 @@ class PlasmaDesc(ctypes.Structure):
                 ("ppc", ctypes.c_int32 * 3), ("pad_", ctypes.c_int32)]
 
 
+class Profile(ctypes.Structure):
+    _fields_ = [("sort_ms", ctypes.c_double), ("tile_ms", ctypes.c_double), ("loose_ms", ctypes.c_double),
+                ("jpost_ms", ctypes.c_double), ("field_ms", ctypes.c_double), ("window_ms", ctypes.c_double),
+                ("steps", ctypes.c_int64), ("sorts", ctypes.c_int64), ("tile_launches", ctypes.c_int64)]
+
+
 # every symbol the header declares, with its ctypes signature
 _SIGS = {
+    "pic_profile_enable": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "pic_profile_read": (ctypes.c_int, [_vp, ctypes.POINTER(Profile)]),
     "pic_set_laser": (ctypes.c_int, [_vp, ctypes.POINTER(LaserDesc)]),
     "pic_set_plasma": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(PlasmaDesc)]),
     "pic_inject_plasma": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
@@ -272,6 +280,14 @@ class Simulation:
         """E, B, J as numpy arrays rolled so that x index 0 is the window's trailing cell."""
         _, org = self.window_state()
         return tuple(np.roll(t.cpu().numpy(), -org, axis=3) for t in (self.E, self.B, self.J))
+
+    def profile_enable(self, on=True):
+        self._check(lib().pic_profile_enable(self.handle, 1 if on else 0))
+
+    def profile_read(self):
+        p = Profile()
+        self._check(lib().pic_profile_read(self.handle, ctypes.byref(p)))
+        return {k: getattr(p, k) for k, _ in Profile._fields_}
 
     # ------------------------------------------------------------ the cycle
     def gather_push(self, s=0):
