@@ -185,8 +185,11 @@ def main():
                         "FWHM 2.5 laser from the x boundary, window at c, 1000-step run".format(*cfg["n"]),
             "particles": int(npart),
             "cells": ncell,
-            "sort_interval": sim.desc.sort_interval or 2,
-            "tile": [sim.desc.tile[a] or 8 for a in range(3)],
+            "tiling": {"tile": [sim.desc.tile[a] or 8 for a in range(3)],
+                       "guard": sim.desc.guard if sim.desc.guard >= 0 else 1,
+                       "threads": sim.desc.threads or 512, "interleave": sim.desc.interleave or 8,
+                       "sort_interval": sim.desc.sort_interval or 2,
+                       "source": "explicit" if tiling else "autotune cache or library default"},
         },
         "gather_push_deposit_particle_steps_per_s": npart * launches / (prof["tile_ms"] * 1e-3),
         "phase_ms_per_step": {k[:-3]: prof[k] / max(1, prof["steps"]) for k in

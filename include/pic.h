@@ -284,6 +284,20 @@ pic_status pic_set_window(pic_ctx *ctx, int64_t start_step);
  * (host outputs). */
 pic_status pic_window_state(pic_ctx *ctx, int64_t *shift, int32_t *origin);
 
+/* Change the fused step's tiling on a live context (same meaning and
+ * defaults as the pic_grid_desc fields; the LDS footprint must fit).  Every
+ * species is re-sorted at its next pic_step.  Results do not depend on the
+ * tiling (bit for bit).  Used by the autotuner. */
+typedef struct {
+    int32_t tile[3];
+    int32_t guard;
+    int32_t threads;
+    int32_t interleave;
+    int32_t sort_interval;
+} pic_tiling;
+
+pic_status pic_set_tiling(pic_ctx *ctx, const pic_tiling *tiling);
+
 /* Start (enable != 0) or stop timing the phases of pic_step; starting
  * clears the accumulated times.  Creates HIP events on first use (host
  * runtime objects, no device memory). */

@@ -66,10 +66,42 @@ struct Small {
     int pad1;
 };
 
+// Largest sort key space of any tiling with tiles of at most kMaxTile cells
+// per axis (ragged last tiles pad the key space up to a whole tile).
+constexpr int kMaxTile = 16;
+
+int64_t max_keys(const pic_grid_desc* d) {
+    int64_t k = 1;
+    for (int a = 0; a < 3; ++a) k *= (int64_t)d->n[a] + kMaxTile - 1;
+    return k;
+}
+
+// nullptr if the tiling is acceptable for a grid of n cells, else the reason.
+const char* validate_tiling(const int32_t n[3], const int32_t tile[3], int32_t guard, int32_t threads,
+                            int32_t interleave, int32_t sort_interval) {
+    for (int a = 0; a < 3; ++a) {
+        if (tile[a] < 0 || (tile[a] > 0 && tile[a] > n[a])) return "tile larger than the grid";
+        if (tile[a] > kMaxTile) return "tile above 16 cells per axis";
+    }
+    if (sort_interval < 0) return "negative sort interval";
+    if (guard > 3) return "tile guard above 3 cells";
+    if (threads != 0 && threads != 256 && threads != 512 && threads != 1024)
+        return "threads per tile must be 256, 512 or 1024";
+    if (interleave < 0) return "negative interleave";
+    pic_grid_desc tmp{};
+    for (int a = 0; a < 3; ++a) {
+        tmp.n[a] = n[a];
+        tmp.tile[a] = tile[a];
+    }
+    tmp.guard = guard;
+    const Tiling tl = tiling_of(&tmp);
+    if (tile_lds_bytes(tl.t, tl.guard) > kMaxLds) return "tile and guard exceed the 160 KiB of LDS";
+    return nullptr;
+}
+
 Layout layout(const pic_grid_desc* d, int64_t maxp) {
     const int64_t ncell = (int64_t)d->n[0] * d->n[1] * d->n[2];
-    const Tiling tl = tiling_of(d);
-    const int64_t nkeys = (int64_t)tl.t.ntiles * tl.t.tcells;
+    const int64_t nkeys = max_keys(d);
     Layout L;
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -91,7 +123,7 @@ Layout layout(const pic_grid_desc* d, int64_t maxp) {
     L.sort_rank = take((size_t)maxp * 4);
     L.hist = take(((size_t)nkeys + 1) * 4);
     L.sums = take((((size_t)nkeys + 1 + 1023) / 1024 + 1) * 4);
-    L.stride = take((size_t)tl.t.ntiles * 4);
+    L.stride = take(0);
     L.total = o;
     return L;
 }
@@ -187,16 +219,9 @@ pic_status validate(const pic_grid_desc* d, char* msg, size_t len) {
     if (d->bc_x != PIC_BC_PERIODIC && d->bc_x != PIC_BC_MOVING_WINDOW) return bad("unknown x boundary");
     if (d->jpost < PIC_JPOST_NONE || d->jpost > PIC_JPOST_DENOISER) return bad("unknown current post-processing");
     if (d->pd_variant < 0 || d->pd_variant > 1) return bad("unknown perfect-dispersion variant");
-    for (int a = 0; a < 3; ++a)
-        if (d->tile[a] < 0 || (d->tile[a] > 0 && d->tile[a] > d->n[a])) return bad("tile larger than the grid");
-    if (d->sort_interval < 0) return bad("negative sort interval");
-    if (d->guard > 3) return bad("tile guard above 3 cells");
-    if (d->threads != 0 && d->threads != 256 && d->threads != 512 && d->threads != 1024)
-        return bad("threads per tile must be 256, 512 or 1024");
-    if (d->interleave < 0) return bad("negative interleave");
-    const Tiling tl = tiling_of(d);
-    if ((int64_t)tl.t.ntiles * tl.t.tcells >= (1ll << 31)) return bad("tile key space exceeds 2^31");
-    if (tile_lds_bytes(tl.t, tl.guard) > kMaxLds) return bad("tile and guard exceed the 160 KiB of LDS");
+    if (max_keys(d) >= (1ll << 31)) return bad("tile key space exceeds 2^31");
+    const char* why = validate_tiling(d->n, d->tile, d->guard, d->threads, d->interleave, d->sort_interval);
+    if (why) return bad(why);
     if (d->solver == PIC_SOLVER_YEE) {
         double s = 0.0;
         for (int a = 0; a < 3; ++a) s += 1.0 / (d->d[a] * d->d[a]);
@@ -770,6 +795,20 @@ pic_status pic_window_state(pic_ctx* c, int64_t* shift, int32_t* origin) {
     if (!c) return PIC_EINVAL;
     if (shift) *shift = c->shift;
     if (origin) *origin = c->g.origin;
+    return PIC_OK;
+}
+
+pic_status pic_set_tiling(pic_ctx* c, const pic_tiling* t) {
+    if (!c || !t) return PIC_EINVAL;
+    const char* why = validate_tiling(c->desc.n, t->tile, t->guard, t->threads, t->interleave, t->sort_interval);
+    if (why) return fail(c, PIC_EINVAL, "%s", why);
+    for (int a = 0; a < 3; ++a) c->desc.tile[a] = t->tile[a];
+    c->desc.guard = t->guard;
+    c->desc.threads = t->threads;
+    c->desc.interleave = t->interleave;
+    c->desc.sort_interval = t->sort_interval;
+    c->tl = tiling_of(&c->desc);
+    for (auto& sp : c->sp) sp.sorted = false;
     return PIC_OK;
 }
 

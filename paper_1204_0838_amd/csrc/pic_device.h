@@ -65,16 +65,17 @@ struct PrevDev {
 // device error flags (bit set)
 enum { ERR_CFL = 1, ERR_NONFINITE = 2, ERR_OVERFLOW = 4 };
 
-// round(x * 2^20) as int64, round-half-even, for |x| < 2^31 (x is a current
-// contribution already scaled by 2^20, so the result is round(v * 2^40)).
-// Split exactly: h = rint(x) (|x - h| <= 1/2, so x - h is exact), x 2^20 =
-// h 2^20 + (x - h) 2^20 with only the last term rounded.  About ten VALU
-// instructions instead of a general float -> int64 conversion.
-__device__ __forceinline__ long long to_fix20(float x) {
-    const float h = rintf(x);
-    const int hi = (int)h;
-    const int lo = (int)rintf((x - h) * 0x1p20f);
-    return ((long long)hi << 20) + (long long)lo;
+// round(x) as int64, round-half-even, for |x| < 2^51 (x is a current
+// contribution already scaled by 2^40, so the result is round(v * 2^40)).
+// Adding the exact double of x to M = 1.5 * 2^52, where doubles are spaced
+// exactly 1 apart, rounds once, half to even, to an integer; that integer is
+// the difference of the bit patterns of the sum and of M (same exponent while
+// |x| < 2^51).  Three VALU instructions instead of a general float -> int64
+// conversion.
+__device__ __forceinline__ long long to_fix(float x) {
+    const double M = 0x1.8p52;
+    const double d = (double)x + M;
+    return __double_as_longlong(d) - __double_as_longlong(M);
 }
 
 __device__ __forceinline__ int wrapi(int i, int n) {

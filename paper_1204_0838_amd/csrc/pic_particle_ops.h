@@ -81,7 +81,7 @@ __device__ __forceinline__ bool moved(const int c0[3], const int c1[3], const fl
 // with P_x the running sum of dS_x along x and M = S0 + dS/2 (this product form
 // equals dS_x (S0y S0z + dSy S0z/2 + S0y dSz/2 + dSy dSz/3) summed along x).
 // Emit::add(comp, jx, jy, jz, value) receives each contribution scaled by
-// 2^20 (exact), (jx, jy, jz) being union-node indices 0..4 along x, y, z.
+// 2^40 (exact), (jx, jy, jz) being union-node indices 0..4 along x, y, z.
 // Callers skip particles that did not move (every contribution is zero).
 template <class Emit>
 __device__ __forceinline__ void esirkepov(const Axis5 A[3], float qw, Emit& em) {
@@ -106,7 +106,7 @@ __device__ __forceinline__ void esirkepov(const Axis5 A[3], float qw, Emit& em) 
             for (int b = 0; b < 5; ++b) {
                 if (b >= lb) continue;
                 const float Y = fmaf(A[t1].dS[b] * A[t2].dS[cc], 1.0f / 12.0f, M[t1][b] * M[t2][cc]);
-                const float qy = (qw * Y) * 0x1p20f;
+                const float qy = (qw * Y) * 0x1p40f;
 #pragma unroll
                 for (int a = 0; a < 4; ++a) {
                     if (a >= la) continue;

@@ -27,7 +27,7 @@ struct LdsEmit {
     int jr;
     int X[5], Y[5], Z[5];
     __device__ __forceinline__ void add(int comp, int jx, int jy, int jz, float v) const {
-        atomicAdd(J + (comp * jr + X[jx] + Y[jy] + Z[jz]), (unsigned long long)to_fix20(v));
+        atomicAdd(J + (comp * jr + X[jx] + Y[jy] + Z[jz]), (unsigned long long)to_fix(v));
     }
 };
 
@@ -36,7 +36,7 @@ struct GlobalEmitT {
     int ncell;
     int X[5], Y[5], Z[5];
     __device__ __forceinline__ void add(int comp, int jx, int jy, int jz, float v) const {
-        atomicAdd(acc + ((size_t)comp * ncell + X[jx] + Y[jy] + Z[jz]), (unsigned long long)to_fix20(v));
+        atomicAdd(acc + ((size_t)comp * ncell + X[jx] + Y[jy] + Z[jz]), (unsigned long long)to_fix(v));
     }
 };
 

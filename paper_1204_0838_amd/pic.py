@@ -73,8 +73,14 @@ class Profile(ctypes.Structure):
                 ("steps", ctypes.c_int64), ("sorts", ctypes.c_int64), ("tile_launches", ctypes.c_int64)]
 
 
+class Tiling(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32 * 3), ("guard", ctypes.c_int32), ("threads", ctypes.c_int32),
+                ("interleave", ctypes.c_int32), ("sort_interval", ctypes.c_int32)]
+
+
 # every symbol the header declares, with its ctypes signature
 _SIGS = {
+    "pic_set_tiling": (ctypes.c_int, [_vp, ctypes.POINTER(Tiling)]),
     "pic_profile_enable": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "pic_profile_read": (ctypes.c_int, [_vp, ctypes.POINTER(Profile)]),
     "pic_set_laser": (ctypes.c_int, [_vp, ctypes.POINTER(LaserDesc)]),
@@ -280,6 +286,14 @@ class Simulation:
         """E, B, J as numpy arrays rolled so that x index 0 is the window's trailing cell."""
         _, org = self.window_state()
         return tuple(np.roll(t.cpu().numpy(), -org, axis=3) for t in (self.E, self.B, self.J))
+
+    def set_tiling(self, tile=(0, 0, 0), guard=-1, threads=0, interleave=0, sort_interval=0):
+        t = Tiling()
+        for a in range(3):
+            t.tile[a] = int(tile[a])
+        t.guard, t.threads, t.interleave, t.sort_interval = int(guard), int(threads), int(interleave), \
+            int(sort_interval)
+        self._check(lib().pic_set_tiling(self.handle, ctypes.byref(t)))
 
     def profile_enable(self, on=True):
         self._check(lib().pic_profile_enable(self.handle, 1 if on else 0))

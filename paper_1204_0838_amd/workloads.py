@@ -54,10 +54,15 @@ def initial_particles(cfg: dict) -> int:
     return cells_x * ny * nz * ppc
 
 
-def build(cfg: dict, capacity_factor: float = 1.05, device="cuda:0", **tiling):
-    """A Simulation holding the workload at t = 0 (plasma loaded, laser and window set)."""
-    from . import pic
+def build(cfg: dict, capacity_factor: float = 1.05, device="cuda:0", tuned: bool = True, **tiling):
+    """A Simulation holding the workload at t = 0 (plasma loaded, laser and window set).
 
+    Tiling: explicit keyword arguments, else the autotuner's cached choice
+    for this shape (when `tuned`), else the library defaults."""
+    from . import autotune, pic
+
+    if not tiling and tuned:
+        tiling = autotune.load(cfg) or {}
     nx, ny, nz = cfg["n"]
     p = cfg["plasma"]
     ppc = p["ppc"][0] * p["ppc"][1] * p["ppc"][2]

@@ -70,6 +70,25 @@ def test_fused_step_equals_split_bit_exact_pd_larger():
     _assert_same(a, b)
 
 
+def test_retiling_a_live_run_does_not_change_results():
+    """pic_set_tiling between steps (what the autotuner does) keeps bit-exactness."""
+    grid = inputs.Grid(n=(32, 16, 16), d=(0.25, 0.5, 0.5), dt=0.25, solver="pd")
+    pl = inputs.uniform_random_plasma(grid, ppc=8, seed=45, temperature_ev=80000.0, ux_amp=0.2)
+    a, b = _pair(grid, pl)
+    tilings = [dict(tile=(8, 8, 8), guard=1, threads=512, interleave=8, sort_interval=2),
+               dict(tile=(8, 4, 4), guard=2, threads=1024, interleave=4, sort_interval=3),
+               dict(tile=(16, 4, 4), guard=0, threads=256, interleave=1, sort_interval=1),
+               dict(tile=(4, 4, 4), guard=1, threads=512, interleave=16, sort_interval=4)]
+    for t in tilings:
+        a.set_tiling(**t)
+        a.step(2)
+    for _ in range(2 * len(tilings)):
+        b.gather_push(0)
+        b.deposit(0)
+        b.field_step()
+    _assert_same(a, b)
+
+
 def test_sort_groups_particles_by_tile_and_keeps_them():
     grid = inputs.Grid(n=(24, 16, 12), d=(0.25, 0.5, 0.5), dt=0.25, solver="pd")
     pl = inputs.uniform_random_plasma(grid, ppc=4, seed=44)
