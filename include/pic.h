@@ -86,7 +86,8 @@ enum { PIC_JPOST_NONE = 0, PIC_JPOST_BINOMIAL = 1, PIC_JPOST_DENOISER = 2 };
  *                1 = corner weights zero.
  *   bc_x         PIC_BC_PERIODIC or PIC_BC_MOVING_WINDOW.
  *   jpost        current post-processing before the field update.
- *   tile[3]      cells per particle tile of the fused step (0 = default 8).
+ *   tile[3]      cells per particle tile of the fused step, 3..16 per axis
+ *                (0 = default 8; clamped to the grid).
  *   sort_interval steps between cell sorts in pic_step (0 = default 2).
  *   guard        cells a particle may drift out of its tile and still be
  *                handled in LDS (0..3; a negative value selects the
@@ -312,6 +313,60 @@ const char *pic_last_error(const pic_ctx *ctx);
 
 /* Release the context (host memory only; caller buffers are untouched). */
 void pic_destroy(pic_ctx *ctx);
+
+/* ---- Batched launcher --------------------------------------------------
+ *
+ * A batch advances many independent simulations (members: contexts made
+ * with pic_init_grid / pic_init_species / pic_set_*) in lockstep with one
+ * kernel launch per phase for all of them: the fused tile step's work list
+ * is the concatenation of every member's tiles, and each cell, plane or
+ * particle kernel indexes members by its grid's second dimension.  A member
+ * reaches exactly (bit for bit) the state that its own pic_step would reach;
+ * sort, window, laser and injection schedules stay per member.  This serves
+ * parameter scans, the optimisation of accelerator parameters through many
+ * simulations that Sections 1 and 3.3 point to: many uneven laser-wakefield
+ * setups, none large enough alone to fill the GPU.  The batching itself is
+ * this library's design, not the paper's.
+ *
+ * Per step the host writes a table of member descriptors into a slot of the
+ * batch workspace (a ring of slots, so no step waits for the previous one)
+ * through a small pinned host staging ring that the batch allocates with
+ * hipHostMalloc and frees in pic_batch_destroy.
+ */
+typedef struct pic_batch pic_batch;
+
+/* Device workspace a batch of n members needs (0 if n < 1). */
+size_t pic_batch_workspace_bytes(int32_t n_members);
+
+/* members: host array of n context pointers (distinct, each with the same
+ * number of species >= 1, all created on `stream`).  The contexts stay owned
+ * by the caller and must outlive the batch; between batch calls they may be
+ * used directly (pic_reduce, pic_species_view, ...) on the same stream.
+ * workspace: device buffer of pic_batch_workspace_bytes(n), 256-byte aligned,
+ * owned by the caller.  The tile step runs with the first member's threads
+ * per tile.  Synchronises the stream once. */
+pic_status pic_batch_create(pic_batch **out, pic_ctx *const *members, int32_t n, void *workspace,
+                            size_t workspace_bytes, void *stream);
+
+/* nsteps production steps of every member (each equal to pic_step(member, 1)
+ * per step).  Asynchronous, except for a host wait when the staging ring is
+ * full or a member's plasma injection needs an exact particle count. */
+pic_status pic_batch_step(pic_batch *batch, int32_t nsteps);
+
+/* Wait for queued work; report the first member's device-side error. */
+pic_status pic_batch_sync(pic_batch *batch);
+
+/* Phase timing of pic_batch_step, as pic_profile_enable / pic_profile_read
+ * (tile_launches counts batched tile launches). */
+pic_status pic_batch_profile_enable(pic_batch *batch, int32_t enable);
+pic_status pic_batch_profile_read(pic_batch *batch, pic_profile *out);
+
+/* Text of the batch's sticky error (never NULL). */
+const char *pic_batch_last_error(const pic_batch *batch);
+
+/* Release the batch (its pinned staging ring and events; members and
+ * buffers are untouched).  Synchronises the stream. */
+void pic_batch_destroy(pic_batch *batch);
 
 #ifdef __cplusplus
 }

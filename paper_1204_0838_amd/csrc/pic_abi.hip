@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -50,7 +51,7 @@ Tiling tiling_of(const pic_grid_desc* d) {
 // species take consecutive sub-ranges of them.
 struct Layout {
     size_t acc, jtmp, rho, small, prev_cell, prev_off, alt_cell, alt_off, alt_u, alt_w, alt_id, sort_rank, hist,
-        sums, stride, total;
+        sums, toff, toff_stride, total;
 };
 
 // small block: err flags, per-species counts, reduction results
@@ -69,10 +70,19 @@ struct Small {
 // Largest sort key space of any tiling with tiles of at most kMaxTile cells
 // per axis (ragged last tiles pad the key space up to a whole tile).
 constexpr int kMaxTile = 16;
+// Smallest tile edge (keeps the per-species tile ranges small).
+constexpr int kMinTile = 3;
 
 int64_t max_keys(const pic_grid_desc* d) {
     int64_t k = 1;
     for (int a = 0; a < 3; ++a) k *= (int64_t)d->n[a] + kMaxTile - 1;
+    return k;
+}
+
+// Most tiles any accepted tiling can have.
+int64_t max_tiles(const pic_grid_desc* d) {
+    int64_t k = 1;
+    for (int a = 0; a < 3; ++a) k *= ((int64_t)d->n[a] + kMinTile - 1) / kMinTile;
     return k;
 }
 
@@ -82,6 +92,7 @@ const char* validate_tiling(const int32_t n[3], const int32_t tile[3], int32_t g
     for (int a = 0; a < 3; ++a) {
         if (tile[a] < 0 || (tile[a] > 0 && tile[a] > n[a])) return "tile larger than the grid";
         if (tile[a] > kMaxTile) return "tile above 16 cells per axis";
+        if (tile[a] > 0 && tile[a] < kMinTile) return "tile below 3 cells per axis";
     }
     if (sort_interval < 0) return "negative sort interval";
     if (guard > 3) return "tile guard above 3 cells";
@@ -123,7 +134,8 @@ Layout layout(const pic_grid_desc* d, int64_t maxp) {
     L.sort_rank = take((size_t)maxp * 4);
     L.hist = take(((size_t)nkeys + 1) * 4);
     L.sums = take((((size_t)nkeys + 1 + 1023) / 1024 + 1) * 4);
-    L.stride = take(0);
+    L.toff_stride = align_up(((size_t)max_tiles(d) + 1) * 4);
+    L.toff = take(kMaxSpecies * L.toff_stride);
     L.total = o;
     return L;
 }
@@ -138,6 +150,77 @@ struct Species {
     int64_t sort_step;       // step of the last sort
     bool sorted;             // tile ranges valid
     bool prev_valid;         // x^n of the last split gather_push kept
+};
+
+// Phase timing: an event recorded before and after each timed phase.
+enum { PH_SORT, PH_TILE, PH_LOOSE, PH_JPOST, PH_FIELD, PH_WINDOW, PH_COUNT };
+
+struct Prof {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    struct Mark {
+        int phase;
+        hipEvent_t a, b;
+    };
+    std::vector<Mark> marks;
+    int64_t steps = 0, sorts = 0, tiles = 0;
+    ~Prof() {
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    }
+    // record an event (nullptr when timing is off)
+    hipError_t mark(hipStream_t st, hipEvent_t* ev) {
+        *ev = nullptr;
+        if (!on) return hipSuccess;
+        if (used == pool.size()) {
+            hipEvent_t e;
+            hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) return r;
+            pool.push_back(e);
+        }
+        *ev = pool[used++];
+        return hipEventRecord(*ev, st);
+    }
+    hipError_t end(hipStream_t st, int phase, hipEvent_t start) {
+        if (!on || !start) return hipSuccess;
+        hipEvent_t e;
+        hipError_t r = mark(st, &e);
+        if (r != hipSuccess) return r;
+        marks.push_back({phase, start, e});
+        return hipSuccess;
+    }
+    hipError_t enable(hipStream_t st, bool en) {
+        if (en) {
+            hipError_t r = hipStreamSynchronize(st);
+            if (r != hipSuccess) return r;
+            marks.clear();
+            used = 0;
+            steps = sorts = tiles = 0;
+        }
+        on = en;
+        return hipSuccess;
+    }
+    hipError_t read(hipStream_t st, pic_profile* out) {
+        hipError_t r = hipStreamSynchronize(st);
+        if (r != hipSuccess) return r;
+        double ms[PH_COUNT] = {0, 0, 0, 0, 0, 0};
+        for (const auto& m : marks) {
+            float t = 0.0f;
+            r = hipEventElapsedTime(&t, m.a, m.b);
+            if (r != hipSuccess) return r;
+            ms[m.phase] += t;
+        }
+        out->sort_ms = ms[PH_SORT];
+        out->tile_ms = ms[PH_TILE];
+        out->loose_ms = ms[PH_LOOSE];
+        out->jpost_ms = ms[PH_JPOST];
+        out->field_ms = ms[PH_FIELD];
+        out->window_ms = ms[PH_WINDOW];
+        out->steps = steps;
+        out->sorts = sorts;
+        out->tile_launches = tiles;
+        return hipSuccess;
+    }
 };
 
 }  // namespace
@@ -165,18 +248,7 @@ struct pic_ctx {
     bool has_plasma[kMaxSpecies] = {};
     PlasmaDev plasma[kMaxSpecies];
     // phase timing (pic_profile_*)
-    bool prof_on = false;
-    std::vector<hipEvent_t> ev_pool;
-    size_t ev_used = 0;
-    struct Mark {
-        int phase;
-        hipEvent_t a, b;
-    };
-    std::vector<Mark> marks;
-    int64_t prof_steps = 0, prof_sorts = 0, prof_tiles = 0;
-    ~pic_ctx() {
-        for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
-    }
+    Prof prof;
 };
 
 namespace {
@@ -300,6 +372,7 @@ FieldPtrs fields_of(pic_ctx* c) {
 
 unsigned long long* acc_of(pic_ctx* c) { return reinterpret_cast<unsigned long long*>(c->ws + c->L.acc); }
 int* hist_of(pic_ctx* c) { return reinterpret_cast<int*>(c->ws + c->L.hist); }
+int* toff_of(pic_ctx* c, int32_t s) { return reinterpret_cast<int*>(c->ws + c->L.toff + (size_t)s * c->L.toff_stride); }
 
 void jtmp_of(pic_ctx* c, float* out[3]) {
     for (int a = 0; a < 3; ++a) out[a] = reinterpret_cast<float*>(c->ws + c->L.jtmp) + (size_t)a * c->g.ncell;
@@ -398,34 +471,20 @@ pic_status inject_slab(pic_ctx* c, int32_t s, int32_t xb, int32_t xe) {
     return PIC_OK;
 }
 
-// Phase timing: an event recorded before and after each timed phase.
-enum { PH_SORT, PH_TILE, PH_LOOSE, PH_JPOST, PH_FIELD, PH_WINDOW, PH_COUNT };
-
 pic_status prof_mark(pic_ctx* c, hipEvent_t* ev) {
-    *ev = nullptr;
-    if (!c->prof_on) return PIC_OK;
-    if (c->ev_used == c->ev_pool.size()) {
-        hipEvent_t e;
-        HIPCHK(c, hipEventCreate(&e));
-        c->ev_pool.push_back(e);
-    }
-    *ev = c->ev_pool[c->ev_used++];
-    HIPCHK(c, hipEventRecord(*ev, c->stream));
+    HIPCHK(c, c->prof.mark(c->stream, ev));
     return PIC_OK;
 }
 
 pic_status prof_end(pic_ctx* c, int phase, hipEvent_t start) {
-    if (!c->prof_on || !start) return PIC_OK;
-    hipEvent_t e;
-    PICCHK(prof_mark(c, &e));
-    c->marks.push_back({phase, start, e});
+    HIPCHK(c, c->prof.end(c->stream, phase, start));
     return PIC_OK;
 }
 
 // End of a step: count it; move the window one cell when it is due.
 pic_status end_step(pic_ctx* c) {
     c->step += 1;
-    if (c->prof_on) c->prof_steps += 1;
+    if (c->prof.on) c->prof.steps += 1;
     if (!c->g.window || c->step < c->window_start) return PIC_OK;
     hipEvent_t t0;
     PICCHK(prof_mark(c, &t0));
@@ -444,7 +503,7 @@ pic_status sort_species(pic_ctx* c, int32_t s) {
     int* rank = reinterpret_cast<int*>(c->ws + c->L.sort_rank) + sp.base;
     HIPCHK(c, launch_sort(c->g, c->tl.t, dev_from(c, sp, sp.cur), dev_from(c, sp, sp.alt), &sm->count[s],
                           &sm->sorted[s], (int)sp.bound, hist_of(c), rank, reinterpret_cast<int*>(c->ws + c->L.sums),
-                          c->tl.interleave, c->stream));
+                          c->tl.interleave, toff_of(c, s), c->stream));
     std::swap(sp.cur, sp.alt);
     sp.sorted = true;
     sp.sort_step = c->step;
@@ -475,6 +534,281 @@ pic_status finish_step(pic_ctx* c) {
     PICCHK(field_update(c, Juse));
     PICCHK(prof_end(c, PH_FIELD, t1));
     return end_step(c);
+}
+
+}  // namespace
+
+// ---- batched launcher ------------------------------------------------------
+
+struct pic_batch {
+    std::vector<pic_ctx*> m;
+    int nsp = 0;
+    hipStream_t stream = nullptr;
+    char* ws = nullptr;
+    size_t tab_bytes = 0;    // member table of one slot
+    size_t slot_bytes = 0;   // table + flat tile offsets
+    char* host = nullptr;    // pinned staging ring (nslots slots)
+    std::vector<hipEvent_t> ev;
+    std::vector<bool> used;
+    int next = 0;
+    std::string err;
+    Prof prof;
+    ~pic_batch() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        if (host) (void)hipHostFree(host);
+    }
+};
+
+namespace {
+
+constexpr int kBatchSlots = 16;
+
+size_t batch_tab_bytes(int32_t n) { return align_up((size_t)n * sizeof(InstDesc)); }
+size_t batch_slot_bytes(int32_t n) { return batch_tab_bytes(n) + align_up(((size_t)n + 1) * sizeof(int)); }
+
+pic_status bfail(pic_batch* b, pic_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    b->err = buf;
+    return st;
+}
+
+#define BHIPCHK(b, expr)                                                                             \
+    do {                                                                                             \
+        hipError_t e_ = (expr);                                                                      \
+        if (e_ != hipSuccess) return bfail(b, PIC_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));  \
+    } while (0)
+
+// Member status -> batch error naming the member.
+pic_status bmember(pic_batch* b, int i, pic_status st) {
+    if (st != PIC_OK) bfail(b, st, "member %d: %s", i, b->m[i]->err.c_str());
+    return st;
+}
+
+// Descriptor of member c for species s at the start of its current step.
+void fill_desc(pic_ctx* c, int32_t s, InstDesc& d) {
+    Species& sp = c->sp[s];
+    memset(&d, 0, sizeof d);
+    d.g = c->g;
+    d.t = c->tl.t;
+    d.guard = c->tl.guard;
+    d.pd = c->desc.solver == PIC_SOLVER_PD;
+    d.depth = c->tl.interleave;
+    d.nkeys = c->tl.t.ntiles * c->tl.t.tcells;
+    d.c = c->pd;
+    d.f = fields_of(c);
+    float* jt[3];
+    jtmp_of(c, jt);
+    for (int a = 0; a < 3; ++a) {
+        d.J[a] = c->f.J[a];
+        d.Jt[a] = jt[a];
+    }
+    d.jpost = c->desc.jpost == PIC_JPOST_BINOMIAL;
+    d.sorting = !sp.sorted || c->step - sp.sort_step >= c->tl.sort_interval;
+    d.s = dev_from(c, sp, sp.cur);
+    d.alt = dev_from(c, sp, sp.alt);
+    d.hist = hist_of(c);
+    d.toff = toff_of(c, s);
+    d.rank = reinterpret_cast<int*>(c->ws + c->L.sort_rank) + sp.base;
+    d.sums = reinterpret_cast<int*>(c->ws + c->L.sums);
+    d.acc = acc_of(c);
+    Small* sm = small_of(c);
+    d.err = &sm->err;
+    d.count = &sm->count[s];
+    d.sorted = &sm->sorted[s];
+    d.capacity = (int)sp.user.capacity;
+    d.hdt = (float)(0.5 * c->desc.dt);
+    jscale(c, d.jscale);
+    // laser planes, with the same arithmetic as field_update / laser_plane
+    const double dt = c->desc.dt, t = c->step * dt;
+    d.laser_on = c->has_laser && c->shift == 0 && t <= c->laser.t_end;
+    if (d.laser_on) {
+        const pic_laser_desc& L = c->laser;
+        const double dx = c->desc.d[0];
+        const double h = 0.5 * dt;
+        d.lcoef[0] = h * laser_e(L, t) / dx;
+        d.lcoef[1] = dt * laser_e(L, (t + 0.5 * dt) + 0.5 * dx) / dx;
+        d.lcoef[2] = h * laser_e(L, t + dt) / dx;
+        d.lix_b = L.src_x - 1;
+        d.lix_e = L.src_x;
+        d.yc = L.yc;
+        d.zc = L.zc;
+        d.inv_w2 = 1.0 / (L.waist * L.waist);
+        d.dy = c->desc.d[1];
+        d.dz = c->desc.d[2];
+    }
+    d.wmove = c->g.window && c->step + 1 >= c->window_start;
+    d.inject = d.wmove && c->has_plasma[s];
+    d.slab = c->g.n[0] - 1 - c->g.kill_hi;
+    d.shift = c->shift + (d.wmove ? 1 : 0);
+    if (c->has_plasma[s]) d.plasma = c->plasma[s];
+}
+
+// Stage the member table (and flat tile offsets) of species s into the next
+// ring slot; returns the device addresses.
+pic_status upload_tables(pic_batch* b, int32_t s, InstDesc** dtab, int** dbegin, int* total_tiles) {
+    const int n = (int)b->m.size();
+    const int k = b->next;
+    b->next = (k + 1) % kBatchSlots;
+    if (b->used[k]) BHIPCHK(b, hipEventSynchronize(b->ev[k]));
+    char* h = b->host + (size_t)k * b->slot_bytes;
+    InstDesc* tab = reinterpret_cast<InstDesc*>(h);
+    int* begin = reinterpret_cast<int*>(h + b->tab_bytes);
+    int64_t tot = 0;
+    for (int i = 0; i < n; ++i) {
+        fill_desc(b->m[i], s, tab[i]);
+        begin[i] = (int)tot;
+        tot += b->m[i]->tl.t.ntiles;
+    }
+    if (tot >= (1ll << 31)) return bfail(b, PIC_EINVAL, "more than 2^31 tiles in the batch");
+    begin[n] = (int)tot;
+    char* dslot = b->ws + (size_t)k * b->slot_bytes;
+    BHIPCHK(b, hipMemcpyAsync(dslot, h, b->slot_bytes, hipMemcpyHostToDevice, b->stream));
+    BHIPCHK(b, hipEventRecord(b->ev[k], b->stream));
+    b->used[k] = true;
+    *dtab = reinterpret_cast<InstDesc*>(dslot);
+    *dbegin = reinterpret_cast<int*>(dslot + b->tab_bytes);
+    *total_tiles = (int)tot;
+    return PIC_OK;
+}
+
+pic_status bmark(pic_batch* b, hipEvent_t* e) {
+    BHIPCHK(b, b->prof.mark(b->stream, e));
+    return PIC_OK;
+}
+
+pic_status bend(pic_batch* b, int phase, hipEvent_t e) {
+    BHIPCHK(b, b->prof.end(b->stream, phase, e));
+    return PIC_OK;
+}
+
+// One step of every member: per species sort (members due), tiled step and
+// loose particles; then current read-out, field update with laser planes and
+// window motion with injection.  The host bookkeeping mirrors pic_step.
+pic_status batch_one_step(pic_batch* b) {
+    const int n = (int)b->m.size();
+    InstDesc* dtab = nullptr;
+    int* dbegin = nullptr;
+    for (int32_t s = 0; s < b->nsp; ++s) {
+        int total = 0;
+        PICCHK(upload_tables(b, s, &dtab, &dbegin, &total));
+        int max_sort = 0, max_keys1 = 0, max_tiles1 = 0, max_loose = 0;
+        bool any_sort = false;
+        size_t lds = 0;
+        for (int i = 0; i < n; ++i) {
+            pic_ctx* c = b->m[i];
+            Species& sp = c->sp[s];
+            const bool sorting = !sp.sorted || c->step - sp.sort_step >= c->tl.sort_interval;
+            if (sorting) {
+                any_sort = true;
+                max_sort = (int)std::max<int64_t>(max_sort, sp.bound);
+                max_keys1 = std::max(max_keys1, c->tl.t.ntiles * c->tl.t.tcells + 1);
+                max_tiles1 = std::max(max_tiles1, c->tl.t.ntiles + 1);
+                std::swap(sp.cur, sp.alt);
+                sp.sorted = true;
+                sp.sort_step = c->step;
+                sp.loose = 0;
+            }
+            sp.prev_valid = false;
+            max_loose = (int)std::max<int64_t>(max_loose, sp.loose);
+            lds = std::max(lds, tile_lds_bytes(c->tl.t, c->tl.guard));
+        }
+        hipEvent_t t0, t1, t2;
+        if (any_sort) {
+            PICCHK(bmark(b, &t0));
+            BHIPCHK(b, launch_batch_sort(dtab, n, max_sort, max_keys1, max_tiles1, b->stream));
+            PICCHK(bend(b, PH_SORT, t0));
+            if (b->prof.on) b->prof.sorts += 1;
+        }
+        PICCHK(bmark(b, &t1));
+        BHIPCHK(b, launch_batch_tile(dtab, dbegin, n, total, b->m[0]->tl.threads, lds, b->stream));
+        PICCHK(bend(b, PH_TILE, t1));
+        if (b->prof.on) b->prof.tiles += 1;
+        if (max_loose > 0) {
+            PICCHK(bmark(b, &t2));
+            BHIPCHK(b, launch_batch_loose(dtab, n, max_loose, b->stream));
+            PICCHK(bend(b, PH_LOOSE, t2));
+        }
+        // the window phase below needs each species' table; keep species 0's
+        // for the field phase and re-stage the others then
+    }
+    // current read-out and field update (member-wide parts of the last table)
+    int max_cells = 0, max_plane = 0;
+    bool any_bin = false, any_laser = false, any_move = false;
+    for (int i = 0; i < n; ++i) {
+        pic_ctx* c = b->m[i];
+        max_cells = std::max(max_cells, c->g.ncell);
+        max_plane = std::max(max_plane, c->g.n[1] * c->g.n[2]);
+        any_bin = any_bin || c->desc.jpost == PIC_JPOST_BINOMIAL;
+        const double t = c->step * c->desc.dt;
+        any_laser = any_laser || (c->has_laser && c->shift == 0 && t <= c->laser.t_end);
+        any_move = any_move || (c->g.window && c->step + 1 >= c->window_start);
+    }
+    hipEvent_t t3, t4, t5;
+    PICCHK(bmark(b, &t3));
+    BHIPCHK(b, launch_batch_jfinal(dtab, n, max_cells, b->stream));
+    if (any_bin) BHIPCHK(b, launch_batch_binomial(dtab, n, max_cells, b->stream));
+    PICCHK(bend(b, PH_JPOST, t3));
+    PICCHK(bmark(b, &t4));
+    BHIPCHK(b, launch_batch_bhalf(dtab, n, max_cells, b->stream));
+    if (any_laser) BHIPCHK(b, launch_batch_laser(dtab, n, 0, max_plane, b->stream));
+    BHIPCHK(b, launch_batch_efull(dtab, n, max_cells, b->stream));
+    if (any_laser) BHIPCHK(b, launch_batch_laser(dtab, n, 1, max_plane, b->stream));
+    BHIPCHK(b, launch_batch_bhalf(dtab, n, max_cells, b->stream));
+    if (any_laser) BHIPCHK(b, launch_batch_laser(dtab, n, 2, max_plane, b->stream));
+    PICCHK(bend(b, PH_FIELD, t4));
+    PICCHK(bmark(b, &t5));
+    if (any_move) {
+        BHIPCHK(b, launch_batch_clear(dtab, n, max_plane, b->stream));
+        for (int32_t s = 0; s < b->nsp; ++s) {
+            // capacity bound of the injected slab (exact count only when needed)
+            long long max_cand = 0;
+            bool any = false;
+            for (int i = 0; i < n; ++i) {
+                pic_ctx* c = b->m[i];
+                if (!(c->g.window && c->step + 1 >= c->window_start) || !c->has_plasma[s]) continue;
+                Species& sp = c->sp[s];
+                const PlasmaDev& P = c->plasma[s];
+                const int64_t most = (int64_t)c->g.n[1] * c->g.n[2] * P.ppc[0] * P.ppc[1] * P.ppc[2];
+                if (sp.bound + most > sp.user.capacity) {
+                    PICCHK(bmember(b, i, refresh_bound(c, s)));
+                    if (sp.bound + most > sp.user.capacity)
+                        return bfail(b, PIC_ENOMEM, "member %d species %d: %lld particles plus up to %lld injected exceed capacity %lld",
+                                     i, s, (long long)sp.bound, (long long)most, (long long)sp.user.capacity);
+                }
+                sp.bound += most;
+                sp.loose += most;
+                max_cand = std::max<long long>(max_cand, most);
+                any = true;
+            }
+            if (!any) continue;
+            InstDesc* tab_s = dtab;
+            if (s != b->nsp - 1) {
+                int total = 0;
+                int* dummy = nullptr;
+                // the sort state of species s is already advanced: its arrays
+                // are now `cur` with no sort pending
+                PICCHK(upload_tables(b, s, &tab_s, &dummy, &total));
+            }
+            BHIPCHK(b, launch_batch_inject(tab_s, n, max_cand, b->stream));
+        }
+    }
+    PICCHK(bend(b, PH_WINDOW, t5));
+    // host bookkeeping of the step's end (end_step without the launches)
+    for (int i = 0; i < n; ++i) {
+        pic_ctx* c = b->m[i];
+        const bool move = c->g.window && c->step + 1 >= c->window_start;
+        c->step += 1;
+        if (move) {
+            c->g.origin = c->g.origin + 1 == c->g.n[0] ? 0 : c->g.origin + 1;
+            c->shift += 1;
+        }
+    }
+    if (b->prof.on) b->prof.steps += 1;
+    return PIC_OK;
 }
 
 }  // namespace
@@ -630,14 +964,14 @@ pic_status pic_step(pic_ctx* c, int32_t nsteps) {
                 PICCHK(prof_mark(c, &t0));
                 PICCHK(sort_species(c, s));
                 PICCHK(prof_end(c, PH_SORT, t0));
-                if (c->prof_on) c->prof_sorts += 1;
+                if (c->prof.on) c->prof.sorts += 1;
             }
             Small* sm = small_of(c);
             PICCHK(prof_mark(c, &t1));
             HIPCHK(c, launch_pic_tile(c->g, c->tl.t, c->tl.guard, c->tl.threads, fields_of(c), dev_of(c, sp),
-                                      hist_of(c), acc_of(c), &sm->err, c->stream));
+                                      toff_of(c, s), acc_of(c), &sm->err, c->stream));
             PICCHK(prof_end(c, PH_TILE, t1));
-            if (c->prof_on) c->prof_tiles += 1;
+            if (c->prof.on) c->prof.tiles += 1;
             if (sp.loose > 0) {
                 PICCHK(prof_mark(c, &t2));
                 HIPCHK(c, launch_push_deposit_range(c->g, fields_of(c), dev_of(c, sp), &sm->sorted[s],
@@ -814,34 +1148,13 @@ pic_status pic_set_tiling(pic_ctx* c, const pic_tiling* t) {
 
 pic_status pic_profile_enable(pic_ctx* c, int32_t enable) {
     if (!c) return PIC_EINVAL;
-    if (enable) {
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        c->marks.clear();
-        c->ev_used = 0;
-        c->prof_steps = c->prof_sorts = c->prof_tiles = 0;
-    }
-    c->prof_on = enable != 0;
+    HIPCHK(c, c->prof.enable(c->stream, enable != 0));
     return PIC_OK;
 }
 
 pic_status pic_profile_read(pic_ctx* c, pic_profile* out) {
     if (!c || !out) return PIC_EINVAL;
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    double ms[PH_COUNT] = {0, 0, 0, 0, 0, 0};
-    for (const auto& m : c->marks) {
-        float t = 0.0f;
-        HIPCHK(c, hipEventElapsedTime(&t, m.a, m.b));
-        ms[m.phase] += t;
-    }
-    out->sort_ms = ms[PH_SORT];
-    out->tile_ms = ms[PH_TILE];
-    out->loose_ms = ms[PH_LOOSE];
-    out->jpost_ms = ms[PH_JPOST];
-    out->field_ms = ms[PH_FIELD];
-    out->window_ms = ms[PH_WINDOW];
-    out->steps = c->prof_steps;
-    out->sorts = c->prof_sorts;
-    out->tile_launches = c->prof_tiles;
+    HIPCHK(c, c->prof.read(c->stream, out));
     return PIC_OK;
 }
 
@@ -851,5 +1164,90 @@ const char* pic_last_error(const pic_ctx* c) {
 }
 
 void pic_destroy(pic_ctx* c) { delete c; }
+
+size_t pic_batch_workspace_bytes(int32_t n) {
+    if (n < 1) return 0;
+    return (size_t)kBatchSlots * batch_slot_bytes(n);
+}
+
+pic_status pic_batch_create(pic_batch** out, pic_ctx* const* members, int32_t n, void* workspace,
+                            size_t workspace_bytes, void* stream) {
+    if (!out) return PIC_EINVAL;
+    *out = nullptr;
+    if (!members || n < 1 || !workspace) return PIC_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(workspace) & (kAlign - 1)) != 0) return PIC_EINVAL;
+    if (workspace_bytes < pic_batch_workspace_bytes(n)) return PIC_ENOMEM;
+    const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    for (int32_t i = 0; i < n; ++i) {
+        if (!members[i]) return PIC_EINVAL;
+        if (members[i]->stream != st) return PIC_EINVAL;
+        if (members[i]->sp.empty() || members[i]->sp.size() != members[0]->sp.size()) return PIC_EINVAL;
+        for (int32_t k = 0; k < i; ++k)
+            if (members[k] == members[i]) return PIC_EINVAL;
+    }
+    pic_batch* b = new (std::nothrow) pic_batch();
+    if (!b) return PIC_ENOMEM;
+    b->m.assign(members, members + n);
+    b->nsp = (int)members[0]->sp.size();
+    b->stream = st;
+    b->ws = reinterpret_cast<char*>(workspace);
+    b->tab_bytes = batch_tab_bytes(n);
+    b->slot_bytes = batch_slot_bytes(n);
+    hipError_t e = hipHostMalloc((void**)&b->host, (size_t)kBatchSlots * b->slot_bytes, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        b->host = nullptr;
+        delete b;
+        return PIC_EDEVICE;
+    }
+    b->ev.assign(kBatchSlots, nullptr);
+    b->used.assign(kBatchSlots, false);
+    for (int k = 0; k < kBatchSlots && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&b->ev[k], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        delete b;
+        return PIC_EDEVICE;
+    }
+    *out = b;
+    return PIC_OK;
+}
+
+pic_status pic_batch_step(pic_batch* b, int32_t nsteps) {
+    if (!b || nsteps < 0) return PIC_EINVAL;
+    for (pic_ctx* c : b->m)
+        if (c->desc.jpost == PIC_JPOST_DENOISER)
+            return bfail(b, PIC_EINVAL, "the batch runs the plain and binomial current paths only");
+    for (int32_t it = 0; it < nsteps; ++it) PICCHK(batch_one_step(b));
+    return PIC_OK;
+}
+
+pic_status pic_batch_sync(pic_batch* b) {
+    if (!b) return PIC_EINVAL;
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    for (size_t i = 0; i < b->m.size(); ++i) PICCHK(bmember(b, (int)i, device_errors(b->m[i])));
+    return PIC_OK;
+}
+
+pic_status pic_batch_profile_enable(pic_batch* b, int32_t enable) {
+    if (!b) return PIC_EINVAL;
+    BHIPCHK(b, b->prof.enable(b->stream, enable != 0));
+    return PIC_OK;
+}
+
+pic_status pic_batch_profile_read(pic_batch* b, pic_profile* out) {
+    if (!b || !out) return PIC_EINVAL;
+    BHIPCHK(b, b->prof.read(b->stream, out));
+    return PIC_OK;
+}
+
+const char* pic_batch_last_error(const pic_batch* b) {
+    if (!b) return "null batch";
+    return b->err.c_str();
+}
+
+void pic_batch_destroy(pic_batch* b) {
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    delete b;
+}
 
 }  // extern "C"

@@ -93,12 +93,10 @@ __device__ __forceinline__ float sval(const Geom& g, const PDCoef& c, const floa
 
 // B -= h curl' E with forward differences; curl'_x = D_y S_y E_z - D_z S_z E_y, cyclic.
 template <bool PD>
-__global__ void __launch_bounds__(256) k_bhalf(Geom g, PDCoef c, const float* __restrict__ Ex,
-                                               const float* __restrict__ Ey, const float* __restrict__ Ez,
-                                               float* __restrict__ Bx, float* __restrict__ By,
-                                               float* __restrict__ Bz, float h) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= g.ncell) return;
+__device__ __forceinline__ void bhalf_cell(const Geom& g, const PDCoef& c, const float* __restrict__ Ex,
+                                           const float* __restrict__ Ey, const float* __restrict__ Ez,
+                                           float* __restrict__ Bx, float* __restrict__ By, float* __restrict__ Bz,
+                                           float h, int idx) {
     const Nbr n = neighbours(g, idx);
     // E at the +x neighbour is zero across the window seam
     const float dyEz = (sval<PD, 1>(g, c, Ez, n.i, n.jp, n.k) - sval<PD, 1>(g, c, Ez, n.i, n.j, n.k)) * g.inv_d[1];
@@ -114,14 +112,22 @@ __global__ void __launch_bounds__(256) k_bhalf(Geom g, PDCoef c, const float* __
     Bz[idx] -= h * (dxEy - dyEx);
 }
 
-// E += dt (curl B - J) with backward differences.
-__global__ void __launch_bounds__(256) k_efull(Geom g, float* __restrict__ Ex, float* __restrict__ Ey,
-                                               float* __restrict__ Ez, const float* __restrict__ Bx,
-                                               const float* __restrict__ By, const float* __restrict__ Bz,
-                                               const float* __restrict__ Jx, const float* __restrict__ Jy,
-                                               const float* __restrict__ Jz) {
+template <bool PD>
+__global__ void __launch_bounds__(256) k_bhalf(Geom g, PDCoef c, const float* __restrict__ Ex,
+                                               const float* __restrict__ Ey, const float* __restrict__ Ez,
+                                               float* __restrict__ Bx, float* __restrict__ By,
+                                               float* __restrict__ Bz, float h) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= g.ncell) return;
+    bhalf_cell<PD>(g, c, Ex, Ey, Ez, Bx, By, Bz, h, idx);
+}
+
+// E += dt (curl B - J) with backward differences.
+__device__ __forceinline__ void efull_cell(const Geom& g, float* __restrict__ Ex, float* __restrict__ Ey,
+                                           float* __restrict__ Ez, const float* __restrict__ Bx,
+                                           const float* __restrict__ By, const float* __restrict__ Bz,
+                                           const float* __restrict__ Jx, const float* __restrict__ Jy,
+                                           const float* __restrict__ Jz, int idx) {
     const Nbr n = neighbours(g, idx);
     const float bz = Bz[idx], by = By[idx], bx = Bx[idx];
     const float bzm_x = n.xm_ok ? Bz[at(g, n.im, n.j, n.k)] : 0.0f;
@@ -137,13 +143,22 @@ __global__ void __launch_bounds__(256) k_efull(Geom g, float* __restrict__ Ex, f
     Ez[idx] += g.dt * ((dxBy - dyBx) - Jz[idx]);
 }
 
-// One (1/4, 1/2, 1/4) pass along each axis, as the separable 27-point product
-// stencil, src -> dst (distinct buffers).
-__global__ void __launch_bounds__(256) k_binomial(Geom g, const float* __restrict__ s0, const float* __restrict__ s1,
-                                                  const float* __restrict__ s2, float* __restrict__ d0,
-                                                  float* __restrict__ d1, float* __restrict__ d2) {
+__global__ void __launch_bounds__(256) k_efull(Geom g, float* __restrict__ Ex, float* __restrict__ Ey,
+                                               float* __restrict__ Ez, const float* __restrict__ Bx,
+                                               const float* __restrict__ By, const float* __restrict__ Bz,
+                                               const float* __restrict__ Jx, const float* __restrict__ Jy,
+                                               const float* __restrict__ Jz) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= g.ncell) return;
+    efull_cell(g, Ex, Ey, Ez, Bx, By, Bz, Jx, Jy, Jz, idx);
+}
+
+// One (1/4, 1/2, 1/4) pass along each axis, as the separable 27-point product
+// stencil, src -> dst (distinct buffers).
+__device__ __forceinline__ void binomial_cell(const Geom& g, const float* __restrict__ s0,
+                                              const float* __restrict__ s1, const float* __restrict__ s2,
+                                              float* __restrict__ d0, float* __restrict__ d1,
+                                              float* __restrict__ d2, int idx) {
     const Nbr n = neighbours(g, idx);
     const float wx[3] = {0.25f, 0.5f, 0.25f};
     const int xs[3] = {n.im, n.i, n.ip};
@@ -172,6 +187,43 @@ __global__ void __launch_bounds__(256) k_binomial(Geom g, const float* __restric
     }
 }
 
+__global__ void __launch_bounds__(256) k_binomial(Geom g, const float* __restrict__ s0, const float* __restrict__ s1,
+                                                  const float* __restrict__ s2, float* __restrict__ d0,
+                                                  float* __restrict__ d1, float* __restrict__ d2) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= g.ncell) return;
+    binomial_cell(g, s0, s1, s2, d0, d1, d2, idx);
+}
+
+// Batched field kernels: grid y = member.
+__global__ void __launch_bounds__(256) k_batch_bhalf(const InstDesc* __restrict__ tab) {
+    const InstDesc& d = tab[blockIdx.y];
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= d.g.ncell) return;
+    const Geom g = d.g;
+    const PDCoef c = d.c;
+    if (d.pd)
+        bhalf_cell<true>(g, c, d.f.E[0], d.f.E[1], d.f.E[2], d.f.B[0], d.f.B[1], d.f.B[2], d.hdt, idx);
+    else
+        bhalf_cell<false>(g, c, d.f.E[0], d.f.E[1], d.f.E[2], d.f.B[0], d.f.B[1], d.f.B[2], d.hdt, idx);
+}
+
+__global__ void __launch_bounds__(256) k_batch_efull(const InstDesc* __restrict__ tab) {
+    const InstDesc& d = tab[blockIdx.y];
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= d.g.ncell) return;
+    const Geom g = d.g;
+    efull_cell(g, d.f.E[0], d.f.E[1], d.f.E[2], d.f.B[0], d.f.B[1], d.f.B[2], d.J[0], d.J[1], d.J[2], idx);
+}
+
+__global__ void __launch_bounds__(256) k_batch_binomial(const InstDesc* __restrict__ tab) {
+    const InstDesc& d = tab[blockIdx.y];
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (!d.jpost || idx >= d.g.ncell) return;
+    const Geom g = d.g;
+    binomial_cell(g, d.Jt[0], d.Jt[1], d.Jt[2], d.J[0], d.J[1], d.J[2], idx);
+}
+
 __global__ void k_zero_u64(unsigned long long* p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0ull;
@@ -196,6 +248,24 @@ hipError_t launch_efull(const Geom& g, float* const E[3], float* const B[3], flo
 hipError_t launch_binomial(const Geom& g, float* const src[3], float* const dst[3], hipStream_t st) {
     const int nb = (g.ncell + 255) / 256;
     hipLaunchKernelGGL(k_binomial, dim3(nb), dim3(256), 0, st, g, src[0], src[1], src[2], dst[0], dst[1], dst[2]);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_bhalf(const InstDesc* d, int n, int max_cells, hipStream_t st) {
+    if (n <= 0 || max_cells <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_bhalf, dim3((max_cells + 255) / 256, n), dim3(256), 0, st, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_efull(const InstDesc* d, int n, int max_cells, hipStream_t st) {
+    if (n <= 0 || max_cells <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_efull, dim3((max_cells + 255) / 256, n), dim3(256), 0, st, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_binomial(const InstDesc* d, int n, int max_cells, hipStream_t st) {
+    if (n <= 0 || max_cells <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_binomial, dim3((max_cells + 255) / 256, n), dim3(256), 0, st, d);
     return hipGetLastError();
 }
 

@@ -20,6 +20,68 @@ struct PlasmaDev {
     int ppc[3];
 };
 
+// One member of a batch of independent simulations for one species and one
+// step, as the batched kernels see it (a device-resident table the host
+// rewrites before each step).  Geometry is the one at the start of the step.
+struct InstDesc {
+    Geom g;
+    TileGeom t;
+    int guard;
+    int pd;                  // perfect-dispersion smoothing in the B update
+    int depth;               // in-tile block transpose of the sort
+    int nkeys;               // sort keys (t.ntiles * t.tcells)
+    PDCoef c;
+    FieldPtrs f;
+    float* J[3];             // current read by the E update
+    float* Jt[3];            // workspace current (binomial filter source)
+    int jpost;               // 0: none, 1: binomial filter
+    int sorting;             // 1: sort s -> alt first; the step then runs on alt
+    SpeciesDev s;            // particle arrays at the start of the step
+    SpeciesDev alt;          // the other array set
+    int* hist;               // sort histogram, then its exclusive scan (member scratch)
+    int* toff;               // tile ranges of the species (written by its sort)
+    int* rank;
+    int* sums;
+    unsigned long long* acc;
+    int* err;
+    int* count;              // particles in the arrays
+    int* sorted;             // particles inside the tile ranges of the last sort
+    int capacity;
+    float hdt;               // dt / 2
+    double jscale[3];
+    // laser source planes: B_z behind the source at t and t + dt, E_y on the
+    // source at t + dt/2
+    int laser_on;
+    int lix_b, lix_e;
+    double lcoef[3];
+    double yc, zc, inv_w2, dy, dz;
+    // moving window at the end of the step
+    int wmove;               // 1: clear the plane at origin, origin += 1
+    int inject;              // 1: load the species' plasma on window cell `slab` after the move
+    int slab;
+    long long shift;         // window shift after the move
+    PlasmaDev plasma;
+};
+
+// Particles arrays the tile step of a batch member works on.
+__host__ __device__ inline const SpeciesDev& step_arrays(const InstDesc& d) { return d.sorting ? d.alt : d.s; }
+
+// batched kernels: one launch per phase over `n` members (grid y = member,
+// except the tile step, whose work list is the concatenation of all tiles)
+hipError_t launch_batch_sort(const InstDesc* d, int n, int max_particles, int max_keys1, int max_tiles1,
+                             hipStream_t st);
+hipError_t launch_batch_tile(const InstDesc* d, const int* tile_begin, int n, int total_tiles, int threads,
+                             size_t lds_bytes, hipStream_t st);
+hipError_t launch_batch_loose(const InstDesc* d, int n, int max_loose, hipStream_t st);
+hipError_t launch_batch_jfinal(const InstDesc* d, int n, int max_cells, hipStream_t st);
+hipError_t launch_batch_binomial(const InstDesc* d, int n, int max_cells, hipStream_t st);
+hipError_t launch_batch_bhalf(const InstDesc* d, int n, int max_cells, hipStream_t st);
+hipError_t launch_batch_efull(const InstDesc* d, int n, int max_cells, hipStream_t st);
+// which: 0, 1, 2 = the laser planes in the order they are applied
+hipError_t launch_batch_laser(const InstDesc* d, int n, int which, int max_plane, hipStream_t st);
+hipError_t launch_batch_clear(const InstDesc* d, int n, int max_plane, hipStream_t st);
+hipError_t launch_batch_inject(const InstDesc* d, int n, long long max_cand, hipStream_t st);
+
 // window / injection / laser kernels (pic_window.hip)
 hipError_t launch_clear_plane(const Geom& g, const FieldPtrs& f, int ix, hipStream_t st);
 hipError_t launch_inject(const Geom& g, const PlasmaDev& P, const SpeciesDev& s, long long shift, int xb, int xe,
@@ -35,17 +97,18 @@ hipError_t launch_deposit(const Geom& g, const SpeciesDev& s, const PrevDev& pre
 hipError_t launch_jfinal(const Geom& g, unsigned long long* acc, float* const J[3], const double scale[3],
                          int zero_acc, hipStream_t st);
 
-// sort (pic_sort.hip): src -> dst, new count into d_count and d_sorted
+// sort (pic_sort.hip): src -> dst, new count into d_count and d_sorted, tile
+// ranges into toff (t.ntiles + 1 entries); hist, rank, sums are scratch.
 // depth: in-tile block-transpose depth (1 = plain cell order)
 hipError_t launch_sort(const Geom& g, const TileGeom& t, const SpeciesDev& src, const SpeciesDev& dst,
                        int* d_count, int* d_sorted, int max_count, int* hist, int* rank, int* sums, int depth,
-                       hipStream_t st);
+                       int* toff, hipStream_t st);
 
 // fused tile kernel (pic_tile.hip)
 size_t tile_lds_bytes(const TileGeom& t, int guard);
-// off: scanned key histogram of the last sort (tile ranges)
+// toff: tile ranges of the species' last sort
 hipError_t launch_pic_tile(const Geom& g, const TileGeom& t, int guard, int threads, const FieldPtrs& f,
-                           const SpeciesDev& s, const int* off, unsigned long long* acc, int* d_err, hipStream_t st);
+                           const SpeciesDev& s, const int* toff, unsigned long long* acc, int* d_err, hipStream_t st);
 hipError_t launch_push_deposit_range(const Geom& g, const FieldPtrs& f, const SpeciesDev& s, const int* d_begin,
                                      const int* d_count, int max_n, unsigned long long* acc, int* d_err,
                                      hipStream_t st);

@@ -90,10 +90,8 @@ __global__ void __launch_bounds__(256) k_deposit(Geom g, SpeciesDev s, PrevDev p
     esirkepov(A, s.mq * s.w[p], em);
 }
 
-__global__ void k_jfinal(unsigned long long* __restrict__ acc, float* J0, float* J1, float* J2, int ncell,
-                         double s0, double s1, double s2, int zero_acc) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ncell) return;
+__device__ __forceinline__ void jfinal_one(unsigned long long* __restrict__ acc, float* J0, float* J1, float* J2,
+                                           int ncell, double s0, double s1, double s2, int zero_acc, int i) {
     const long long a0 = (long long)acc[i], a1 = (long long)acc[(size_t)ncell + i],
                     a2 = (long long)acc[2 * (size_t)ncell + i];
     J0[i] = (float)((double)a0 * s0);
@@ -104,6 +102,30 @@ __global__ void k_jfinal(unsigned long long* __restrict__ acc, float* J0, float*
         acc[(size_t)ncell + i] = 0ull;
         acc[2 * (size_t)ncell + i] = 0ull;
     }
+}
+
+__global__ void k_jfinal(unsigned long long* __restrict__ acc, float* J0, float* J1, float* J2, int ncell,
+                         double s0, double s1, double s2, int zero_acc) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ncell) return;
+    jfinal_one(acc, J0, J1, J2, ncell, s0, s1, s2, zero_acc, i);
+}
+
+// Batched read-out of the current (accumulator cleared); into the workspace
+// current when the binomial filter follows.
+__global__ void __launch_bounds__(256) k_batch_jfinal(const InstDesc* __restrict__ tab) {
+    const InstDesc& d = tab[blockIdx.y];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ncell = d.g.ncell;
+    if (i >= ncell) return;
+    float* const* J = d.jpost ? d.Jt : d.J;
+    jfinal_one(d.acc, J[0], J[1], J[2], ncell, d.jscale[0], d.jscale[1], d.jscale[2], 1, i);
+}
+
+hipError_t launch_batch_jfinal(const InstDesc* d, int n, int max_cells, hipStream_t st) {
+    if (n <= 0 || max_cells <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_jfinal, dim3((max_cells + 255) / 256, n), dim3(256), 0, st, d);
+    return hipGetLastError();
 }
 
 hipError_t launch_gather_push(const Geom& g, const FieldPtrs& f, const SpeciesDev& s, const PrevDev& prev,

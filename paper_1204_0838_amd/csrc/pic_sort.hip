@@ -26,11 +26,8 @@ __device__ __forceinline__ int tile_key(const TileGeom& t, const int c[3]) {
     return tile * t.tcells + lx + t.T[0] * (ly + t.T[1] * lz);
 }
 
-__global__ void __launch_bounds__(256) k_sort_count(Geom g, TileGeom t, const int* __restrict__ cell,
-                                                    const int* __restrict__ d_count, int* __restrict__ hist,
-                                                    int* __restrict__ rank) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= *d_count) return;
+__device__ __forceinline__ void count_one(const Geom& g, const TileGeom& t, const int* __restrict__ cell, int p,
+                                          int* __restrict__ hist, int* __restrict__ rank) {
     const int cl = cell[p];
     if ((unsigned)cl >= (unsigned)g.ncell) {
         rank[p] = -1;
@@ -45,10 +42,18 @@ __global__ void __launch_bounds__(256) k_sort_count(Geom g, TileGeom t, const in
     rank[p] = atomicAdd(hist + tile_key(t, c), 1);
 }
 
+__global__ void __launch_bounds__(256) k_sort_count(Geom g, TileGeom t, const int* __restrict__ cell,
+                                                    const int* __restrict__ d_count, int* __restrict__ hist,
+                                                    int* __restrict__ rank) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= *d_count) return;
+    count_one(g, t, cell, p, hist, rank);
+}
+
 // Exclusive scan, phase 1: per-block totals of 1024-element blocks.
-__global__ void __launch_bounds__(1024) k_scan_reduce(const int* __restrict__ in, int n, int* __restrict__ sums) {
+__device__ __forceinline__ void scan_reduce_block(const int* __restrict__ in, int n, int* __restrict__ sums, int bx) {
     __shared__ int ws[16];
-    const int i = blockIdx.x * 1024 + threadIdx.x;
+    const int i = bx * 1024 + threadIdx.x;
     int v = i < n ? in[i] : 0;
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
@@ -56,8 +61,12 @@ __global__ void __launch_bounds__(1024) k_scan_reduce(const int* __restrict__ in
     if (threadIdx.x == 0) {
         int s = 0;
         for (int k = 0; k < 16; ++k) s += ws[k];
-        sums[blockIdx.x] = s;
+        sums[bx] = s;
     }
+}
+
+__global__ void __launch_bounds__(1024) k_scan_reduce(const int* __restrict__ in, int n, int* __restrict__ sums) {
+    scan_reduce_block(in, n, sums, blockIdx.x);
 }
 
 // Block-wide inclusive scan of one value per thread (1024 threads).
@@ -84,7 +93,7 @@ __device__ __forceinline__ int block_scan_incl(int v, int* ws) {
 }
 
 // Phase 2: exclusive scan of the block totals by one workgroup; total -> sums[nb].
-__global__ void __launch_bounds__(1024) k_scan_sums(int* __restrict__ sums, int nb) {
+__device__ __forceinline__ void scan_sums_block(int* __restrict__ sums, int nb) {
     __shared__ int ws[32];
     __shared__ int carry;
     if (threadIdx.x == 0) carry = 0;
@@ -102,20 +111,24 @@ __global__ void __launch_bounds__(1024) k_scan_sums(int* __restrict__ sums, int 
     if (threadIdx.x == 0) sums[nb] = carry;
 }
 
+__global__ void __launch_bounds__(1024) k_scan_sums(int* __restrict__ sums, int nb) { scan_sums_block(sums, nb); }
+
 // Phase 3: exclusive scan inside each block plus the block offset; out may alias in.
-__global__ void __launch_bounds__(1024) k_scan_apply(const int* in, int n, const int* __restrict__ sums, int* out) {
+__device__ __forceinline__ void scan_apply_block(const int* in, int n, const int* __restrict__ sums, int* out, int bx) {
     __shared__ int ws[32];
-    const int i = blockIdx.x * 1024 + threadIdx.x;
+    const int i = bx * 1024 + threadIdx.x;
     const int v = i < n ? in[i] : 0;
     const int inc = block_scan_incl(v, ws);
-    if (i < n) out[i] = sums[blockIdx.x] + inc - v;
+    if (i < n) out[i] = sums[bx] + inc - v;
 }
 
-__global__ void __launch_bounds__(256) k_sort_scatter(Geom g, TileGeom t, SpeciesDev src, SpeciesDev dst,
-                                                      const int* __restrict__ d_count, const int* __restrict__ rank,
-                                                      const int* __restrict__ off, int depth) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= *d_count) return;
+__global__ void __launch_bounds__(1024) k_scan_apply(const int* in, int n, const int* __restrict__ sums, int* out) {
+    scan_apply_block(in, n, sums, out, blockIdx.x);
+}
+
+__device__ __forceinline__ void scatter_one(const Geom& g, const TileGeom& t, const SpeciesDev& src,
+                                            const SpeciesDev& dst, int p, const int* __restrict__ rank,
+                                            const int* __restrict__ off, int depth) {
     const int r = rank[p];
     if (r < 0) return;
     const int cl = src.cell[p];
@@ -144,6 +157,14 @@ __global__ void __launch_bounds__(256) k_sort_scatter(Geom g, TileGeom t, Specie
     dst.id[dest] = src.id[p];
 }
 
+__global__ void __launch_bounds__(256) k_sort_scatter(Geom g, TileGeom t, SpeciesDev src, SpeciesDev dst,
+                                                      const int* __restrict__ d_count, const int* __restrict__ rank,
+                                                      const int* __restrict__ off, int depth) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= *d_count) return;
+    scatter_one(g, t, src, dst, p, rank, off, depth);
+}
+
 // New live count = total of the histogram.
 __global__ void k_sort_finish(const int* __restrict__ off, int nkeys, int* __restrict__ d_count,
                               int* __restrict__ d_sorted) {
@@ -151,9 +172,89 @@ __global__ void k_sort_finish(const int* __restrict__ off, int nkeys, int* __res
     d_sorted[0] = off[nkeys];
 }
 
+// Tile ranges of the species: toff[t] = first particle of tile t (t = 0..ntiles).
+__global__ void __launch_bounds__(256) k_tile_offsets(const int* __restrict__ off, int tcells, int ntiles,
+                                                      int* __restrict__ toff) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t <= ntiles) toff[t] = off[t * tcells];
+}
+
+// Batched sort: grid y = member; members that do not sort this step return at once.
+__global__ void __launch_bounds__(256) k_batch_zero_hist(const InstDesc* __restrict__ tab) {
+    const InstDesc& d = tab[blockIdx.y];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (!d.sorting || i > d.nkeys) return;
+    d.hist[i] = 0;
+}
+
+__global__ void __launch_bounds__(256) k_batch_sort_count(const InstDesc* __restrict__ tab) {
+    const InstDesc& d = tab[blockIdx.y];
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (!d.sorting || p >= *d.count) return;
+    const Geom g = d.g;
+    const TileGeom t = d.t;
+    count_one(g, t, d.s.cell, p, d.hist, d.rank);
+}
+
+__global__ void __launch_bounds__(1024) k_batch_scan_reduce(const InstDesc* __restrict__ tab) {
+    const InstDesc& d = tab[blockIdx.y];
+    const int n = d.nkeys + 1;
+    if (!d.sorting || (int)blockIdx.x * 1024 >= n) return;
+    scan_reduce_block(d.hist, n, d.sums, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(1024) k_batch_scan_sums(const InstDesc* __restrict__ tab) {
+    const InstDesc& d = tab[blockIdx.y];
+    if (!d.sorting) return;
+    scan_sums_block(d.sums, (d.nkeys + 1 + 1023) / 1024);
+}
+
+__global__ void __launch_bounds__(1024) k_batch_scan_apply(const InstDesc* __restrict__ tab) {
+    const InstDesc& d = tab[blockIdx.y];
+    const int n = d.nkeys + 1;
+    if (!d.sorting || (int)blockIdx.x * 1024 >= n) return;
+    scan_apply_block(d.hist, n, d.sums, d.hist, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(256) k_batch_sort_scatter(const InstDesc* __restrict__ tab) {
+    const InstDesc& d = tab[blockIdx.y];
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (!d.sorting || p >= *d.count) return;
+    const Geom g = d.g;
+    const TileGeom t = d.t;
+    const SpeciesDev src = d.s, dst = d.alt;
+    scatter_one(g, t, src, dst, p, d.rank, d.hist, d.depth);
+}
+
+__global__ void __launch_bounds__(256) k_batch_sort_finish(const InstDesc* __restrict__ tab) {
+    const InstDesc& d = tab[blockIdx.y];
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (!d.sorting || t > d.t.ntiles) return;
+    d.toff[t] = d.hist[t * d.t.tcells];
+    if (t == 0) {
+        d.count[0] = d.hist[d.nkeys];
+        d.sorted[0] = d.hist[d.nkeys];
+    }
+}
+
+hipError_t launch_batch_sort(const InstDesc* d, int n, int max_particles, int max_keys1, int max_tiles1,
+                             hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int np = max_particles > 0 ? max_particles : 1;
+    const int nb = (max_keys1 + 1023) / 1024;
+    hipLaunchKernelGGL(k_batch_zero_hist, dim3((max_keys1 + 255) / 256, n), dim3(256), 0, st, d);
+    hipLaunchKernelGGL(k_batch_sort_count, dim3((np + 255) / 256, n), dim3(256), 0, st, d);
+    hipLaunchKernelGGL(k_batch_scan_reduce, dim3(nb, n), dim3(1024), 0, st, d);
+    hipLaunchKernelGGL(k_batch_scan_sums, dim3(1, n), dim3(1024), 0, st, d);
+    hipLaunchKernelGGL(k_batch_scan_apply, dim3(nb, n), dim3(1024), 0, st, d);
+    hipLaunchKernelGGL(k_batch_sort_scatter, dim3((np + 255) / 256, n), dim3(256), 0, st, d);
+    hipLaunchKernelGGL(k_batch_sort_finish, dim3((max_tiles1 + 255) / 256, n), dim3(256), 0, st, d);
+    return hipGetLastError();
+}
+
 hipError_t launch_sort(const Geom& g, const TileGeom& t, const SpeciesDev& src, const SpeciesDev& dst,
                        int* d_count, int* d_sorted, int max_count, int* hist, int* rank, int* sums, int depth,
-                       hipStream_t st) {
+                       int* toff, hipStream_t st) {
     const int nkeys = t.ntiles * t.tcells;
     hipError_t e = hipMemsetAsync(hist, 0, ((size_t)nkeys + 1) * sizeof(int), st);
     if (e != hipSuccess) return e;
@@ -167,6 +268,8 @@ hipError_t launch_sort(const Geom& g, const TileGeom& t, const SpeciesDev& src, 
     hipLaunchKernelGGL(k_sort_scatter, dim3((np + 255) / 256), dim3(256), 0, st, g, t, src, dst, d_count, rank, hist,
                        depth);
     hipLaunchKernelGGL(k_sort_finish, dim3(1), dim3(1), 0, st, hist, nkeys, d_count, d_sorted);
+    hipLaunchKernelGGL(k_tile_offsets, dim3((t.ntiles + 1 + 255) / 256), dim3(256), 0, st, hist, t.tcells, t.ntiles,
+                       toff);
     return hipGetLastError();
 }
 

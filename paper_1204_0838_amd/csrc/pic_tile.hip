@@ -89,13 +89,12 @@ __device__ __noinline__ int push_deposit_global(const Geom& g, const FieldPtrs& 
     return errs;
 }
 
+// Body of the fused step for one tile (the whole workgroup cooperates).
 template <int NT>
-__global__ void __launch_bounds__(NT) k_pic_tile(Geom g, TileGeom t, int guard, FieldPtrs f, SpeciesDev s,
-                                                 const int* __restrict__ off,
-                                                 unsigned long long* __restrict__ acc, int* __restrict__ d_err) {
-    extern __shared__ unsigned long long lds_u64[];
-    const int tile = xcd_tile(blockIdx.x, t.ntiles);
-    if (tile >= t.ntiles) return;
+__device__ __forceinline__ void tile_body(const Geom& g, const TileGeom& t, int guard, const FieldPtrs& f,
+                                          const SpeciesDev& s, const int* __restrict__ toff,
+                                          unsigned long long* __restrict__ acc, int* __restrict__ d_err,
+                                          unsigned long long* lds_u64, int tile) {
     const int tz = tile / (t.nt[0] * t.nt[1]);
     const int tr = tile - tz * t.nt[0] * t.nt[1];
     const int ty = tr / t.nt[0];
@@ -137,8 +136,8 @@ __global__ void __launch_bounds__(NT) k_pic_tile(Geom g, TileGeom t, int guard, 
     float* const Bl[3] = {Fl + 3 * fr, Fl + 4 * fr, Fl + 5 * fr};
     const int fstride[3] = {1, fx, fx * fy};
     const int jstride[3] = {1, jx, jx * jy};
-    const int pb = off[tile * t.tcells];
-    const int n = off[(tile + 1) * t.tcells] - pb;
+    const int pb = toff[tile];
+    const int n = toff[tile + 1] - pb;
     int errs = 0;
     // software pipeline: the next particle's SoA loads are issued before the
     // current particle is processed
@@ -243,15 +242,42 @@ __global__ void __launch_bounds__(NT) k_pic_tile(Geom g, TileGeom t, int guard, 
     }
 }
 
+template <int NT>
+__global__ void __launch_bounds__(NT) k_pic_tile(Geom g, TileGeom t, int guard, FieldPtrs f, SpeciesDev s,
+                                                 const int* __restrict__ toff, unsigned long long* __restrict__ acc,
+                                                 int* __restrict__ d_err) {
+    extern __shared__ unsigned long long lds_u64[];
+    const int tile = xcd_tile(blockIdx.x, t.ntiles);
+    if (tile >= t.ntiles) return;
+    tile_body<NT>(g, t, guard, f, s, toff, acc, d_err, lds_u64, tile);
+}
+
+// Batched form: the work list is the concatenation of every member's tiles
+// (member m owns flat tiles [tile_begin[m], tile_begin[m+1])), mapped XCD by
+// XCD like the single-instance launch.
+template <int NT>
+__global__ void __launch_bounds__(NT) k_batch_tile(const InstDesc* __restrict__ tab,
+                                                   const int* __restrict__ tile_begin, int n, int total) {
+    extern __shared__ unsigned long long lds_u64[];
+    const int ft = xcd_tile(blockIdx.x, total);
+    if (ft >= total) return;
+    int lo = 0, hi = n - 1;   // last member whose range starts at or before ft
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tile_begin[mid] <= ft) lo = mid; else hi = mid - 1;
+    }
+    const InstDesc& d = tab[lo];
+    const Geom g = d.g;
+    const TileGeom t = d.t;
+    const FieldPtrs f = d.f;
+    const SpeciesDev s = step_arrays(d);
+    tile_body<NT>(g, t, d.guard, f, s, d.toff, d.acc, d.err, lds_u64, ft - tile_begin[lo]);
+}
+
 // Particles appended after the last sort (not in any tile range): the same
 // step through global memory.
-__global__ void __launch_bounds__(256) k_push_deposit_range(Geom g, FieldPtrs f, SpeciesDev s,
-                                                            const int* __restrict__ d_begin,
-                                                            const int* __restrict__ d_count,
-                                                            unsigned long long* __restrict__ acc,
-                                                            int* __restrict__ d_err) {
-    const int p = *d_begin + blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= *d_count) return;
+__device__ __forceinline__ void loose_one(const Geom& g, const FieldPtrs& f, const SpeciesDev& s, int p,
+                                          unsigned long long* acc, int* d_err) {
     const int cell = s.cell[p];
     if ((unsigned)cell >= (unsigned)g.ncell) return;
     int c[3];
@@ -264,6 +290,26 @@ __global__ void __launch_bounds__(256) k_push_deposit_range(Geom g, FieldPtrs f,
     if (errs) atomicOr(d_err, errs);
 }
 
+__global__ void __launch_bounds__(256) k_push_deposit_range(Geom g, FieldPtrs f, SpeciesDev s,
+                                                            const int* __restrict__ d_begin,
+                                                            const int* __restrict__ d_count,
+                                                            unsigned long long* __restrict__ acc,
+                                                            int* __restrict__ d_err) {
+    const int p = *d_begin + blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= *d_count) return;
+    loose_one(g, f, s, p, acc, d_err);
+}
+
+__global__ void __launch_bounds__(256) k_batch_loose(const InstDesc* __restrict__ tab) {
+    const InstDesc& d = tab[blockIdx.y];
+    const int p = *d.sorted + blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= *d.count) return;
+    const Geom g = d.g;
+    const FieldPtrs f = d.f;
+    const SpeciesDev s = step_arrays(d);
+    loose_one(g, f, s, p, d.acc, d.err);
+}
+
 size_t tile_lds_bytes(const TileGeom& t, int guard) {
     const size_t H = guard + 2;
     const size_t fr = (t.T[0] + 2 * H) * (t.T[1] + 2 * H) * (t.T[2] + 2 * H);
@@ -273,25 +319,52 @@ size_t tile_lds_bytes(const TileGeom& t, int guard) {
 
 template <int NT>
 static hipError_t launch_tile_nt(const Geom& g, const TileGeom& t, int guard, const FieldPtrs& f,
-                                 const SpeciesDev& s, const int* off, unsigned long long* acc,
+                                 const SpeciesDev& s, const int* toff, unsigned long long* acc,
                                  int* d_err, hipStream_t st) {
     const size_t lds = tile_lds_bytes(t, guard);
     const int nb = ((t.ntiles + 7) / 8) * 8;
     hipError_t e = hipFuncSetAttribute((const void*)k_pic_tile<NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_pic_tile<NT>, dim3(nb), dim3(NT), lds, st, g, t, guard, f, s, off, acc, d_err);
+    hipLaunchKernelGGL(k_pic_tile<NT>, dim3(nb), dim3(NT), lds, st, g, t, guard, f, s, toff, acc, d_err);
     return hipGetLastError();
 }
 
 hipError_t launch_pic_tile(const Geom& g, const TileGeom& t, int guard, int threads, const FieldPtrs& f,
-                           const SpeciesDev& s, const int* off, unsigned long long* acc,
+                           const SpeciesDev& s, const int* toff, unsigned long long* acc,
                            int* d_err, hipStream_t st) {
     switch (threads) {
-        case 256: return launch_tile_nt<256>(g, t, guard, f, s, off, acc, d_err, st);
-        case 1024: return launch_tile_nt<1024>(g, t, guard, f, s, off, acc, d_err, st);
-        default: return launch_tile_nt<512>(g, t, guard, f, s, off, acc, d_err, st);
+        case 256: return launch_tile_nt<256>(g, t, guard, f, s, toff, acc, d_err, st);
+        case 1024: return launch_tile_nt<1024>(g, t, guard, f, s, toff, acc, d_err, st);
+        default: return launch_tile_nt<512>(g, t, guard, f, s, toff, acc, d_err, st);
     }
+}
+
+template <int NT>
+static hipError_t launch_batch_tile_nt(const InstDesc* d, const int* tile_begin, int n, int total, size_t lds,
+                                       hipStream_t st) {
+    const int nb = ((total + 7) / 8) * 8;
+    hipError_t e = hipFuncSetAttribute((const void*)k_batch_tile<NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_batch_tile<NT>, dim3(nb), dim3(NT), lds, st, d, tile_begin, n, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_tile(const InstDesc* d, const int* tile_begin, int n, int total_tiles, int threads,
+                             size_t lds_bytes, hipStream_t st) {
+    if (n <= 0 || total_tiles <= 0) return hipSuccess;
+    switch (threads) {
+        case 256: return launch_batch_tile_nt<256>(d, tile_begin, n, total_tiles, lds_bytes, st);
+        case 1024: return launch_batch_tile_nt<1024>(d, tile_begin, n, total_tiles, lds_bytes, st);
+        default: return launch_batch_tile_nt<512>(d, tile_begin, n, total_tiles, lds_bytes, st);
+    }
+}
+
+hipError_t launch_batch_loose(const InstDesc* d, int n, int max_loose, hipStream_t st) {
+    if (n <= 0 || max_loose <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_loose, dim3((max_loose + 255) / 256, n), dim3(256), 0, st, d);
+    return hipGetLastError();
 }
 
 hipError_t launch_push_deposit_range(const Geom& g, const FieldPtrs& f, const SpeciesDev& s, const int* d_begin,

@@ -107,6 +107,15 @@ _SIGS = {
     "pic_sync": (ctypes.c_int, [_vp]),
     "pic_last_error": (ctypes.c_char_p, [_vp]),
     "pic_destroy": (None, [_vp]),
+    "pic_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32]),
+    "pic_batch_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int32, _vp,
+                                        ctypes.c_size_t, _vp]),
+    "pic_batch_step": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "pic_batch_sync": (ctypes.c_int, [_vp]),
+    "pic_batch_profile_enable": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "pic_batch_profile_read": (ctypes.c_int, [_vp, ctypes.POINTER(Profile)]),
+    "pic_batch_last_error": (ctypes.c_char_p, [_vp]),
+    "pic_batch_destroy": (None, [_vp]),
 }
 
 _lib = None
@@ -364,3 +373,60 @@ class Simulation:
         return {"cell": v["cell"].cpu().numpy(), "off": np.stack([t.cpu().numpy() for t in v["off"]]),
                 "u": np.stack([t.cpu().numpy() for t in v["u"]]), "w": v["w"].cpu().numpy(),
                 "id": v["id"].cpu().numpy()}
+
+
+class Batch:
+    """Lockstep driver of several Simulations (one launch per phase for all).
+
+    Every member must use the same stream and have the same number of
+    species; members stay usable on their own between batch calls.
+    """
+
+    def __init__(self, members):
+        self.members = list(members)
+        if not self.members:
+            raise PicError(PIC_EINVAL, "empty batch")
+        dev = self.members[0].device
+        self.stream = self.members[0].stream
+        n = len(self.members)
+        nbytes = int(lib().pic_batch_workspace_bytes(n))
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        arr = (_vp * n)(*[m.handle.value for m in self.members])
+        h = ctypes.c_void_p()
+        st = lib().pic_batch_create(ctypes.byref(h), arr, n, ctypes.c_void_p(base + off), nbytes,
+                                    ctypes.c_void_p(self.stream.cuda_stream))
+        if st != PIC_OK:
+            raise PicError(st, "pic_batch_create failed")
+        self.handle = h
+
+    def _check(self, st):
+        if st != PIC_OK:
+            msg = lib().pic_batch_last_error(self.handle)
+            raise PicError(st, msg.decode() if msg else "")
+
+    def step(self, nsteps=1):
+        self._check(lib().pic_batch_step(self.handle, int(nsteps)))
+
+    def sync(self):
+        self._check(lib().pic_batch_sync(self.handle))
+
+    def profile_enable(self, on=True):
+        self._check(lib().pic_batch_profile_enable(self.handle, 1 if on else 0))
+
+    def profile_read(self):
+        p = Profile()
+        self._check(lib().pic_batch_profile_read(self.handle, ctypes.byref(p)))
+        return {k: getattr(p, k) for k, _ in Profile._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().pic_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -11,10 +11,19 @@ waist 5 c/w_p, intensity FWHM 2.5 / w_p) launched through the x boundary.
 The paper resolves lambda0 with dx = 0.06 lambda0 (Section 3.1); keeping that
 resolution gives lambda0 = 4.17 c/w_p, i.e. omega0 = 1.508 w_p.  The window
 starts to move at c when the pulse peak reaches 64 cells from the front.
+
+C3 is a parameter scan of 64 such setups of uneven size, advanced together
+by the batched launcher: instance i draws from seeded stream 3 + i its grid
+(nx uniform in 64..256, ny and nz in 32..64, each rounded to a multiple of
+8 cells), its laser strength a0 in [2, 5] and its plateau density in
+[0.5, 2] n0; spacings, solver, laser shape and ramp are C1's, the window
+starts when the pulse peak is a quarter of the box from the front, 200 steps.
 """
 from __future__ import annotations
 
 import math
+
+import numpy as np
 
 C1 = {
     "name": "C1",
@@ -77,3 +86,44 @@ def build(cfg: dict, capacity_factor: float = 1.05, device="cuda:0", tuned: bool
                   nz * cfg["d"][2] / 2, L["src_x"])
     sim.set_window(window_start_step(cfg))
     return sim
+
+
+def c3_members(count: int = 64, seed0: int = 3, base: dict = C1) -> list:
+    """Configurations of the C3 parameter-scan instances (see the module doc)."""
+    from .inputs import uniform53
+
+    out = []
+    for i in range(count):
+        u = uniform53(seed0 + i, np.arange(5, dtype=np.uint64))
+        nx = 64 + int(u[0] * 193)
+        ny = 32 + int(u[1] * 33)
+        nz = 32 + int(u[2] * 33)
+        n = tuple(8 * int(round(v / 8.0)) for v in (nx, ny, nz))
+        cfg = scaled(base, n)
+        cfg["name"] = f"C3[{i}]"
+        cfg["steps"] = 200
+        cfg["laser"] = dict(base["laser"], a0=2.0 + 3.0 * float(u[3]))
+        cfg["plasma"] = dict(base["plasma"], n_plateau=0.5 + 1.5 * float(u[4]))
+        cfg["front_margin"] = n[0] // 4
+        out.append(cfg)
+    return out
+
+
+def size_class(cfg: dict) -> str:
+    """Instance-size class used to share autotuned tilings across a scan."""
+    nx, ny, nz = cfg["n"]
+    cells = nx * ny * nz
+    return "S" if cells < (1 << 18) else ("M" if cells < (1 << 19) else "L")
+
+
+def build_batch(cfgs: list, capacity_factor: float = 1.05, device="cuda:0", tilings=None):
+    """Simulations for every configuration plus the Batch that drives them.
+
+    tilings: optional list (one dict per member) of tiling keywords."""
+    from . import pic
+
+    sims = []
+    for i, cfg in enumerate(cfgs):
+        t = dict(tilings[i]) if tilings else {}
+        sims.append(build(cfg, capacity_factor, device, tuned=False, **t))
+    return sims, pic.Batch(sims)

@@ -50,6 +50,7 @@ def test_validation_accepts_paper_shaped_grids():
     (dict(dt=float("nan")), "positive"),
     (dict(jpost=7), "post-processing"),
     (dict(tile=(128, 8, 8)), "tile"),
+    (dict(tile=(8, 2, 8)), "tile below 3"),
 ])
 def test_validation_rejects_bad_descriptors(kw, fragment):
     st, msg = pic.validate(_desc(**kw))

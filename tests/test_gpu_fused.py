@@ -106,3 +106,34 @@ def test_sort_groups_particles_by_tile_and_keeps_them():
     tx, ty, tz = (c % nx) // T[0], ((c // nx) % ny) // T[1], (c // (nx * ny)) // T[2]
     tile = tx + 3 * (ty + 4 * tz)
     assert np.all(np.diff(tile) >= 0)   # tiles are contiguous and in order
+
+
+def test_two_species_keep_their_own_tile_ranges():
+    """Two species of very different sizes, sorted every third step: each
+    species' fused steps between sorts must use its own tile ranges (fused ==
+    split bit for bit, both species)."""
+    grid = inputs.Grid(n=(24, 16, 16), d=(0.25, 0.5, 0.5), dt=0.25, solver="pd")
+    big = inputs.uniform_random_plasma(grid, ppc=8, seed=51, temperature_ev=50000.0, ux_amp=0.2)
+    small = inputs.uniform_random_plasma(grid, ppc=1, seed=52, temperature_ev=50000.0)
+    small.m = 3.0
+    sims = []
+    for kw in (dict(tile=(8, 8, 8), sort_interval=3), {}):
+        s = pic.Simulation(grid.n, grid.d, grid.dt, solver="pd", max_particles=big.count + small.count, **kw)
+        s.add_particles(small)     # the smaller species sorts first, the larger one last
+        s.add_particles(big)
+        sims.append(s)
+    a, b = sims
+    a.step(7)
+    for _ in range(7):
+        for sp in range(2):
+            b.gather_push(sp)
+            b.deposit(sp)
+        b.field_step()
+    for fa, fb in ((a.E, b.E), (a.B, b.B), (a.J, b.J)):
+        assert torch.equal(fa, fb)
+    for sp in range(2):
+        pa, pb = a.particles_host(sp), b.particles_host(sp)
+        ia, ib = np.argsort(pa["id"]), np.argsort(pb["id"])
+        assert np.array_equal(pa["id"][ia], pb["id"][ib])
+        assert np.array_equal(pa["u"][:, ia], pb["u"][:, ib])
+        assert np.array_equal(pa["cell"][ia], pb["cell"][ib])
