@@ -81,6 +81,91 @@ def measured_traffic(path, cfg):
     return rec.get("bytes_per_launch") if rec.get("source_sha256") == h.hexdigest() else None
 
 
+def bench_c3(args):
+    """C3: the 64-member parameter scan advanced by the batched launcher
+    (one launch per phase for all members), W warm-up + K timed batch steps
+    (defaults 5 + 195 of the 200-step scan); then the same members advanced
+    one after another with pic_step for a few steps, for comparison."""
+    import torch
+
+    from paper_1204_0838_amd import autotune, workloads
+
+    cfgs = workloads.c3_members()
+    tilings = [autotune.load_class(workloads.size_class(c), c) or {} for c in cfgs]
+    t_setup = time.perf_counter()
+    sims, batch = workloads.build_batch(cfgs, tilings=tilings)
+    batch.sync()
+    print(f"# setup {time.perf_counter() - t_setup:.1f}s, {len(sims)} members", file=sys.stderr, flush=True)
+    batch.step(args.warmup)
+    batch.sync()
+
+    def live():
+        return sum(s.reduce()["n_particles"] for s in sims)
+
+    n0 = live()
+    batch.profile_enable(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(batch.stream)
+    left = args.steps
+    while left > 0:
+        k = min(50, left)
+        batch.step(k)
+        left -= k
+        print(f"# {args.steps - left}/{args.steps} batch steps", file=sys.stderr, flush=True)
+    e1.record(batch.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    prof = batch.profile_read()
+    batch.sync()
+    n1 = live()
+    npart = 0.5 * (n0 + n1)
+    K = args.steps
+    ncell = sum(c["n"][0] * c["n"][1] * c["n"][2] for c in cfgs)
+    tile_ms = prof["tile_ms"] / max(1, prof["tile_launches"])
+    alg_bytes = 60.0 * npart + 48.0 * ncell
+    achieved = alg_bytes / (tile_ms * 1e-3) / 1e9
+    # the same members one after another (per-member launches), a few steps
+    seq_steps = 10
+    torch.cuda.synchronize()
+    e0.record(batch.stream)
+    for s in sims:
+        s.step(seq_steps)
+    e1.record(batch.stream)
+    torch.cuda.synchronize()
+    seq_ms = e0.elapsed_time(e1) / seq_steps
+    out = {
+        "metric": "particle-steps/s (gather+push+deposit), batched parameter scan",
+        "value": npart * K / (ms * 1e-3),
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "C3 parameter scan: 64 LWFA instances (nx 64..256, ny, nz 32..64, a0 2..5, "
+                               "plateau density 0.5..2, 8 ppc, C1 spacings/solver/laser), 200 steps, one launch "
+                               "per phase for all members",
+                   "members": len(sims), "particles": int(npart), "cells": ncell,
+                   "tiling_by_class": {k: v for k, v in zip([workloads.size_class(c) for c in cfgs], tilings)}},
+        "gather_push_deposit_particle_steps_per_s": npart * prof["tile_launches"] / (prof["tile_ms"] * 1e-3),
+        "phase_ms_per_step": {k[:-3]: prof[k] / max(1, prof["steps"]) for k in
+                              ("sort_ms", "tile_ms", "loose_ms", "jpost_ms", "field_ms", "window_ms")},
+        "sequential_ms_per_step": seq_ms,
+        "batched_speedup_vs_sequential": seq_ms / (ms / K),
+        "roofline": {"bound": "hbm", "kernel": "k_batch_tile", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "alg_bytes_per_launch": alg_bytes, "mean_launch_ms": tile_ms},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +178,8 @@ def main():
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-json", type=str, default="", help="per-launch HBM bytes from rocprofv3 counters")
+    ap.add_argument("--workload", type=str, default="c1", choices=["c1", "c3"],
+                    help="c1 (default): the LWFA slab; c3: the batched 64-member parameter scan")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 5 device copies of 1 GiB (reference for the FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
@@ -110,6 +197,12 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4, "copies": 5}))
+        return
+
+    if args.workload == "c3":
+        if args.steps == 995:
+            args.steps = 195
+        bench_c3(args)
         return
 
     from paper_1204_0838_amd import workloads

@@ -10,6 +10,10 @@ keyed by grid shape, particles per cell and solver; ``bench.py`` and
 ``workloads.build`` read the cache.
 
     python -m paper_1204_0838_amd.autotune --warmup 600 --steps 12
+    python -m paper_1204_0838_amd.autotune --batch --warmup 60 --steps 6
+
+The batched form tunes the members of a parameter scan per instance-size
+class on the live batch (one tiling per class; threads per tile batch-wide).
 """
 from __future__ import annotations
 
@@ -67,35 +71,104 @@ def time_candidate(sim, c: dict, steps: int) -> float:
 
 
 def tune(sim, steps: int = 12, rounds: int = 2, log=sys.stderr):
-    """Coordinate descent over SPACE; returns (best, table of (candidate, ms/step))."""
+    """Coordinate descent over SPACE; returns (best, ms/step, table of (candidate, ms/step)).
+
+    The run evolves while it is tuned (the window moves, the wake grows), so
+    each candidate is timed right after the current best, and it replaces the
+    best only if it beats that fresh measurement by more than 1 %."""
     best = dict(DEFAULT)
-    seen = {}
-
-    def measure(c):
-        k = json.dumps(c, sort_keys=True)
-        if k not in seen:
-            seen[k] = time_candidate(sim, c, steps)
-            if log:
-                print(f"# tune {c} -> {seen[k]:.3f} ms/step", file=log, flush=True)
-        return seen[k]
-
-    best_ms = measure(best)
+    table = []
+    best_ms = time_candidate(sim, best, steps)
     for _ in range(rounds):
         improved = False
         for knob, values in SPACE.items():
             for v in values:
                 c = dict(best)
                 c[knob] = v
-                if not feasible(c):
+                if c == best or not feasible(c):
                     continue
-                ms = measure(c)
-                if ms < best_ms:
+                ref = time_candidate(sim, best, steps)
+                ms = time_candidate(sim, c, steps)
+                table.append((c, ms, ref))
+                if log:
+                    print(f"# tune {c} -> {ms:.3f} ms/step (best now {ref:.3f})", file=log, flush=True)
+                if ms < 0.99 * ref:
                     best, best_ms, improved = c, ms, True
+                else:
+                    best_ms = ref
         if not improved:
             break
     sim.set_tiling(**best)
-    table = [(json.loads(k), ms) for k, ms in sorted(seen.items(), key=lambda kv: kv[1])]
-    return best, best_ms, table
+    table.sort(key=lambda r: r[1] / r[2])
+    return best, best_ms, [(c, ms) for c, ms, _ in table]
+
+
+def class_key(cls: str, cfg: dict) -> str:
+    p = cfg["plasma"]["ppc"]
+    return "batch|{}|ppc{}|{}".format(cls, p[0] * p[1] * p[2], cfg["solver"])
+
+
+def time_batch(batch, steps: int) -> float:
+    import torch
+
+    batch.step(1)          # members re-sort under new tilings
+    batch.sync()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(batch.stream)
+    batch.step(steps)
+    e1.record(batch.stream)
+    batch.sync()
+    return e0.elapsed_time(e1) / steps
+
+
+def tune_batch(batch, sims, cfgs, steps: int = 6, rounds: int = 2, log=sys.stderr):
+    """Per size-class coordinate descent on a live batch.
+
+    Members of one class (workloads.size_class) share a tiling; threads per
+    tile is one batch-wide knob (the batched tile launch uses one workgroup
+    size).  As in tune(), each candidate is timed right after the current
+    best.  Returns ({class: best tiling}, batch ms/step)."""
+    from . import workloads
+
+    classes = {}
+    for i, c in enumerate(cfgs):
+        classes.setdefault(workloads.size_class(c), []).append(i)
+    best = {k: dict(DEFAULT) for k in classes}
+
+    def measure(tilings):
+        for k, idx in classes.items():
+            for i in idx:
+                sims[i].set_tiling(**tilings[k])
+        return time_batch(batch, steps)
+
+    best_ms = measure(best)
+    if log:
+        print(f"# batch tune start {best_ms:.3f} ms/step", file=log, flush=True)
+    for _ in range(rounds):
+        improved = False
+        for knob, values in SPACE.items():
+            for k in (classes if knob != "threads" else ["*"]):
+                targets = list(classes) if k == "*" else [k]
+                for v in values:
+                    cand = {kk: dict(b) for kk, b in best.items()}
+                    for t in targets:
+                        cand[t][knob] = v
+                    if cand == best or not all(feasible(cand[t]) for t in targets):
+                        continue
+                    ref = measure(best)
+                    ms = measure(cand)
+                    if log:
+                        print(f"# batch tune {k} {knob}={v} -> {ms:.3f} ms/step (best now {ref:.3f})", file=log,
+                              flush=True)
+                    if ms < 0.99 * ref:
+                        best, best_ms, improved = cand, ms, True
+                    else:
+                        best_ms = ref
+        if not improved:
+            break
+    measure(best)
+    return best, best_ms
 
 
 def load(cfg: dict, path: str = CACHE):
@@ -110,6 +183,30 @@ def load(cfg: dict, path: str = CACHE):
     best = dict(rec["best"])
     best["tile"] = tuple(best["tile"])
     return best
+
+
+def load_class(cls: str, cfg: dict, path: str = CACHE):
+    """Cached tiling of a batch size class, or None."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f).get(class_key(cls, cfg))
+    if not rec:
+        return None
+    best = dict(rec["best"])
+    best["tile"] = tuple(best["tile"])
+    return best
+
+
+def save_classes(cfg: dict, best: dict, best_ms: float, note: str, path: str = CACHE):
+    cache = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            cache = json.load(f)
+    for cls, b in best.items():
+        cache[class_key(cls, cfg)] = {"best": b, "batch_ms_per_step": best_ms, "note": note}
+    with open(path, "w") as f:
+        json.dump(cache, f, indent=1)
 
 
 def save(cfg: dict, best: dict, best_ms: float, table, note: str, path: str = CACHE):
@@ -128,9 +225,23 @@ def main():
     ap.add_argument("--grid", type=str, default="")
     ap.add_argument("--warmup", type=int, default=600)
     ap.add_argument("--steps", type=int, default=12)
+    ap.add_argument("--batch", action="store_true", help="tune the C3 parameter scan per size class")
     args = ap.parse_args()
     sys.path.insert(0, os.path.dirname(HERE))
     from paper_1204_0838_amd import workloads
+
+    if args.batch:
+        cfgs = workloads.c3_members()
+        sims, batch = workloads.build_batch(cfgs)
+        t0 = time.perf_counter()
+        batch.step(args.warmup)
+        batch.sync()
+        best, best_ms = tune_batch(batch, sims, cfgs, args.steps)
+        save_classes(cfgs[0], best, best_ms, f"per-class coordinate descent on the live C3 batch at step "
+                     f"{args.warmup}, {args.steps} timed batch steps per candidate, "
+                     f"{time.perf_counter() - t0:.0f} s")
+        print(json.dumps({"best": best, "batch_ms_per_step": best_ms}))
+        return
 
     cfg = workloads.C1
     if args.grid:

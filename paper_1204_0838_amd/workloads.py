@@ -75,7 +75,9 @@ def build(cfg: dict, capacity_factor: float = 1.05, device="cuda:0", tuned: bool
     nx, ny, nz = cfg["n"]
     p = cfg["plasma"]
     ppc = p["ppc"][0] * p["ppc"][1] * p["ppc"][2]
-    cap = int(initial_particles(cfg) * capacity_factor) + 4 * ny * nz * ppc
+    # every lattice slot of the window (the host-side bound of the initial load
+    # counts them all) with headroom for electrons swept along with the window
+    cap = int((nx - 3) * ny * nz * ppc * capacity_factor) + 4 * ny * nz * ppc
     sim = pic.Simulation(cfg["n"], cfg["d"], cfg["dt"], solver=cfg["solver"], bc_x=1, max_particles=cap,
                          device=device, **tiling)
     sim.add_empty_species(cap)
@@ -116,7 +118,7 @@ def size_class(cfg: dict) -> str:
     return "S" if cells < (1 << 18) else ("M" if cells < (1 << 19) else "L")
 
 
-def build_batch(cfgs: list, capacity_factor: float = 1.05, device="cuda:0", tilings=None):
+def build_batch(cfgs: list, capacity_factor: float = 1.3, device="cuda:0", tilings=None):
     """Simulations for every configuration plus the Batch that drives them.
 
     tilings: optional list (one dict per member) of tiling keywords."""
