@@ -16,9 +16,12 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
+_SRCS = (_SRC, os.path.join(_HERE, "denoise.c"))
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 _dp = ctypes.POINTER(ctypes.c_double)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_i32p = ctypes.POINTER(ctypes.c_int32)
 
 
 class OraGrid(ctypes.Structure):
@@ -28,11 +31,11 @@ class OraGrid(ctypes.Structure):
 
 
 def build(force: bool = False) -> str:
-    """Compile oracle.c into liboracle.so with gcc (strict IEEE double, no fast-math)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    """Compile oracle.c and denoise.c into liboracle.so with gcc (strict IEEE double, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(f) for f in _SRCS):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fno-fast-math",
-                               "-ffp-contract=off", _SRC, "-o", tmp, "-lm"])
+                               "-ffp-contract=off", *_SRCS, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -63,6 +66,11 @@ def lib():
             "ora_pd_coeffs": (i32, [_dp, i32, _dp, _dp, _dp]),
             "ora_diag": (None, [G, i64, _dp, _dp, dbl, dbl, _dp, _dp, _dp, _dp]),
             "ora_step": (i32, [G, i64, _dp, _dp, _dp, dbl, dbl, _dp, _dp, _dp, i32, _dp]),
+            "ora_bf16": (dbl, [dbl]),
+            "ora_conv3d": (None, [_i64p, _i32p, i64, _dp, i32, _dp, _dp, i32, _dp]),
+            "ora_denoise": (i32, [_i64p, _i32p, i64, _dp, _dp, i32, _dp, _dp, _dp, _dp, _dp, _dp, i32, _dp, _dp]),
+            "ora_denoise_grad": (dbl, [_i64p, _i32p, i64, _dp, _dp, i32, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
+                                       _dp, _dp, _dp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -342,3 +350,64 @@ def step(g: OraGrid, x, u, w, E, B, q=-1.0, m=1.0, jpost: int = 0):
     if st != 0:
         raise FloatingPointError("oracle step produced a non-finite value")
     return {"x": x, "u": u, "E": E, "B": B, "J": J, "x_prev": xp}
+
+
+# ---------------------------------------------------------------- current denoiser (denoise.c)
+
+BC = {"periodic": 0, "zero": 1, "window": 2}
+
+
+def bf16(x: float) -> float:
+    """Nearest bfloat16 value (ties to even)."""
+    return lib().ora_bf16(float(x))
+
+
+def _dims(n, bc):
+    nn = (ctypes.c_int64 * 3)(*[int(v) for v in n])
+    b = (ctypes.c_int32 * 3)(*[BC[v] if isinstance(v, str) else int(v) for v in bc])
+    return nn, b
+
+
+def conv3d(inp, W, b=None, bc=("periodic",) * 3, origin: int = 0):
+    """3x3x3 cross-correlation: inp [cin, nz, ny, nx], W [cout, cin, 3, 3, 3] ([z][y][x] taps)."""
+    inp = f64(inp)
+    W = f64(W)
+    cin, nz, ny, nx = inp.shape
+    cout = W.shape[0]
+    assert W.shape == (cout, cin, 3, 3, 3)
+    out = np.zeros((cout, nz, ny, nx))
+    nn, bb = _dims((nx, ny, nz), bc)
+    bias = f64(b) if b is not None else None
+    lib().ora_conv3d(nn, bb, int(origin), _p(inp), cin, _p(W), _p(bias) if bias is not None else None, cout,
+                     _p(out))
+    return out
+
+
+def denoise(J, scale, params, bc=("periodic",) * 3, origin: int = 0, round_bf16: bool = True):
+    """(Jout, y) of the three-layer denoiser; J [3, nz, ny, nx]; params = (W1, b1, W2, b2, W3, b3)."""
+    J = f64(J)
+    _, nz, ny, nx = J.shape
+    W1, b1, W2, b2, W3, b3 = [f64(a) for a in params]
+    H = W1.shape[0]
+    Jout = np.zeros_like(J)
+    y = np.zeros_like(J)
+    nn, bb = _dims((nx, ny, nz), bc)
+    sc = f64(scale)
+    st = lib().ora_denoise(nn, bb, int(origin), _p(J), _p(sc), H, _p(W1), _p(b1), _p(W2), _p(b2), _p(W3), _p(b3),
+                           1 if round_bf16 else 0, _p(Jout), _p(y))
+    if st != 0:
+        raise MemoryError("oracle denoiser")
+    return Jout, y
+
+
+def denoise_grad(x, r, params, bc=("zero",) * 3, origin: int = 0):
+    """(loss, grads) of the training loss mean((y - r)^2) at x (scaled input), exact FP64."""
+    x = f64(x)
+    r = f64(r)
+    _, nz, ny, nx = x.shape
+    P = [f64(a) for a in params]
+    G = [np.zeros_like(a) for a in P]
+    H = P[0].shape[0]
+    nn, bb = _dims((nx, ny, nz), bc)
+    loss = lib().ora_denoise_grad(nn, bb, int(origin), _p(x), _p(r), H, *[_p(a) for a in P], *[_p(g) for g in G])
+    return loss, G
