@@ -308,6 +308,28 @@ pic_status pic_profile_enable(pic_ctx *ctx, int32_t enable);
  * Synchronises the stream. */
 pic_status pic_profile_read(pic_ctx *ctx, pic_profile *out);
 
+/* Learned current denoiser (desc.jpost = PIC_JPOST_DENOISER).  Not part of
+ * the paper: the paper fights particle noise in the current with cubic
+ * shapes and many particles per cell (Sections 1, 3.1); this network is a
+ * learned replacement for the binomial filter at few particles per cell.
+ *   x  = bf16(J_d / scale_d)
+ *   a1 = bf16(relu(conv(x,  W1) + b1)),  a2 = bf16(relu(conv(a1, W2) + b2))
+ *   J_d <- J_d + scale_d (conv(a2, W3) + b3)_d
+ * conv: 3x3x3 cross-correlation, output size = input size; y and z
+ * periodic, x periodic or, in a moving window, zero beyond the window's
+ * ends.  Weights and activations bf16 (rounded to nearest even), FP32
+ * accumulation and biases, on the matrix cores.
+ * weights (host, FP32, copied and rounded to bf16): W1 [32][3][3][3][3],
+ * then W2 [32][32][3][3][3], then W3 [3][32][3][3][3], each indexed
+ * [out][in][z][y][x] with tap (z, y, x) = offsets (-1, 0, +1) + 1.
+ * biases (host, FP32): b1[32], b2[32], b3[3].  scale (host): 3 values > 0.
+ * Synchronises the stream. */
+pic_status pic_denoiser_set(pic_ctx *ctx, const float *weights, const float *biases, const float *scale);
+
+/* Apply the grid's current post-processing (desc.jpost) to J in place.
+ * Asynchronous. */
+pic_status pic_current_filter(pic_ctx *ctx);
+
 /* Text of the sticky error (never NULL). */
 const char *pic_last_error(const pic_ctx *ctx);
 

@@ -51,7 +51,7 @@ Tiling tiling_of(const pic_grid_desc* d) {
 // species take consecutive sub-ranges of them.
 struct Layout {
     size_t acc, jtmp, rho, small, prev_cell, prev_off, alt_cell, alt_off, alt_u, alt_w, alt_id, sort_rank, hist,
-        sums, toff, toff_stride, total;
+        sums, toff, toff_stride, dn_w, dn_h1, dn_h2, total;
 };
 
 // small block: err flags, per-species counts, reduction results
@@ -136,6 +136,10 @@ Layout layout(const pic_grid_desc* d, int64_t maxp) {
     L.sums = take((((size_t)nkeys + 1 + 1023) / 1024 + 1) * 4);
     L.toff_stride = align_up(((size_t)max_tiles(d) + 1) * 4);
     L.toff = take(kMaxSpecies * L.toff_stride);
+    const bool dn = d->jpost == PIC_JPOST_DENOISER;
+    L.dn_w = take(dn ? (kDnW1 + kDnW2 + kDnW3) * 2 + kDnBias * 4 : 0);
+    L.dn_h1 = take(dn ? (size_t)ncell * 64 : 0);
+    L.dn_h2 = take(dn ? (size_t)ncell * 64 : 0);
     L.total = o;
     return L;
 }
@@ -247,6 +251,9 @@ struct pic_ctx {
     int64_t shift = 0;
     bool has_plasma[kMaxSpecies] = {};
     PlasmaDev plasma[kMaxSpecies];
+    // learned current denoiser (pic_denoiser_set)
+    bool has_dn = false;
+    DenoiseWeights dn{};
     // phase timing (pic_profile_*)
     Prof prof;
 };
@@ -512,6 +519,37 @@ pic_status sort_species(pic_ctx* c, int32_t s) {
     return PIC_OK;
 }
 
+// Boundary rule of the denoiser's convolutions for this grid.
+void dn_bc(const pic_ctx* c, int bc[3]) {
+    bc[0] = c->g.window ? 2 : 0;
+    bc[1] = 0;
+    bc[2] = 0;
+}
+
+// Jin -> Jout through the denoiser (distinct buffers).
+pic_status denoise(pic_ctx* c, float* const Jin[3], float* const Jout[3]) {
+    if (!c->has_dn) return fail(c, PIC_ESTATE, "denoiser weights not set");
+    int bc[3];
+    dn_bc(c, bc);
+    HIPCHK(c, launch_denoise(c->g, bc, c->dn, Jin, Jout, reinterpret_cast<__bf16*>(c->ws + c->L.dn_h1),
+                             reinterpret_cast<__bf16*>(c->ws + c->L.dn_h2), c->stream));
+    return PIC_OK;
+}
+
+// J post-processing in place (through the workspace current).
+pic_status filter_in_place(pic_ctx* c) {
+    if (c->desc.jpost == PIC_JPOST_NONE) return PIC_OK;
+    float* tmp[3];
+    jtmp_of(c, tmp);
+    if (c->desc.jpost == PIC_JPOST_BINOMIAL)
+        HIPCHK(c, launch_binomial(c->g, c->f.J, tmp, c->stream));
+    else
+        PICCHK(denoise(c, c->f.J, tmp));
+    for (int a = 0; a < 3; ++a)
+        HIPCHK(c, hipMemcpyAsync(c->f.J[a], tmp[a], (size_t)c->g.ncell * 4, hipMemcpyDeviceToDevice, c->stream));
+    return PIC_OK;
+}
+
 // Current post-processing and field update of one production step.
 pic_status finish_step(pic_ctx* c) {
     double sc[3];
@@ -527,7 +565,10 @@ pic_status finish_step(pic_ctx* c) {
     } else if (c->desc.jpost == PIC_JPOST_NONE) {
         HIPCHK(c, launch_jfinal(c->g, acc_of(c), c->f.J, sc, 1, c->stream));
     } else {
-        return fail(c, PIC_EINVAL, "denoiser weights not set");
+        float* tmp[3];
+        jtmp_of(c, tmp);
+        HIPCHK(c, launch_jfinal(c->g, acc_of(c), tmp, sc, 1, c->stream));
+        PICCHK(denoise(c, tmp, c->f.J));
     }
     PICCHK(prof_end(c, PH_JPOST, t0));
     PICCHK(prof_mark(c, &t1));
@@ -940,15 +981,7 @@ pic_status pic_deposit(pic_ctx* c, int32_t s) {
 pic_status pic_field_step(pic_ctx* c) {
     if (!c) return PIC_EINVAL;
     float* Juse[3] = {c->f.J[0], c->f.J[1], c->f.J[2]};
-    if (c->desc.jpost == PIC_JPOST_BINOMIAL) {
-        float* tmp[3];
-        jtmp_of(c, tmp);
-        HIPCHK(c, launch_binomial(c->g, c->f.J, tmp, c->stream));
-        for (int a = 0; a < 3; ++a)
-            HIPCHK(c, hipMemcpyAsync(c->f.J[a], tmp[a], (size_t)c->g.ncell * 4, hipMemcpyDeviceToDevice, c->stream));
-    } else if (c->desc.jpost == PIC_JPOST_DENOISER) {
-        return fail(c, PIC_EINVAL, "denoiser weights not set");
-    }
+    PICCHK(filter_in_place(c));
     PICCHK(field_update(c, Juse));
     HIPCHK(c, launch_zero_u64(acc_of(c), 3 * (int64_t)c->g.ncell, c->stream));
     return end_step(c);
@@ -1156,6 +1189,66 @@ pic_status pic_profile_read(pic_ctx* c, pic_profile* out) {
     if (!c || !out) return PIC_EINVAL;
     HIPCHK(c, c->prof.read(c->stream, out));
     return PIC_OK;
+}
+
+pic_status pic_denoiser_set(pic_ctx* c, const float* weights, const float* biases, const float* scale) {
+    if (!c || !weights || !biases || !scale) return PIC_EINVAL;
+    if (c->desc.jpost != PIC_JPOST_DENOISER)
+        return fail(c, PIC_ESTATE, "the grid was not created with the denoiser current post-processing");
+    for (int d = 0; d < 3; ++d)
+        if (!(scale[d] > 0.0f) || !isfinite(scale[d])) return fail(c, PIC_EINVAL, "scales must be positive and finite");
+    const size_t nw1 = 32 * 3 * 27, nw2 = 32 * 32 * 27, nw3 = 3 * 32 * 27;
+    for (size_t i = 0; i < nw1 + nw2 + nw3; ++i)
+        if (!isfinite(weights[i])) return fail(c, PIC_EINVAL, "non-finite weight");
+    for (size_t i = 0; i < 67; ++i)
+        if (!isfinite(biases[i])) return fail(c, PIC_EINVAL, "non-finite bias");
+    // pack: bf16 round to nearest even
+    auto bf = [](float v) -> uint16_t {
+        uint32_t u;
+        memcpy(&u, &v, 4);
+        u += 0x7FFFu + ((u >> 16) & 1u);
+        return (uint16_t)(u >> 16);
+    };
+    std::vector<uint16_t> w((kDnW1 + kDnW2 + kDnW3), 0);
+    uint16_t* w1 = w.data();
+    uint16_t* w2 = w1 + kDnW1;
+    uint16_t* w3 = w2 + kDnW2;
+    const float* W1 = weights;
+    const float* W2 = W1 + nw1;
+    const float* W3 = W2 + nw2;
+    for (int co = 0; co < 32; ++co)
+        for (int ci = 0; ci < 3; ++ci)
+            for (int t = 0; t < 27; ++t) w1[co * 128 + t * 4 + ci] = bf(W1[(co * 3 + ci) * 27 + t]);
+    for (int t = 0; t < 27; ++t)
+        for (int co = 0; co < 32; ++co)
+            for (int ci = 0; ci < 32; ++ci) w2[(t * 32 + co) * 32 + ci] = bf(W2[(co * 32 + ci) * 27 + t]);
+    for (int t = 0; t < 27; ++t)
+        for (int co = 0; co < 3; ++co)
+            for (int ci = 0; ci < 32; ++ci) w3[(t * 16 + co) * 32 + ci] = bf(W3[(co * 32 + ci) * 27 + t]);
+    std::vector<float> b(kDnBias, 0.0f);
+    for (int i = 0; i < 32; ++i) b[i] = biases[i];
+    for (int i = 0; i < 32; ++i) b[32 + i] = biases[32 + i];
+    for (int i = 0; i < 3; ++i) b[64 + i] = biases[64 + i];
+    char* dst = c->ws + c->L.dn_w;
+    const size_t wbytes = w.size() * 2;
+    HIPCHK(c, hipMemcpyAsync(dst, w.data(), wbytes, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(dst + wbytes, b.data(), kDnBias * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    DenoiseWeights& d = c->dn;
+    d.w1 = reinterpret_cast<const __bf16*>(dst);
+    d.w2 = d.w1 + kDnW1;
+    d.w3 = d.w2 + kDnW2;
+    d.b1 = reinterpret_cast<const float*>(dst + wbytes);
+    d.b2 = d.b1 + 32;
+    d.b3 = d.b2 + 32;
+    for (int i = 0; i < 3; ++i) d.scale[i] = scale[i];
+    c->has_dn = true;
+    return PIC_OK;
+}
+
+pic_status pic_current_filter(pic_ctx* c) {
+    if (!c) return PIC_EINVAL;
+    return filter_in_place(c);
 }
 
 const char* pic_last_error(const pic_ctx* c) {

@@ -82,6 +82,27 @@ hipError_t launch_batch_laser(const InstDesc* d, int n, int which, int max_plane
 hipError_t launch_batch_clear(const InstDesc* d, int n, int max_plane, hipStream_t st);
 hipError_t launch_batch_inject(const InstDesc* d, int n, long long max_cand, hipStream_t st);
 
+// Learned current denoiser (pic_denoise.hip).  Packed bf16 weights:
+// w1 [32 out][128] with k = tap * 4 + in (in < 3, tap < 27, else zero);
+// w2 [27 tap][32 out][32 in]; w3 [27 tap][16 out][32 in] (out < 3, else zero);
+// tap = 9 (dz + 1) + 3 (dy + 1) + (dx + 1).  Biases FP32: b1[32], b2[32], b3[16].
+struct DenoiseWeights {
+    const __bf16* w1;
+    const __bf16* w2;
+    const __bf16* w3;
+    const float* b1;
+    const float* b2;
+    const float* b3;
+    float scale[3];
+};
+constexpr size_t kDnW1 = 32 * 128, kDnW2 = 27 * 32 * 32, kDnW3 = 27 * 16 * 32;   // bf16 elements
+constexpr size_t kDnBias = 32 + 32 + 16;                                            // floats
+
+// bc per axis: 0 periodic, 1 zero outside the box, 2 moving window (zero
+// beyond the window's ends).  Jin -> Jout (distinct), h1, h2: [ncell][32] bf16.
+hipError_t launch_denoise(const Geom& g, const int bc[3], const DenoiseWeights& w, float* const Jin[3],
+                          float* const Jout[3], __bf16* h1, __bf16* h2, hipStream_t st);
+
 // window / injection / laser kernels (pic_window.hip)
 hipError_t launch_clear_plane(const Geom& g, const FieldPtrs& f, int ix, hipStream_t st);
 hipError_t launch_inject(const Geom& g, const PlasmaDev& P, const SpeciesDev& s, long long shift, int xb, int xe,

@@ -107,6 +107,9 @@ _SIGS = {
     "pic_sync": (ctypes.c_int, [_vp]),
     "pic_last_error": (ctypes.c_char_p, [_vp]),
     "pic_destroy": (None, [_vp]),
+    "pic_denoiser_set": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
+                                        ctypes.POINTER(ctypes.c_float)]),
+    "pic_current_filter": (ctypes.c_int, [_vp]),
     "pic_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32]),
     "pic_batch_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int32, _vp,
                                         ctypes.c_size_t, _vp]),
@@ -311,6 +314,21 @@ class Simulation:
         p = Profile()
         self._check(lib().pic_profile_read(self.handle, ctypes.byref(p)))
         return {k: getattr(p, k) for k, _ in Profile._fields_}
+
+    # ------------------------------------------------------------ current post-processing
+    def set_denoiser(self, params, scale):
+        """params = (W1 [32,3,3,3,3], b1 [32], W2 [32,32,3,3,3], b2 [32], W3 [3,32,3,3,3], b3 [3])."""
+        W1, b1, W2, b2, W3, b3 = [np.ascontiguousarray(np.asarray(a, dtype=np.float32)) for a in params]
+        assert W1.shape == (32, 3, 3, 3, 3) and W2.shape == (32, 32, 3, 3, 3) and W3.shape == (3, 32, 3, 3, 3)
+        w = np.concatenate([W1.ravel(), W2.ravel(), W3.ravel()]).astype(np.float32)
+        b = np.concatenate([b1.ravel(), b2.ravel(), b3.ravel()]).astype(np.float32)
+        sc = np.ascontiguousarray(np.asarray(scale, dtype=np.float32))
+        fp = ctypes.POINTER(ctypes.c_float)
+        self._check(lib().pic_denoiser_set(self.handle, w.ctypes.data_as(fp), b.ctypes.data_as(fp),
+                                           sc.ctypes.data_as(fp)))
+
+    def current_filter(self):
+        self._check(lib().pic_current_filter(self.handle))
 
     # ------------------------------------------------------------ the cycle
     def gather_push(self, s=0):
