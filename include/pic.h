@@ -390,6 +390,50 @@ const char *pic_batch_last_error(const pic_batch *batch);
  * buffers are untouched).  Synchronises the stream. */
 void pic_batch_destroy(pic_batch *batch);
 
+/* ---- Denoiser training --------------------------------------------------
+ *
+ * Trains the pic_denoiser_set network on pairs of currents: an input J
+ * deposited by few particles per cell and a target J_target deposited by
+ * many (the same plasma), on crops of n[0] x n[1] x n[2] cells with zero
+ * beyond the crop's faces.  Loss: mean over cells and the 3 components of
+ * (y - r)^2, y the network's correction in units of scale (J' = J + scale y),
+ * r = (J_target - J) / scale.  Forward and backward run on the bf16 matrix
+ * cores with FP32 accumulation; parameters are FP32 master weights updated
+ * by Adam (beta1 0.9, beta2 0.999, eps 1e-8), rounded to bf16 for every
+ * convolution.  Weight and bias layouts are those of pic_denoiser_set.
+ */
+typedef struct pic_dn_trainer pic_dn_trainer;
+
+/* Device workspace for crops of crop[3] cells (0 when invalid). */
+size_t pic_dn_trainer_workspace_bytes(const int32_t crop[3]);
+
+/* workspace: caller-owned device buffer, 256-byte aligned, kept until
+ * destroy.  stream: the caller's hipStream_t. */
+pic_status pic_dn_trainer_create(pic_dn_trainer **out, const int32_t crop[3], void *workspace,
+                                 size_t workspace_bytes, void *stream);
+
+/* Load parameters (host, FP32) and scales; resets the optimiser state.
+ * Synchronises. */
+pic_status pic_dn_trainer_set_params(pic_dn_trainer *tr, const float *weights, const float *biases,
+                                     const float *scale);
+
+/* Current FP32 master parameters (host outputs).  Synchronises. */
+pic_status pic_dn_trainer_get_params(pic_dn_trainer *tr, float *weights, float *biases);
+
+/* One Adam step on one crop.  input[3], target[3]: device FP32 component
+ * arrays of n[0]*n[1]*n[2] values (x fastest).  *loss (host, may be NULL)
+ * receives the loss before the update; asynchronous when loss is NULL. */
+pic_status pic_dn_trainer_step(pic_dn_trainer *tr, float *const input[3], float *const target[3], float lr,
+                               double *loss);
+
+/* Loss and gradients without an update (host outputs, pic_denoiser_set
+ * layouts).  Synchronises. */
+pic_status pic_dn_trainer_grad(pic_dn_trainer *tr, float *const input[3], float *const target[3], double *loss,
+                               float *grad_weights, float *grad_biases);
+
+const char *pic_dn_trainer_last_error(const pic_dn_trainer *tr);
+void pic_dn_trainer_destroy(pic_dn_trainer *tr);
+
 #ifdef __cplusplus
 }
 #endif

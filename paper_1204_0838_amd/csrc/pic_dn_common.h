@@ -1,0 +1,162 @@
+// Building blocks of the learned current denoiser's convolutions (inference
+// and training): three 3x3x3 convolution layers on the deposited current, as
+// implicit GEMMs on the bf16 matrix cores (v_mfma_f32_16x16x32_bf16, FP32
+// accumulation).
+//
+//   x  = bf16(J_d / s_d)                    layer 1: 3 (padded to 4) -> 32 channels
+//   a1 = bf16(relu(conv(x, W1) + b1))
+//   a2 = bf16(relu(conv(a1, W2) + b2))      layer 2: 32 -> 32 (84 % of the work)
+//   J'_d = J_d + s_d (conv(a2, W3) + b3)_d  layer 3: 32 -> 3 (padded to 16)
+//
+// conv is the "same"-size 3x3x3 cross-correlation; y and z are periodic, x is
+// periodic or (moving window) zero beyond the window's two ends, or zero
+// outside the box on any axis (training crops).  Activations live in HBM
+// channels-last as bf16 [cell][32] (64 B per cell).
+//
+// One workgroup of 8 wavefronts computes a tile of 16 x 4 x 8 cells (x, y, z)
+// in window coordinates: it stages the tile's input halo (18 x 6 x 10 cells,
+// rows padded to 20) and the layer's weights in LDS, then each wavefront
+// takes one z-plane: 4 rows of 16 cells = 4 MFMA row blocks, times 2 (or 1)
+// blocks of 16 output channels, accumulated over the 27 taps x 32 input
+// channels (one MFMA K-step of 32 per tap).
+//
+// MFMA operand layout (16x16x32): lane l holds A row l%16, K elements
+// 8(l/16)..8(l/16)+7; B column l%16 with the same K elements; the result
+// holds column l%16, rows 4(l/16)..4(l/16)+3.  A row = a cell, K = input
+// channels, B column = an output channel.
+//
+// LDS rows of 64 B (a cell's 32 channels, or a weight row) are stored as four
+// 16-byte chunks rotated by rot(r) = ((r >> 1) ^ (r >> 2)) & 3, so that the 16
+// consecutive rows one A or B read touches spread over all banks.
+#pragma once
+
+#include "pic_internal.h"
+
+namespace pic {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int DN_TX = 16, DN_TY = 4, DN_TZ = 8;        // output tile
+constexpr int DN_HX = 20, DN_HY = DN_TY + 2, DN_HZ = DN_TZ + 2;   // halo tile (x padded)
+constexpr int DN_HCELLS = DN_HX * DN_HY * DN_HZ;
+constexpr int DN_THREADS = 512;
+
+__device__ __forceinline__ int dn_rot(int r) { return ((r >> 1) ^ (r >> 2)) & 3; }
+
+// Byte offset of 16-byte chunk q of 64-byte row r.
+__device__ __forceinline__ int dn_chunk(int r, int q) { return r * 64 + (((q + dn_rot(r)) & 3) << 4); }
+
+// Storage index along one axis of window/box coordinate v, or -1 when the
+// neighbour reads as zero.  bc: 0 periodic, 1 zero outside [0, n), 2 moving
+// window (zero outside [0, n), storage = (v + origin) mod n).
+__device__ __forceinline__ int dn_axis(int v, int n, int bc, int origin) {
+    if (bc == 0) return v < 0 ? v + n : (v >= n ? v - n : v);
+    if (v < 0 || v >= n) return -1;
+    if (bc == 2) {
+        v += origin;
+        return v >= n ? v - n : v;
+    }
+    return v;
+}
+
+struct DnArgs {
+    int n[3];
+    int bc[3];
+    int origin;
+    const float* J[3];        // layer 1 input; layer 3 residual input
+    float* Jout[3];           // layer 3 output
+    const __bf16* act_in;     // 32-channel input [cell][32]
+    __bf16* act_out;          // 32-channel output [cell][32]
+    const __bf16* w;          // packed weights (see the host packing)
+    const float* bias;
+    float scale[3], inv_scale[3];
+    // training
+    const __bf16* c4_in;      // 4-channel input [cell][4] (output gradient of layer 3)
+    const __bf16* mask;       // relu mask source [cell][32] (an activation: > 0 passes)
+    const float* Jt[3];       // target current
+    __bf16* c4_out;           // 4-channel output [cell][4] (loss gradient of y)
+    double* loss;             // += sum of squared errors / (3 N)
+    float grad_scale;         // 2 / (3 N)
+};
+
+// Kernel variants: input of the 4-channel-input shape, and epilogues.
+enum { DN_L1_J_ACT = 0, DN_L1_C4_MASK, DN_L2_ACT, DN_L2_MASK, DN_L3_RESID, DN_L3_LOSS };
+
+// Output tiles of a box of n cells.
+inline dim3 dn_grid(const int n[3]) {
+    return dim3((n[0] + DN_TX - 1) / DN_TX, (n[1] + DN_TY - 1) / DN_TY, (n[2] + DN_TZ - 1) / DN_TZ);
+}
+
+hipError_t launch_dn_layer(int kind, const DnArgs& a, hipStream_t st);
+
+// Tile origin (window coordinates) of this workgroup.
+__device__ __forceinline__ void dn_tile(int t0[3]) {
+    t0[0] = blockIdx.x * DN_TX;
+    t0[1] = blockIdx.y * DN_TY;
+    t0[2] = blockIdx.z * DN_TZ;
+}
+
+// Copy `rows` 64-byte rows of packed weights into LDS (swizzled).
+__device__ __forceinline__ void dn_stage_weights(const __bf16* __restrict__ w, int rows, char* lds) {
+    const uint4* src = reinterpret_cast<const uint4*>(w);
+    for (int g = threadIdx.x; g < rows * 4; g += DN_THREADS)
+        *reinterpret_cast<uint4*>(lds + dn_chunk(g >> 2, g & 3)) = src[g];
+}
+
+// Storage cell index of halo cell (hx, hy, hz) of the tile, or -1 for zero.
+__device__ __forceinline__ int dn_halo_src(const DnArgs& a, const int t0[3], int hx, int hy, int hz) {
+    const int x = dn_axis(t0[0] - 1 + hx, a.n[0], a.bc[0], a.origin);
+    const int y = dn_axis(t0[1] - 1 + hy, a.n[1], a.bc[1], 0);
+    const int z = dn_axis(t0[2] - 1 + hz, a.n[2], a.bc[2], 0);
+    if (x < 0 || y < 0 || z < 0) return -1;
+    return x + a.n[0] * (y + a.n[1] * z);
+}
+
+// Stage a 32-channel bf16 activation halo.
+__device__ __forceinline__ void dn_stage_act(const DnArgs& a, const int t0[3], char* lds) {
+    const uint4* src = reinterpret_cast<const uint4*>(a.act_in);
+    for (int g = threadIdx.x; g < DN_HCELLS * 4; g += DN_THREADS) {
+        const int c = g >> 2, q = g & 3;
+        const int hx = c % DN_HX, r = c / DN_HX, hy = r % DN_HY, hz = r / DN_HY;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (hx < DN_TX + 2) {
+            const int s = dn_halo_src(a, t0, hx, hy, hz);
+            if (s >= 0) v = src[(size_t)s * 4 + q];
+        }
+        *reinterpret_cast<uint4*>(lds + dn_chunk(c, q)) = v;
+    }
+}
+
+// Storage cell of output row block `blk` (y row), lane row m, plane lz; -1 outside the box.
+__device__ __forceinline__ int dn_out_cell(const DnArgs& a, const int t0[3], int lz, int blk, int m) {
+    const int x = t0[0] + m, y = t0[1] + blk, z = t0[2] + lz;
+    if (x >= a.n[0] || y >= a.n[1] || z >= a.n[2]) return -1;
+    const int xs = a.bc[0] == 2 ? (x + a.origin >= a.n[0] ? x + a.origin - a.n[0] : x + a.origin) : x;
+    return xs + a.n[0] * (y + a.n[1] * z);
+}
+
+// Accumulate the 27 taps x 32 input channels of a 32-channel layer.
+template <int NH>
+__device__ __forceinline__ void dn_mma32(const char* act, const char* wl, f32x4 acc[4][NH]) {
+    const int l = threadIdx.x & 63, lz = threadIdx.x >> 6;
+    const int m = l & 15, q = l >> 4;
+#pragma unroll 1
+    for (int tap = 0; tap < 27; ++tap) {
+        const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;   // 0..2 = offset + 1
+        bf16x8 B[NH];
+#pragma unroll
+        for (int h = 0; h < NH; ++h)
+            B[h] = *reinterpret_cast<const bf16x8*>(wl + dn_chunk(tap * 16 * NH + h * 16 + m, q));
+#pragma unroll
+        for (int blk = 0; blk < 4; ++blk) {
+            const int c = ((lz + dz) * DN_HY + (blk + dy)) * DN_HX + (m + dx);
+            const bf16x8 A = *reinterpret_cast<const bf16x8*>(act + dn_chunk(c, q));
+#pragma unroll
+            for (int h = 0; h < NH; ++h) acc[blk][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B[h], acc[blk][h], 0, 0, 0);
+        }
+    }
+}
+
+}  // namespace pic

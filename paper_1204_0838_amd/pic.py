@@ -110,6 +110,18 @@ _SIGS = {
     "pic_denoiser_set": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
                                         ctypes.POINTER(ctypes.c_float)]),
     "pic_current_filter": (ctypes.c_int, [_vp]),
+    "pic_dn_trainer_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(ctypes.c_int32)]),
+    "pic_dn_trainer_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_int32), _vp,
+                                             ctypes.c_size_t, _vp]),
+    "pic_dn_trainer_set_params": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
+                                                 ctypes.POINTER(ctypes.c_float)]),
+    "pic_dn_trainer_get_params": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_float),
+                                                 ctypes.POINTER(ctypes.c_float)]),
+    "pic_dn_trainer_step": (ctypes.c_int, [_vp, _vp * 3, _vp * 3, ctypes.c_float, ctypes.POINTER(ctypes.c_double)]),
+    "pic_dn_trainer_grad": (ctypes.c_int, [_vp, _vp * 3, _vp * 3, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
+    "pic_dn_trainer_last_error": (ctypes.c_char_p, [_vp]),
+    "pic_dn_trainer_destroy": (None, [_vp]),
     "pic_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32]),
     "pic_batch_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int32, _vp,
                                         ctypes.c_size_t, _vp]),
@@ -441,6 +453,96 @@ class Batch:
     def close(self):
         if getattr(self, "handle", None):
             lib().pic_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+N_WEIGHTS = 32 * 3 * 27 + 32 * 32 * 27 + 3 * 32 * 27
+N_BIASES = 32 + 32 + 3
+
+
+def pack_params(params):
+    """(W1, b1, W2, b2, W3, b3) -> flat FP32 (weights, biases) in the pic_denoiser_set layout."""
+    W1, b1, W2, b2, W3, b3 = [np.asarray(a, dtype=np.float32) for a in params]
+    w = np.ascontiguousarray(np.concatenate([W1.ravel(), W2.ravel(), W3.ravel()]), dtype=np.float32)
+    b = np.ascontiguousarray(np.concatenate([b1.ravel(), b2.ravel(), b3.ravel()]), dtype=np.float32)
+    return w, b
+
+
+def unpack_params(w, b):
+    n1, n2 = 32 * 3 * 27, 32 * 32 * 27
+    return [w[:n1].reshape(32, 3, 3, 3, 3), b[:32], w[n1:n1 + n2].reshape(32, 32, 3, 3, 3), b[32:64],
+            w[n1 + n2:].reshape(3, 32, 3, 3, 3), b[64:67]]
+
+
+class DenoiserTrainer:
+    """Adam training of the current denoiser on crops of ``crop`` = (nx, ny, nz) cells."""
+
+    def __init__(self, crop, device="cuda:0", stream=None):
+        self.crop = tuple(int(v) for v in crop)
+        self.device = torch.device(device)
+        c = (ctypes.c_int32 * 3)(*self.crop)
+        nbytes = int(lib().pic_dn_trainer_workspace_bytes(c))
+        if nbytes == 0:
+            raise PicError(PIC_EINVAL, "invalid crop")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        st = lib().pic_dn_trainer_create(ctypes.byref(h), c, ctypes.c_void_p(base + (-base) % 256), nbytes,
+                                         ctypes.c_void_p(self.stream.cuda_stream))
+        if st != PIC_OK:
+            raise PicError(st, "pic_dn_trainer_create failed")
+        self.handle = h
+
+    def _check(self, st):
+        if st != PIC_OK:
+            msg = lib().pic_dn_trainer_last_error(self.handle)
+            raise PicError(st, msg.decode() if msg else "")
+
+    @staticmethod
+    def _arr3(t):
+        assert t.dtype == torch.float32 and t.is_contiguous() and t.shape[0] == 3
+        return (_vp * 3)(*[t[a].data_ptr() for a in range(3)])
+
+    def set_params(self, params, scale):
+        w, b = pack_params(params)
+        sc = np.ascontiguousarray(np.asarray(scale, dtype=np.float32))
+        fp = ctypes.POINTER(ctypes.c_float)
+        self._check(lib().pic_dn_trainer_set_params(self.handle, w.ctypes.data_as(fp), b.ctypes.data_as(fp),
+                                                    sc.ctypes.data_as(fp)))
+
+    def get_params(self):
+        w = np.zeros(N_WEIGHTS, np.float32)
+        b = np.zeros(N_BIASES, np.float32)
+        fp = ctypes.POINTER(ctypes.c_float)
+        self._check(lib().pic_dn_trainer_get_params(self.handle, w.ctypes.data_as(fp), b.ctypes.data_as(fp)))
+        return unpack_params(w, b)
+
+    def step(self, inp, target, lr, want_loss=True):
+        """inp, target: float32 tensors [3, nz, ny, nx] on the device."""
+        loss = ctypes.c_double()
+        self._check(lib().pic_dn_trainer_step(self.handle, self._arr3(inp), self._arr3(target), float(lr),
+                                              ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def grad(self, inp, target):
+        loss = ctypes.c_double()
+        gw = np.zeros(N_WEIGHTS, np.float32)
+        gb = np.zeros(N_BIASES, np.float32)
+        fp = ctypes.POINTER(ctypes.c_float)
+        self._check(lib().pic_dn_trainer_grad(self.handle, self._arr3(inp), self._arr3(target), ctypes.byref(loss),
+                                              gw.ctypes.data_as(fp), gb.ctypes.data_as(fp)))
+        return loss.value, unpack_params(gw, gb)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().pic_dn_trainer_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

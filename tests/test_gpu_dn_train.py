@@ -1,0 +1,89 @@
+"""Denoiser training on the matrix cores: loss and gradients against the
+exact FP64 oracle (the GPU rounds inputs, activations and backward signals
+to bf16, so agreement is to bf16 accuracy, not to round-off), and an Adam
+run that learns a known linear filter."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from tests.helpers import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1204_0838_amd import pic  # noqa: E402
+
+
+def _bf16_array(a):
+    return np.vectorize(O.bf16)(np.asarray(a, dtype=np.float64))
+
+
+def _params(seed, amp=1.0):
+    rng = np.random.default_rng(seed)
+    W1 = amp * rng.standard_normal((32, 3, 3, 3, 3)) / np.sqrt(81.0)
+    W2 = amp * rng.standard_normal((32, 32, 3, 3, 3)) / np.sqrt(864.0)
+    W3 = amp * rng.standard_normal((3, 32, 3, 3, 3)) / np.sqrt(864.0)
+    b1 = 0.1 * rng.standard_normal(32)
+    b2 = 0.1 * rng.standard_normal(32)
+    b3 = 0.05 * rng.standard_normal(3)
+    return [_bf16_array(W1), b1.astype(np.float32).astype(np.float64), _bf16_array(W2),
+            b2.astype(np.float32).astype(np.float64), _bf16_array(W3), b3.astype(np.float32).astype(np.float64)]
+
+
+SCALE = np.array([0.5, 1.0, 2.0])
+
+
+@pytest.mark.parametrize("crop", [(32, 8, 16), (20, 6, 10)])
+def test_trainer_gradients_match_oracle(crop):
+    nx, ny, nz = crop
+    rng = np.random.default_rng(31)
+    J = rng.standard_normal((3, nz, ny, nx)) * SCALE[:, None, None, None]
+    T = J + 0.5 * rng.standard_normal((3, nz, ny, nx)) * SCALE[:, None, None, None]
+    J = J.astype(np.float32)
+    T = T.astype(np.float32)
+    P = _params(32)
+    tr = pic.DenoiserTrainer(crop)
+    tr.set_params(P, SCALE)
+    inp = torch.as_tensor(J).cuda().contiguous()
+    tgt = torch.as_tensor(T).cuda().contiguous()
+    loss, G = tr.grad(inp, tgt)
+    s = SCALE[:, None, None, None]
+    # the network's input is bf16(J / s) by definition; the rest of the
+    # oracle's pass is exact (the GPU rounds activations and backward signals)
+    x = _bf16_array(J.astype(np.float64) / s)
+    r = (T.astype(np.float64) - J.astype(np.float64)) / s
+    ref_loss, ref_G = O.denoise_grad(x, r, P, bc=("zero", "zero", "zero"))
+    assert abs(loss - ref_loss) <= 1e-2 * ref_loss
+    for name, g, gr in zip(("W1", "b1", "W2", "b2", "W3", "b3"), G, ref_G):
+        assert np.all(np.isfinite(g)), name
+        assert rel_l2(g, gr) <= 3e-2, (name, rel_l2(g, gr))
+
+
+def test_training_learns_a_linear_filter():
+    crop = (32, 8, 16)
+    nx, ny, nz = crop
+    rng = np.random.default_rng(41)
+    J = rng.standard_normal((3, nz, ny, nx))
+    w1 = np.array([0.25, 0.5, 0.25])
+    k = np.einsum("i,j,k->ijk", w1, w1, w1)
+    W = np.zeros((3, 3, 3, 3, 3))
+    for c in range(3):
+        W[c, c] = k
+    T = O.conv3d(J, W, bc=("zero", "zero", "zero"))          # target: the binomial filter of J
+    tr = pic.DenoiserTrainer(crop)
+    tr.set_params(_params(42, amp=0.3), [1.0, 1.0, 1.0])
+    inp = torch.as_tensor(J.astype(np.float32)).cuda().contiguous()
+    tgt = torch.as_tensor(T.astype(np.float32)).cuda().contiguous()
+    first = tr.step(inp, tgt, 2e-3)
+    for _ in range(250):
+        last = tr.step(inp, tgt, 2e-3, want_loss=False)
+    last = tr.step(inp, tgt, 2e-3)
+    assert np.isfinite(last) and last < 0.1 * first, (first, last)
+    P = tr.get_params()
+    assert all(np.all(np.isfinite(p)) for p in P)
+    # the learned parameters plug into the production denoiser
+    sim = pic.Simulation(crop, (0.2, 0.2, 0.2), 0.05, jpost="denoiser")
+    sim.set_denoiser(P, [1.0, 1.0, 1.0])
