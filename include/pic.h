@@ -314,7 +314,13 @@ pic_status pic_profile_read(pic_ctx *ctx, pic_profile *out);
  * learned replacement for the binomial filter at few particles per cell.
  *   x  = bf16(J_d / scale_d)
  *   a1 = bf16(relu(conv(x,  W1) + b1)),  a2 = bf16(relu(conv(a1, W2) + b2))
- *   J_d <- J_d + scale_d (conv(a2, W3) + b3)_d
+ *   y  = conv(a2, W3) + b3
+ *   J <- B(J + sigma curl(y)),   sigma = dx (scale_x + scale_y + scale_z) / 3
+ * B is the binomial filter of PIC_JPOST_BINOMIAL and curl the
+ * backward-difference curl of the E update, whose discrete divergence is
+ * zero: the denoised current obeys the same discrete continuity equation as
+ * the binomially filtered one (periodic axes), carries no grid-scale
+ * (Nyquist) modes, and zero W3, b3 give exactly the filter.
  * conv: 3x3x3 cross-correlation, output size = input size; y and z
  * periodic, x periodic or, in a moving window, zero beyond the window's
  * ends.  Weights and activations bf16 (rounded to nearest even), FP32
@@ -396,8 +402,8 @@ void pic_batch_destroy(pic_batch *batch);
  * deposited by few particles per cell and a target J_target deposited by
  * many (the same plasma), on crops of n[0] x n[1] x n[2] cells with zero
  * beyond the crop's faces.  Loss: mean over cells and the 3 components of
- * (y - r)^2, y the network's correction in units of scale (J' = J + scale y),
- * r = (J_target - J) / scale.  Forward and backward run on the bf16 matrix
+ * ((J' - J_target) / scale)^2 with J' the network's output current.
+ * Forward and backward run on the bf16 matrix
  * cores with FP32 accumulation; parameters are FP32 master weights updated
  * by Adam (beta1 0.9, beta2 0.999, eps 1e-8), rounded to bf16 for every
  * convolution.  Weight and bias layouts are those of pic_denoiser_set.
@@ -407,9 +413,10 @@ typedef struct pic_dn_trainer pic_dn_trainer;
 /* Device workspace for crops of crop[3] cells (0 when invalid). */
 size_t pic_dn_trainer_workspace_bytes(const int32_t crop[3]);
 
-/* workspace: caller-owned device buffer, 256-byte aligned, kept until
- * destroy.  stream: the caller's hipStream_t. */
-pic_status pic_dn_trainer_create(pic_dn_trainer **out, const int32_t crop[3], void *workspace,
+/* cell (host): the crops' cell sizes dx, dy, dz.  workspace: caller-owned
+ * device buffer, 256-byte aligned, kept until destroy.  stream: the
+ * caller's hipStream_t. */
+pic_status pic_dn_trainer_create(pic_dn_trainer **out, const int32_t crop[3], const double cell[3], void *workspace,
                                  size_t workspace_bytes, void *stream);
 
 /* Load parameters (host, FP32) and scales; resets the optimiser state.
@@ -426,10 +433,26 @@ pic_status pic_dn_trainer_get_params(pic_dn_trainer *tr, float *weights, float *
 pic_status pic_dn_trainer_step(pic_dn_trainer *tr, float *const input[3], float *const target[3], float lr,
                                double *loss);
 
+/* One Adam step on the mean gradient of a mini-batch of n crops.
+ * inputs, targets: host arrays of 3 n device pointers (crop i's components
+ * at 3 i .. 3 i + 2).  *loss (host, may be NULL): mean loss of the batch
+ * before the update. */
+pic_status pic_dn_trainer_step_batch(pic_dn_trainer *tr, int32_t n, float *const *inputs, float *const *targets,
+                                     float lr, double *loss);
+
+/* Mean loss over n crops (same array convention), no update.  Synchronises. */
+pic_status pic_dn_trainer_eval(pic_dn_trainer *tr, int32_t n, float *const *inputs, float *const *targets,
+                               double *loss);
+
 /* Loss and gradients without an update (host outputs, pic_denoiser_set
  * layouts).  Synchronises. */
 pic_status pic_dn_trainer_grad(pic_dn_trainer *tr, float *const input[3], float *const target[3], double *loss,
                                float *grad_weights, float *grad_biases);
+
+/* freeze != 0: later updates leave the biases at their current values
+ * (with zero biases the network maps J = 0 to no correction and scales
+ * with its input: net(a J) = a net(J) for a > 0). */
+pic_status pic_dn_trainer_freeze_biases(pic_dn_trainer *tr, int32_t freeze);
 
 const char *pic_dn_trainer_last_error(const pic_dn_trainer *tr);
 void pic_dn_trainer_destroy(pic_dn_trainer *tr);

@@ -68,9 +68,11 @@ def lib():
             "ora_step": (i32, [G, i64, _dp, _dp, _dp, dbl, dbl, _dp, _dp, _dp, i32, _dp]),
             "ora_bf16": (dbl, [dbl]),
             "ora_conv3d": (None, [_i64p, _i32p, i64, _dp, i32, _dp, _dp, i32, _dp]),
-            "ora_denoise": (i32, [_i64p, _i32p, i64, _dp, _dp, i32, _dp, _dp, _dp, _dp, _dp, _dp, i32, _dp, _dp]),
-            "ora_denoise_grad": (dbl, [_i64p, _i32p, i64, _dp, _dp, i32, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
-                                       _dp, _dp, _dp]),
+            "ora_denoise": (i32, [_i64p, _i32p, i64, _dp, _dp, _dp, i32, _dp, _dp, _dp, _dp, _dp, _dp, i32, _dp,
+                                  _dp]),
+            "ora_denoise_grad": (dbl, [_i64p, _i32p, i64, _dp, _dp, _dp, _dp, _dp, i32, _dp, _dp, _dp, _dp, _dp, _dp,
+                                       _dp, _dp, _dp, _dp, _dp, _dp]),
+            "ora_denoise_sigma": (dbl, [_dp, _dp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -383,8 +385,8 @@ def conv3d(inp, W, b=None, bc=("periodic",) * 3, origin: int = 0):
     return out
 
 
-def denoise(J, scale, params, bc=("periodic",) * 3, origin: int = 0, round_bf16: bool = True):
-    """(Jout, y) of the three-layer denoiser; J [3, nz, ny, nx]; params = (W1, b1, W2, b2, W3, b3)."""
+def denoise(J, scale, params, d=(1.0, 1.0, 1.0), bc=("periodic",) * 3, origin: int = 0, round_bf16: bool = True):
+    """(Jout, y) of the denoiser; J [3, nz, ny, nx]; params = (W1, b1, W2, b2, W3, b3); d = cell sizes."""
     J = f64(J)
     _, nz, ny, nx = J.shape
     W1, b1, W2, b2, W3, b3 = [f64(a) for a in params]
@@ -393,21 +395,28 @@ def denoise(J, scale, params, bc=("periodic",) * 3, origin: int = 0, round_bf16:
     y = np.zeros_like(J)
     nn, bb = _dims((nx, ny, nz), bc)
     sc = f64(scale)
-    st = lib().ora_denoise(nn, bb, int(origin), _p(J), _p(sc), H, _p(W1), _p(b1), _p(W2), _p(b2), _p(W3), _p(b3),
-                           1 if round_bf16 else 0, _p(Jout), _p(y))
+    dd = f64(d)
+    st = lib().ora_denoise(nn, bb, int(origin), _p(dd), _p(J), _p(sc), H, _p(W1), _p(b1), _p(W2), _p(b2), _p(W3),
+                           _p(b3), 1 if round_bf16 else 0, _p(Jout), _p(y))
     if st != 0:
         raise MemoryError("oracle denoiser")
     return Jout, y
 
 
-def denoise_grad(x, r, params, bc=("zero",) * 3, origin: int = 0):
-    """(loss, grads) of the training loss mean((y - r)^2) at x (scaled input), exact FP64."""
+def denoise_sigma(d, scale) -> float:
+    return lib().ora_denoise_sigma(_p(f64(d)), _p(f64(scale)))
+
+
+def denoise_grad(J, x, T, scale, params, d=(1.0, 1.0, 1.0), bc=("zero",) * 3, origin: int = 0):
+    """(loss, grads) of the training loss mean(((Jout - T) / s)^2); x is the network input (bf16(J/s))."""
+    J = f64(J)
     x = f64(x)
-    r = f64(r)
-    _, nz, ny, nx = x.shape
+    T = f64(T)
+    _, nz, ny, nx = J.shape
     P = [f64(a) for a in params]
     G = [np.zeros_like(a) for a in P]
     H = P[0].shape[0]
     nn, bb = _dims((nx, ny, nz), bc)
-    loss = lib().ora_denoise_grad(nn, bb, int(origin), _p(x), _p(r), H, *[_p(a) for a in P], *[_p(g) for g in G])
+    loss = lib().ora_denoise_grad(nn, bb, int(origin), _p(f64(d)), _p(J), _p(x), _p(T), _p(f64(scale)), H,
+                                  *[_p(a) for a in P], *[_p(g) for g in G])
     return loss, G

@@ -1,0 +1,284 @@
+"""Learned current denoiser at few particles per cell against the plain
+binomial-filtered run at many, on the C1 laser-wakefield geometry.
+
+Steps (every one runs through the HIP library; torch only moves crops):
+
+The denoiser's output is J' = B(J + sigma curl(y)): the binomial filter of
+the current plus a divergence-free learned correction, so the denoised
+current keeps the filtered current's charge balance and, like it, carries
+no grid-scale (Nyquist) modes.
+
+1. Training pairs.  A 32-ppc run (4x4x2 lattice, binomial filter, fused
+   production step) and a 2-ppc run (1x1x2 lattice, split path so its raw
+   current is visible, binomial filter in its field update) advance in
+   lockstep with the same laser and window.  At sampled steps, seeded crops
+   of the window give (input = raw 2-ppc J, target = filtered 32-ppc J).
+2. Training: Adam on the matrix cores (pic_dn_trainer), per-component scale
+   = RMS of the targets.
+3. Evaluation: a 2-ppc run with the trained denoiser (fused step) and a
+   2-ppc run with the binomial filter, both compared with the 32-ppc run on
+   the wake field E_x over the whole window at fixed checkpoints; a second
+   32-ppc run on another sub-cell lattice (2x4x4) gives the noise floor of
+   that comparison.  Throughput: wall-clock steps per second on the same
+   grid (the runs carry 16x different particle counts).
+
+    python -m paper_1204_0838_amd.c4 --out gpurun_out/c4          # full C1 grid, 1000 steps
+    python -m paper_1204_0838_amd.c4 --grid 128,64,64 --steps 200  # small rehearsal
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+PPC32 = (4, 4, 2)
+PPC32_ALT = (2, 4, 4)
+PPC2 = (1, 1, 2)
+
+
+def _log(msg):
+    print(f"# [{time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def _cfg(base, ppc):
+    cfg = dict(base)
+    cfg["plasma"] = dict(base["plasma"], ppc=tuple(ppc))
+    return cfg
+
+
+def _ex_window(sim):
+    """E_x in window order (x index 0 = the window's trailing cell), host float32."""
+    import torch
+
+    _, org = sim.window_state()
+    return torch.roll(sim.E[0], shifts=-org, dims=2).cpu().numpy()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-30))
+
+
+def collect_pairs(base, steps, sample_steps, crop, ncrops, seed):
+    """Lockstep 32-ppc / 2-ppc runs; returns (pairs, 32-ppc E_x checkpoints, 32-ppc ms/step, particles)."""
+    import torch
+
+    from . import workloads
+
+    big = workloads.build(_cfg(base, PPC32), jpost="binomial")
+    small = workloads.build(_cfg(base, PPC2), jpost="binomial", tuned=False)
+    big.profile_enable(True)
+    nx, ny, nz = base["n"]
+    cx, cy, cz = crop
+    rng = np.random.default_rng(seed)
+    per = int(math.ceil(ncrops / max(1, len(sample_steps))))
+    pairs = []
+    ex = {}
+    checkpoints = set(range(100, steps + 1, 100)) | {steps}
+    t0 = time.perf_counter()
+    for st in range(1, steps + 1):
+        _, org_b = big.window_state()    # the step's current is deposited in the frame before its window shift
+        big.step(1)
+        if st % 2 == 0:
+            small.sort(0)          # drops particles that left the window (the split path keeps them)
+        small.gather_push(0)
+        small.deposit(0)
+        if st in sample_steps and len(pairs) < ncrops:
+            _, org_s = small.window_state()
+            jb = torch.roll(big.J, shifts=-org_b, dims=3)
+            js = torch.roll(small.J, shifts=-org_s, dims=3)
+            for _ in range(per):
+                if len(pairs) >= ncrops:
+                    break
+                x0 = int(rng.integers(0, nx - cx + 1))
+                y0 = int(rng.integers(0, ny - cy + 1))
+                z0 = int(rng.integers(0, nz - cz + 1))
+                sl = (slice(None), slice(z0, z0 + cz), slice(y0, y0 + cy), slice(x0, x0 + cx))
+                pairs.append((js[sl].contiguous(), jb[sl].contiguous()))
+        small.field_step()
+        if st in checkpoints:
+            ex[st] = _ex_window(big)
+        if st % 50 == 0:
+            _log(f"pairs run step {st}/{steps}, {len(pairs)} crops, {time.perf_counter() - t0:.0f} s")
+    prof = big.profile_read()
+    ms = sum(prof[k] for k in ("sort_ms", "tile_ms", "loose_ms", "jpost_ms", "field_ms", "window_ms")) / steps
+    n_big = big.reduce()["n_particles"]
+    big.close()
+    small.close()
+    return pairs, ex, ms, n_big
+
+
+def binomial_init(rng, noise=0.3):
+    """Parameters whose network output is the binomial filter: J' = B(J).
+
+    The last layer starts at zero (y = 0, so J' = B(J) exactly); the first
+    two layers start random, giving training features to build on."""
+    W1 = noise * rng.standard_normal((32, 3, 3, 3, 3)) / np.sqrt(81.0)
+    W2 = noise * rng.standard_normal((32, 32, 3, 3, 3)) / np.sqrt(864.0)
+    W3 = np.zeros((3, 32, 3, 3, 3))
+    return [W1, np.zeros(32), W2, np.zeros(32), W3, np.zeros(3)]
+
+
+def train(pairs, crop, cell, epochs, lr, seed, batch=8):
+    """Adam on mini-batches of crops, starting from the binomial filter,
+    with the biases held at zero.
+
+    A seeded tenth of the crops is held out; the parameters with the lowest
+    held-out loss are kept, and the binomial start itself if training never
+    beats it.  Returns (params, scale, history)."""
+    from . import pic
+
+    tgt_rms = np.sqrt(np.mean([[float((t[d] ** 2).mean()) for d in range(3)] for _, t in pairs], axis=0))
+    scale = np.maximum(tgt_rms, 1e-12).astype(np.float32)
+    rng = np.random.default_rng(seed)
+    order = rng.permutation(len(pairs))
+    nval = max(1, len(pairs) // 10)
+    val = [pairs[i] for i in order[:nval]]
+    trn = [pairs[i] for i in order[nval:]]
+    P = binomial_init(rng)
+    tr = pic.DenoiserTrainer(crop, cell=cell)
+    tr.set_params(P, scale)
+    tr.freeze_biases(True)     # zero biases: no correction where J = 0, and net(a J) = a net(J)
+
+    def val_loss():
+        return tr.eval([p[0] for p in val], [p[1] for p in val])
+
+    init = val_loss()
+    best, best_params = init, tr.get_params()
+    hist = {"val_loss_binomial_start": init, "val_loss": [], "train_loss": []}
+    nstep = epochs * ((len(trn) + batch - 1) // batch)
+    k = 0
+    t0 = time.perf_counter()
+    for ep in range(epochs):
+        perm = rng.permutation(len(trn))
+        tl = []
+        for b0 in range(0, len(trn), batch):
+            idx = perm[b0:b0 + batch]
+            frac = k / max(1, nstep)
+            cur = lr if frac < 0.6 else (lr * 0.3 if frac < 0.85 else lr * 0.1)
+            tl.append(tr.step_batch([trn[i][0] for i in idx], [trn[i][1] for i in idx], cur))
+            k += 1
+        v = val_loss()
+        hist["train_loss"].append(float(np.mean(tl)))
+        hist["val_loss"].append(v)
+        if v < best:
+            best, best_params = v, tr.get_params()
+        _log(f"epoch {ep + 1}/{epochs}: train {hist['train_loss'][-1]:.5f}, held-out {v:.5f} "
+             f"(binomial start {init:.5f}), {time.perf_counter() - t0:.0f} s")
+    hist["kept"] = "trained" if best < init else "binomial start"
+    hist["val_loss_kept"] = best
+    tr.close()
+    return best_params, scale, hist
+
+
+def run_eval(base, ppc, jpost, steps, params=None, scale=None, continuity=False):
+    """One run; returns (E_x checkpoints, ms/step, particles, extra)."""
+    import torch
+
+    from . import workloads
+
+    sim = workloads.build(_cfg(base, ppc), jpost=jpost, tuned=(ppc == PPC32))
+    if params is not None:
+        sim.set_denoiser(params, scale)
+    checkpoints = sorted(set(range(100, steps + 1, 100)) | {steps})
+    ex = {}
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    ms = 0.0
+    done = 0
+    t0 = time.perf_counter()
+    for cp in checkpoints:
+        k = cp - done
+        if continuity and cp == checkpoints[-1]:
+            k -= 1
+        e0.record(sim.stream)
+        sim.step(k)
+        e1.record(sim.stream)
+        torch.cuda.synchronize()
+        ms += e0.elapsed_time(e1)
+        done += k
+        if not (continuity and cp == checkpoints[-1]):
+            ex[cp] = _ex_window(sim)
+        _log(f"{jpost} ppc {ppc} step {done}/{steps}, {time.perf_counter() - t0:.0f} s")
+    extra = {}
+    if continuity:
+        # last step by the split path, to measure the continuity residual of the post-processed current
+        sim.gather_push(0)
+        sim.deposit(0)
+        raw = sim.J.clone()
+        sim.current_filter()
+        r, jm = sim.continuity(0)
+        extra = {"continuity_residual": r, "max_abs_J": jm, "ratio": r / jm if jm > 0 else None}
+        sim.J.copy_(raw)           # the field step applies the post-processing itself
+        sim.field_step()
+        done += 1
+        ex[steps] = _ex_window(sim)
+    n = sim.reduce()["n_particles"]
+    sim.close()
+    return ex, ms / (done - (1 if continuity else 0)), n, extra
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--grid", type=str, default="")
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--crops", type=int, default=256)
+    ap.add_argument("--crop", type=str, default="128,64,64")
+    ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--lr", type=float, default=1e-4)
+    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--out", type=str, default="c4_out")
+    ap.add_argument("--no-floor", action="store_true", help="skip the second 32-ppc run (noise floor)")
+    args = ap.parse_args()
+    sys.path.insert(0, os.path.dirname(HERE))
+    from paper_1204_0838_amd import workloads
+
+    base = workloads.C1
+    if args.grid:
+        base = workloads.scaled(base, [int(v) for v in args.grid.split(",")])
+    crop = tuple(int(v) for v in args.crop.split(","))
+    os.makedirs(args.out, exist_ok=True)
+    steps = args.steps
+    sample_steps = set(np.linspace(steps // 20, steps - 1, 24).astype(int).tolist())
+    _log(f"grid {base['n']}, {steps} steps, pairs from steps {min(sample_steps)}..{max(sample_steps)}")
+    pairs, ex32, ms32, n32 = collect_pairs(base, steps, sample_steps, crop, args.crops, seed=5)
+    _log(f"{len(pairs)} training pairs; 32-ppc run {ms32:.1f} ms/step, {n32} particles")
+    t_train = time.perf_counter()
+    params, scale, hist = train(pairs, crop, base["d"], args.epochs, args.lr, seed=6, batch=args.batch)
+    t_train = time.perf_counter() - t_train
+    del pairs
+    np.savez(os.path.join(args.out, "denoiser_params.npz"), W1=params[0], b1=params[1], W2=params[2], b2=params[3],
+             W3=params[4], b3=params[5], scale=scale)
+    exd, msd, nd, cont = run_eval(base, PPC2, "denoiser", steps, params, scale, continuity=True)
+    exb, msb, nb, _ = run_eval(base, PPC2, "binomial", steps)
+    floor = None
+    if not args.no_floor:
+        exf, msf, nf, _ = run_eval(base, PPC32_ALT, "binomial", steps)
+        floor = {str(k): _rel(exf[k], ex32[k]) for k in sorted(exf)}
+    out = {
+        "grid": list(base["n"]), "steps": steps, "crop": list(crop), "crops": args.crops,
+        "epochs": args.epochs, "batch": args.batch, "lr": args.lr, "train_seconds": t_train, "training": hist,
+        "scale": scale.tolist(),
+        "ms_per_step": {"ppc32_binomial": ms32, "ppc2_denoiser": msd, "ppc2_binomial": msb},
+        "particles": {"ppc32": n32, "ppc2_denoiser": nd, "ppc2_binomial": nb},
+        "speedup_steps_per_s_denoised_vs_ppc32": ms32 / msd,
+        "wake_ex_rel_l2_vs_ppc32": {
+            "ppc2_denoiser": {str(k): _rel(exd[k], ex32[k]) for k in sorted(exd)},
+            "ppc2_binomial": {str(k): _rel(exb[k], ex32[k]) for k in sorted(exb)},
+            "ppc32_other_lattice_noise_floor": floor,
+        },
+        "denoised_continuity": cont,
+    }
+    with open(os.path.join(args.out, "c4_summary.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

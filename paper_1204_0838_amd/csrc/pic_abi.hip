@@ -1241,7 +1241,11 @@ pic_status pic_denoiser_set(pic_ctx* c, const float* weights, const float* biase
     d.b1 = reinterpret_cast<const float*>(dst + wbytes);
     d.b2 = d.b1 + 32;
     d.b3 = d.b2 + 32;
-    for (int i = 0; i < 3; ++i) d.scale[i] = scale[i];
+    for (int i = 0; i < 3; ++i) {
+        d.scale[i] = scale[i];
+        d.inv_d[i] = (float)(1.0 / c->desc.d[i]);
+    }
+    d.sigma = (float)(c->desc.d[0] * ((double)scale[0] + scale[1] + scale[2]) / 3.0);
     c->has_dn = true;
     return PIC_OK;
 }

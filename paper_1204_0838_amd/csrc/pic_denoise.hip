@@ -1,9 +1,10 @@
 // Learned current denoiser: the convolution layers of the network described
-// in pic_dn_common.h.  Inference runs layers 1, 2, 3 with the relu and
-// residual epilogues; training reuses the same layer shapes for the gradient
-// of the loss with respect to the activations (a transposed convolution is a
-// convolution with the taps mirrored and the channel roles swapped), with a
-// relu-mask epilogue, and a layer-3 epilogue that forms the loss.
+// in pic_dn_common.h and its output stage J' = B(J + sigma curl(y)).
+// Inference runs layers 1, 2 (relu epilogues) and 3 (y), then the output
+// stage; training reuses the same layer shapes for the gradient of the loss
+// with respect to the activations (a transposed convolution is a
+// convolution with the taps mirrored and the channel roles swapped) with a
+// relu-mask epilogue, and the output stage with the loss.
 #include "pic_dn_common.h"
 
 namespace pic {
@@ -122,10 +123,7 @@ __global__ void __launch_bounds__(DN_THREADS) k_dn_c32(DnArgs a) {
     dn_store32<EPI>(a, t0, acc);
 }
 
-// 32 -> 3 channels (16 computed).  EPI 0: residual J' = J + s (acc + b);
-// EPI 1: loss of y = acc + b against r = (J_target - J) / s, and its
-// gradient 2 (y - r) / (3 N) as bf16 [cell][4] (channel 3 zero).
-template <int EPI>
+// 32 -> 3 channels (16 computed): y = acc + b as FP32 components into a.Jout.
 __global__ void __launch_bounds__(DN_THREADS) k_dn_c3(DnArgs a) {
     extern __shared__ __attribute__((aligned(16))) char dlds[];
     char* act = dlds;
@@ -141,27 +139,143 @@ __global__ void __launch_bounds__(DN_THREADS) k_dn_c3(DnArgs a) {
     dn_mma32<1>(act, wl, acc);
     const int l = threadIdx.x & 63, lz = threadIdx.x >> 6;
     const int co = l & 15, rq = l >> 4;
-    if (co > 3 || (EPI == 0 && co == 3)) return;
-    double part = 0.0;
+    if (co >= 3) return;
+    const float b = a.bias[co];
 #pragma unroll
     for (int blk = 0; blk < 4; ++blk)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int cell = dn_out_cell(a, t0, lz, blk, rq * 4 + j);
-            if (cell < 0) continue;
-            if (EPI == 0) {
-                a.Jout[co][cell] = fmaf(a.scale[co], acc[blk][0][j] + a.bias[co], a.J[co][cell]);
-            } else if (co == 3) {
-                a.c4_out[(size_t)cell * 4 + 3] = (__bf16)0.0f;
-            } else {
-                const float y = acc[blk][0][j] + a.bias[co];
-                const float r = (a.Jt[co][cell] - a.J[co][cell]) * a.inv_scale[co];
-                const float e = y - r;
-                part += (double)e * (double)e;
-                a.c4_out[(size_t)cell * 4 + co] = (__bf16)(a.grad_scale * e);
-            }
+            if (cell >= 0) a.Jout[co][cell] = acc[blk][0][j] + b;
         }
-    if (EPI == 1 && co < 3) atomicAdd(a.loss, part * (0.5 * (double)a.grad_scale));
+}
+
+// Window/box coordinates of cell index i (x fastest), its storage index,
+// and the storage indices of neighbours (-1 = zero).
+struct DnCell {
+    int w[3];
+    int s;
+};
+
+__device__ __forceinline__ int dn_nb(const DnCombine& c, const DnCell& k, int dx, int dy, int dz) {
+    const int x = dn_axis(k.w[0] + dx, c.n[0], c.bc[0], c.origin);
+    const int y = dn_axis(k.w[1] + dy, c.n[1], c.bc[1], 0);
+    const int z = dn_axis(k.w[2] + dz, c.n[2], c.bc[2], 0);
+    if (x < 0 || y < 0 || z < 0) return -1;
+    return x + c.n[0] * (y + c.n[1] * z);
+}
+
+__device__ __forceinline__ bool dn_cell(const DnCombine& c, int i, DnCell& k) {
+    if (i >= c.n[0] * c.n[1] * c.n[2]) return false;
+    k.w[0] = i % c.n[0];
+    const int r = i / c.n[0];
+    k.w[1] = r % c.n[1];
+    k.w[2] = r / c.n[1];
+    k.s = dn_nb(c, k, 0, 0, 0);
+    return true;
+}
+
+__device__ __forceinline__ float dn_at(const float* __restrict__ F, int s) { return s >= 0 ? F[s] : 0.0f; }
+
+// dst = src + sigma curl(y), curl(y)_a = (y_{a+2} - y_{a+2}[-e_{a+1}]) / d_{a+1} - (y_{a+1} - y_{a+1}[-e_{a+2}]) / d_{a+2}.
+__global__ void __launch_bounds__(256) k_dn_curl_add(DnCombine c) {
+    DnCell k;
+    if (!dn_cell(c, blockIdx.x * blockDim.x + threadIdx.x, k)) return;
+    const int off[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+#pragma unroll
+    for (int comp = 0; comp < 3; ++comp) {
+        const int t1 = (comp + 1) % 3, t2 = (comp + 2) % 3;
+        const int m1 = dn_nb(c, k, -off[t1][0], -off[t1][1], -off[t1][2]);
+        const int m2 = dn_nb(c, k, -off[t2][0], -off[t2][1], -off[t2][2]);
+        const float cu = (c.y[t2][k.s] - dn_at(c.y[t2], m1)) * c.inv_d[t1] -
+                         (c.y[t1][k.s] - dn_at(c.y[t1], m2)) * c.inv_d[t2];
+        c.dst[comp][k.s] = fmaf(c.sigma, cu, c.src[comp][k.s]);
+    }
+}
+
+// Binomial filter of src (27-point product stencil, x innermost).
+template <bool LOSS>
+__device__ __forceinline__ void dn_binomial_cell(const DnCombine& c, const DnCell& k, double& part) {
+    const float w[3] = {0.25f, 0.5f, 0.25f};
+    int nb[27];
+#pragma unroll
+    for (int q = 0; q < 27; ++q) nb[q] = dn_nb(c, k, q % 3 - 1, (q / 3) % 3 - 1, q / 9 - 1);
+#pragma unroll
+    for (int comp = 0; comp < 3; ++comp) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int zc = 0; zc < 3; ++zc) {
+            float ay = 0.0f;
+#pragma unroll
+            for (int yb = 0; yb < 3; ++yb) {
+                float ax = 0.0f;
+#pragma unroll
+                for (int xa = 0; xa < 3; ++xa) ax = fmaf(w[xa], dn_at(c.src[comp], nb[(zc * 3 + yb) * 3 + xa]), ax);
+                ay = fmaf(w[yb], ax, ay);
+            }
+            acc = fmaf(w[zc], ay, acc);
+        }
+        if (LOSS) {
+            const float e = (acc - c.T[comp][k.s]) * c.inv_scale[comp];
+            part += (double)e * (double)e;
+            c.dst[comp][k.s] = c.grad_scale * e * c.inv_scale[comp];
+        } else {
+            c.dst[comp][k.s] = acc;
+        }
+    }
+}
+
+template <bool LOSS>
+__global__ void __launch_bounds__(256) k_dn_binomial(DnCombine c) {
+    DnCell k;
+    const bool ok = dn_cell(c, blockIdx.x * blockDim.x + threadIdx.x, k);
+    double part = 0.0;
+    if (ok) dn_binomial_cell<LOSS>(c, k, part);
+    if (LOSS) {   // every lane takes part in the wavefront reduction
+        for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+        if ((threadIdx.x & 63) == 0) atomicAdd(c.loss, part * (0.5 * (double)c.grad_scale));
+    }
+}
+
+// dy = sigma curl^T(src): dy_a = sigma [(src_{a+2}(p + e_{a+1}) - src_{a+2}(p)) / d_{a+1}
+//                                       - (src_{a+1}(p + e_{a+2}) - src_{a+1}(p)) / d_{a+2}]
+// (the forward-difference curl), as bf16 [cell][4] with channel 3 zero.
+__global__ void __launch_bounds__(256) k_dn_curl_adjoint(DnCombine c) {
+    DnCell k;
+    if (!dn_cell(c, blockIdx.x * blockDim.x + threadIdx.x, k)) return;
+    const int off[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    bf16x4 out;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int a1 = (a + 1) % 3, a2 = (a + 2) % 3;
+        const int p1 = dn_nb(c, k, off[a1][0], off[a1][1], off[a1][2]);
+        const int p2 = dn_nb(c, k, off[a2][0], off[a2][1], off[a2][2]);
+        const float v = (dn_at(c.src[a2], p1) - c.src[a2][k.s]) * c.inv_d[a1] -
+                        (dn_at(c.src[a1], p2) - c.src[a1][k.s]) * c.inv_d[a2];
+        out[a] = (__bf16)(c.sigma * v);
+    }
+    out[3] = (__bf16)0.0f;
+    reinterpret_cast<bf16x4*>(c.dy)[k.s] = out;
+}
+
+static dim3 dn_cells_grid(const DnCombine& c) { return dim3((c.n[0] * c.n[1] * c.n[2] + 255) / 256); }
+
+hipError_t launch_dn_curl_add(const DnCombine& c, hipStream_t st) {
+    hipLaunchKernelGGL(k_dn_curl_add, dn_cells_grid(c), dim3(256), 0, st, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_dn_binomial(const DnCombine& c, bool loss, hipStream_t st) {
+    if (loss)
+        hipLaunchKernelGGL(k_dn_binomial<true>, dn_cells_grid(c), dim3(256), 0, st, c);
+    else
+        hipLaunchKernelGGL(k_dn_binomial<false>, dn_cells_grid(c), dim3(256), 0, st, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_dn_curl_adjoint(const DnCombine& c, hipStream_t st) {
+    hipLaunchKernelGGL(k_dn_curl_adjoint, dn_cells_grid(c), dim3(256), 0, st, c);
+    return hipGetLastError();
 }
 
 static size_t dn_lds(int cout) { return (size_t)DN_HCELLS * 64 + (size_t)27 * cout * 64; }
@@ -182,8 +296,7 @@ hipError_t launch_dn_layer(int kind, const DnArgs& a, hipStream_t st) {
         case DN_L1_C4_MASK: return dn_launch(k_dn_c4<1, 1>, 0, a, st);
         case DN_L2_ACT: return dn_launch(k_dn_c32<0>, dn_lds(32), a, st);
         case DN_L2_MASK: return dn_launch(k_dn_c32<1>, dn_lds(32), a, st);
-        case DN_L3_RESID: return dn_launch(k_dn_c3<0>, dn_lds(16), a, st);
-        case DN_L3_LOSS: return dn_launch(k_dn_c3<1>, dn_lds(16), a, st);
+        case DN_L3_Y: return dn_launch(k_dn_c3, dn_lds(16), a, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -195,7 +308,6 @@ hipError_t launch_denoise(const Geom& g, const int bc[3], const DenoiseWeights& 
         a.n[d] = g.n[d];
         a.bc[d] = bc[d];
         a.J[d] = Jin[d];
-        a.Jout[d] = Jout[d];
         a.scale[d] = w.scale[d];
         a.inv_scale[d] = 1.0f / w.scale[d];
     }
@@ -211,11 +323,36 @@ hipError_t launch_denoise(const Geom& g, const int bc[3], const DenoiseWeights& 
     a.bias = w.b2;
     e = launch_dn_layer(DN_L2_ACT, a, st);
     if (e != hipSuccess) return e;
+    // y (3 FP32 components) reuses the first activation buffer
+    const size_t N = (size_t)g.ncell;
+    float* y = reinterpret_cast<float*>(h1);
     a.act_in = h2;
     a.act_out = nullptr;
     a.w = w.w3;
     a.bias = w.b3;
-    return launch_dn_layer(DN_L3_RESID, a, st);
+    for (int d = 0; d < 3; ++d) a.Jout[d] = y + d * N;
+    e = launch_dn_layer(DN_L3_Y, a, st);
+    if (e != hipSuccess) return e;
+    // t = J + sigma curl(y) in the second activation buffer, then J' = B(t)
+    float* t = reinterpret_cast<float*>(h2);
+    DnCombine c{};
+    for (int d = 0; d < 3; ++d) {
+        c.n[d] = g.n[d];
+        c.bc[d] = bc[d];
+        c.src[d] = Jin[d];
+        c.y[d] = y + d * N;
+        c.dst[d] = t + d * N;
+        c.inv_d[d] = w.inv_d[d];
+    }
+    c.origin = a.origin;
+    c.sigma = w.sigma;
+    e = launch_dn_curl_add(c, st);
+    if (e != hipSuccess) return e;
+    for (int d = 0; d < 3; ++d) {
+        c.src[d] = t + d * N;
+        c.dst[d] = Jout[d];
+    }
+    return launch_dn_binomial(c, false, st);
 }
 
 }  // namespace pic

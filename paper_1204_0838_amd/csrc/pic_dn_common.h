@@ -82,7 +82,34 @@ struct DnArgs {
 };
 
 // Kernel variants: input of the 4-channel-input shape, and epilogues.
-enum { DN_L1_J_ACT = 0, DN_L1_C4_MASK, DN_L2_ACT, DN_L2_MASK, DN_L3_RESID, DN_L3_LOSS };
+// DN_L3_Y writes y = conv(a2, W3) + b3 as FP32 components into Jout.
+enum { DN_L1_J_ACT = 0, DN_L1_C4_MASK, DN_L2_ACT, DN_L2_MASK, DN_L3_Y };
+
+// Output stage J' = B(J + sigma curl(y)) (backward-difference curl, binomial
+// filter B), and for training the loss against a target and the gradient.
+struct DnCombine {
+    int n[3];
+    int bc[3];
+    int origin;
+    const float* src[3];    // curl_add: J;   binomial: its input
+    const float* y[3];
+    float* dst[3];          // curl_add: J + sigma curl(y);  binomial: B(src) (or the loss gradient)
+    float sigma;
+    float inv_d[3];
+    // training
+    const float* T[3];
+    float inv_scale[3];
+    float grad_scale;       // 2 / (3 N)
+    double* loss;
+    __bf16* dy;             // sigma curl^T(src) as bf16 [cell][4]
+};
+
+// dst = src + sigma curl(y)
+hipError_t launch_dn_curl_add(const DnCombine& c, hipStream_t st);
+// dst = B(src); with loss: J' = B(src) against T, dst = dL/dJ' = grad_scale (J' - T) / s^2
+hipError_t launch_dn_binomial(const DnCombine& c, bool loss, hipStream_t st);
+// dy = sigma curl^T(src)
+hipError_t launch_dn_curl_adjoint(const DnCombine& c, hipStream_t st);
 
 // Output tiles of a box of n cells.
 inline dim3 dn_grid(const int n[3]) {

@@ -1,9 +1,10 @@
 // Training of the learned current denoiser on the matrix cores.
 //
 // One training step on a crop of the current (zero beyond the crop's faces):
-//   forward   a1 = bf16(relu(conv(x, W1) + b1)), a2 = ..., y = conv(a2, W3) + b3
-//   loss      mean over cells and 3 channels of (y - r)^2, r = (J_target - J) / s
-//   backward  dy = 2 (y - r) / (3 N)
+//   forward   a1 = bf16(relu(conv(x, W1) + b1)), a2 = ..., y = conv(a2, W3) + b3,
+//             J' = B(J + sigma curl(y))
+//   loss      mean over cells and 3 components of ((J' - J_target) / s)^2
+//   backward  g = dL/dJ' = 2 (J' - J_target) / (3 N s^2), dy = sigma curl^T(B g)
 //             dW3 = sum_cells dy x a2(shifted),   dz2 = conv^T(dy, W3) . [a2 > 0]
 //             dW2 = sum_cells dz2 x a1(shifted),  dz1 = conv^T(dz2, W2) . [a1 > 0]
 //             dW1 = sum_cells dz1 x x(shifted)
@@ -195,12 +196,12 @@ __device__ __forceinline__ int grad_index(int i) {
 // and FP32 kernel biases of every parameter.
 __global__ void k_dn_adam_pack(float* __restrict__ P, float* __restrict__ M, float* __restrict__ V,
                                const float* __restrict__ G, __bf16* __restrict__ K, float* __restrict__ Bk, float lr,
-                               float c1, float c2) {
+                               float c1, float c2, float gscale, int train_bias) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= kP_N) return;
     float p = P[i];
-    if (lr > 0.0f) {
-        const float g = G[grad_index(i)];
+    if (lr > 0.0f && (train_bias || i < kP_B1)) {
+        const float g = G[grad_index(i)] * gscale;
         const float m = 0.9f * M[i] + 0.1f * g;
         const float v = 0.999f * V[i] + 0.001f * g * g;
         M[i] = m;
@@ -250,7 +251,7 @@ constexpr size_t kAl = 256;
 size_t al(size_t v) { return (v + kAl - 1) / kAl * kAl; }
 
 struct TrLayout {
-    size_t P, M, V, G, K, Bk, loss, a1, a2, dy, dz2, dz1, total;
+    size_t P, M, V, G, K, Bk, loss, a1, a2, dy, dz2, dz1, y, g, t, total;
 };
 
 TrLayout tr_layout(const int32_t c[3]) {
@@ -274,6 +275,9 @@ TrLayout tr_layout(const int32_t c[3]) {
     L.dy = take(N * 8);
     L.dz2 = take(N * 64);
     L.dz1 = take(N * 64);
+    L.y = take(N * 12);
+    L.g = take(N * 12);
+    L.t = take(N * 12);
     L.total = o;
     return L;
 }
@@ -286,8 +290,10 @@ struct pic_dn_trainer {
     char* ws;
     TrLayout L;
     float scale[3];
+    double cell[3];
     int64_t steps = 0;
     bool has_params = false;
+    bool train_bias = true;
     std::string err;
 };
 
@@ -340,12 +346,17 @@ hipError_t wgrad(pic_dn_trainer* t, const WgArgs& w) {
     return hipGetLastError();
 }
 
-// Forward, loss and gradients of one crop (input, target: device FP32 SoA).
-pic_status tr_grad(pic_dn_trainer* t, float* const in[3], float* const target[3]) {
+// Forward, loss and (unless forward_only) gradients of one crop (input,
+// target: device FP32 SoA), added to the accumulated loss and gradient;
+// `zero` clears them first.
+pic_status tr_grad(pic_dn_trainer* t, float* const in[3], float* const target[3], bool zero = true,
+                   bool forward_only = false) {
     const int ng = kG_N;
-    hipLaunchKernelGGL(k_dn_zero, dim3((ng + 255) / 256), dim3(256), 0, t->st, at<float>(t, t->L.G), ng,
-                       at<double>(t, t->L.loss));
-    THIPCHK(t, hipGetLastError());
+    if (zero) {
+        hipLaunchKernelGGL(k_dn_zero, dim3((ng + 255) / 256), dim3(256), 0, t->st, at<float>(t, t->L.G), ng,
+                           at<double>(t, t->L.loss));
+        THIPCHK(t, hipGetLastError());
+    }
     const __bf16* K = at<__bf16>(t, t->L.K);
     const float* Bk = at<float>(t, t->L.Bk);
     __bf16 *a1 = at<__bf16>(t, t->L.a1), *a2 = at<__bf16>(t, t->L.a2), *dy = at<__bf16>(t, t->L.dy);
@@ -357,8 +368,43 @@ pic_status tr_grad(pic_dn_trainer* t, float* const in[3], float* const target[3]
     THIPCHK(t, launch_dn_layer(DN_L1_J_ACT, a, t->st));
     a.w = K + kK_W2, a.bias = Bk + 32, a.act_in = a1, a.act_out = a2;
     THIPCHK(t, launch_dn_layer(DN_L2_ACT, a, t->st));
-    a.w = K + kK_W3, a.bias = Bk + 64, a.act_in = a2, a.act_out = nullptr, a.c4_out = dy;
-    THIPCHK(t, launch_dn_layer(DN_L3_LOSS, a, t->st));
+    const size_t N = (size_t)t->n[0] * t->n[1] * t->n[2];
+    float* y = at<float>(t, t->L.y);
+    float* gJ = at<float>(t, t->L.g);
+    a.w = K + kK_W3, a.bias = Bk + 64, a.act_in = a2, a.act_out = nullptr;
+    for (int d = 0; d < 3; ++d) a.Jout[d] = y + d * N;
+    THIPCHK(t, launch_dn_layer(DN_L3_Y, a, t->st));
+    // t = J + sigma curl(y);  J' = B(t);  loss;  g = dL/dJ';  dy = sigma curl^T(B g)
+    float* tb = at<float>(t, t->L.t);
+    DnCombine c{};
+    for (int d = 0; d < 3; ++d) {
+        c.n[d] = t->n[d];
+        c.bc[d] = 1;
+        c.src[d] = in[d];
+        c.y[d] = y + d * N;
+        c.dst[d] = tb + d * N;
+        c.T[d] = target[d];
+        c.inv_scale[d] = 1.0f / t->scale[d];
+        c.inv_d[d] = (float)(1.0 / t->cell[d]);
+    }
+    c.sigma = (float)(t->cell[0] * ((double)t->scale[0] + t->scale[1] + t->scale[2]) / 3.0);
+    c.grad_scale = a.grad_scale;
+    c.loss = a.loss;
+    c.dy = dy;
+    THIPCHK(t, launch_dn_curl_add(c, t->st));
+    for (int d = 0; d < 3; ++d) {
+        c.src[d] = tb + d * N;
+        c.dst[d] = gJ + d * N;
+    }
+    THIPCHK(t, launch_dn_binomial(c, true, t->st));
+    if (forward_only) return PIC_OK;
+    for (int d = 0; d < 3; ++d) {
+        c.src[d] = gJ + d * N;
+        c.dst[d] = tb + d * N;
+    }
+    THIPCHK(t, launch_dn_binomial(c, false, t->st));     // B is symmetric: B^T g = B g
+    for (int d = 0; d < 3; ++d) c.src[d] = tb + d * N;
+    THIPCHK(t, launch_dn_curl_adjoint(c, t->st));
     // backward
     WgArgs w{};
     for (int d = 0; d < 3; ++d) {
@@ -382,7 +428,7 @@ pic_status tr_grad(pic_dn_trainer* t, float* const in[3], float* const target[3]
     return PIC_OK;
 }
 
-pic_status tr_pack(pic_dn_trainer* t, float lr) {
+pic_status tr_pack(pic_dn_trainer* t, float lr, float gscale = 1.0f) {
     float c1 = 1.0f, c2 = 1.0f;
     if (lr > 0.0f) {
         t->steps += 1;
@@ -391,7 +437,7 @@ pic_status tr_pack(pic_dn_trainer* t, float lr) {
     }
     hipLaunchKernelGGL(k_dn_adam_pack, dim3((kP_N + 255) / 256), dim3(256), 0, t->st, at<float>(t, t->L.P),
                        at<float>(t, t->L.M), at<float>(t, t->L.V), at<float>(t, t->L.G), at<__bf16>(t, t->L.K),
-                       at<float>(t, t->L.Bk), lr, c1, c2);
+                       at<float>(t, t->L.Bk), lr, c1, c2, gscale, t->train_bias ? 1 : 0);
     THIPCHK(t, hipGetLastError());
     return PIC_OK;
 }
@@ -411,11 +457,13 @@ size_t pic_dn_trainer_workspace_bytes(const int32_t crop[3]) {
     return tr_layout(crop).total;
 }
 
-pic_status pic_dn_trainer_create(pic_dn_trainer** out, const int32_t crop[3], void* workspace,
+pic_status pic_dn_trainer_create(pic_dn_trainer** out, const int32_t crop[3], const double cell[3], void* workspace,
                                  size_t workspace_bytes, void* stream) {
     if (!out) return PIC_EINVAL;
     *out = nullptr;
-    if (!crop || !valid_crop(crop) || !workspace) return PIC_EINVAL;
+    if (!crop || !valid_crop(crop) || !cell || !workspace) return PIC_EINVAL;
+    for (int d = 0; d < 3; ++d)
+        if (!(cell[d] > 0.0) || !isfinite(cell[d])) return PIC_EINVAL;
     if ((reinterpret_cast<uintptr_t>(workspace) & (kAl - 1)) != 0) return PIC_EINVAL;
     const TrLayout L = tr_layout(crop);
     if (workspace_bytes < L.total) return PIC_ENOMEM;
@@ -424,6 +472,7 @@ pic_status pic_dn_trainer_create(pic_dn_trainer** out, const int32_t crop[3], vo
     for (int d = 0; d < 3; ++d) {
         t->n[d] = crop[d];
         t->scale[d] = 1.0f;
+        t->cell[d] = cell[d];
     }
     t->st = reinterpret_cast<hipStream_t>(stream);
     t->ws = reinterpret_cast<char*>(workspace);
@@ -489,6 +538,43 @@ pic_status pic_dn_trainer_step(pic_dn_trainer* t, float* const input[3], float* 
     return PIC_OK;
 }
 
+pic_status pic_dn_trainer_step_batch(pic_dn_trainer* t, int32_t n, float* const* inputs, float* const* targets,
+                                     float lr, double* loss) {
+    if (!t || n < 1 || !inputs || !targets) return PIC_EINVAL;
+    for (int32_t i = 0; i < 3 * n; ++i)
+        if (!inputs[i] || !targets[i]) return PIC_EINVAL;
+    if (!t->has_params) return tfail(t, PIC_ESTATE, "parameters not set");
+    if (!(lr > 0.0f) || !isfinite(lr)) return tfail(t, PIC_EINVAL, "learning rate must be positive");
+    for (int32_t i = 0; i < n; ++i) {
+        pic_status s = tr_grad(t, inputs + 3 * i, targets + 3 * i, i == 0);
+        if (s != PIC_OK) return s;
+    }
+    if (loss) THIPCHK(t, hipMemcpyAsync(loss, t->ws + t->L.loss, 8, hipMemcpyDeviceToHost, t->st));
+    pic_status s = tr_pack(t, lr, 1.0f / (float)n);
+    if (s != PIC_OK) return s;
+    if (loss) {
+        THIPCHK(t, hipStreamSynchronize(t->st));
+        *loss /= (double)n;
+    }
+    return PIC_OK;
+}
+
+pic_status pic_dn_trainer_eval(pic_dn_trainer* t, int32_t n, float* const* inputs, float* const* targets,
+                               double* loss) {
+    if (!t || n < 1 || !inputs || !targets || !loss) return PIC_EINVAL;
+    for (int32_t i = 0; i < 3 * n; ++i)
+        if (!inputs[i] || !targets[i]) return PIC_EINVAL;
+    if (!t->has_params) return tfail(t, PIC_ESTATE, "parameters not set");
+    for (int32_t i = 0; i < n; ++i) {
+        pic_status s = tr_grad(t, inputs + 3 * i, targets + 3 * i, i == 0, true);
+        if (s != PIC_OK) return s;
+    }
+    THIPCHK(t, hipMemcpyAsync(loss, t->ws + t->L.loss, 8, hipMemcpyDeviceToHost, t->st));
+    THIPCHK(t, hipStreamSynchronize(t->st));
+    *loss /= (double)n;
+    return PIC_OK;
+}
+
 pic_status pic_dn_trainer_grad(pic_dn_trainer* t, float* const input[3], float* const target[3], double* loss,
                                float* grad_weights, float* grad_biases) {
     if (!t || !input || !target || !loss || !grad_weights || !grad_biases) return PIC_EINVAL;
@@ -513,6 +599,12 @@ pic_status pic_dn_trainer_grad(pic_dn_trainer* t, float* const input[3], float* 
     for (int i = 0; i < 32; ++i) grad_biases[i] = g[kG_B1 + i];
     for (int i = 0; i < 32; ++i) grad_biases[32 + i] = g[kG_B2 + i];
     for (int i = 0; i < 3; ++i) grad_biases[64 + i] = g[kG_B3 + i];
+    return PIC_OK;
+}
+
+pic_status pic_dn_trainer_freeze_biases(pic_dn_trainer* t, int32_t freeze) {
+    if (!t) return PIC_EINVAL;
+    t->train_bias = freeze == 0;
     return PIC_OK;
 }
 

@@ -82,7 +82,8 @@ hipError_t launch_batch_laser(const InstDesc* d, int n, int which, int max_plane
 hipError_t launch_batch_clear(const InstDesc* d, int n, int max_plane, hipStream_t st);
 hipError_t launch_batch_inject(const InstDesc* d, int n, long long max_cand, hipStream_t st);
 
-// Learned current denoiser (pic_denoise.hip).  Packed bf16 weights:
+// Learned current denoiser (pic_denoise.hip): J' = B(J + sigma curl(net(J / s))).
+// Packed bf16 weights:
 // w1 [32 out][128] with k = tap * 4 + in (in < 3, tap < 27, else zero);
 // w2 [27 tap][32 out][32 in]; w3 [27 tap][16 out][32 in] (out < 3, else zero);
 // tap = 9 (dz + 1) + 3 (dy + 1) + (dx + 1).  Biases FP32: b1[32], b2[32], b3[16].
@@ -94,6 +95,8 @@ struct DenoiseWeights {
     const float* b2;
     const float* b3;
     float scale[3];
+    float sigma;      // output stage J' = B(J + sigma curl(y)), sigma = dx (s_x + s_y + s_z) / 3
+    float inv_d[3];
 };
 constexpr size_t kDnW1 = 32 * 128, kDnW2 = 27 * 32 * 32, kDnW3 = 27 * 16 * 32;   // bf16 elements
 constexpr size_t kDnBias = 32 + 32 + 16;                                            // floats

@@ -111,8 +111,8 @@ _SIGS = {
                                         ctypes.POINTER(ctypes.c_float)]),
     "pic_current_filter": (ctypes.c_int, [_vp]),
     "pic_dn_trainer_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(ctypes.c_int32)]),
-    "pic_dn_trainer_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_int32), _vp,
-                                             ctypes.c_size_t, _vp]),
+    "pic_dn_trainer_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_int32),
+                                             ctypes.POINTER(ctypes.c_double), _vp, ctypes.c_size_t, _vp]),
     "pic_dn_trainer_set_params": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
                                                  ctypes.POINTER(ctypes.c_float)]),
     "pic_dn_trainer_get_params": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_float),
@@ -120,6 +120,11 @@ _SIGS = {
     "pic_dn_trainer_step": (ctypes.c_int, [_vp, _vp * 3, _vp * 3, ctypes.c_float, ctypes.POINTER(ctypes.c_double)]),
     "pic_dn_trainer_grad": (ctypes.c_int, [_vp, _vp * 3, _vp * 3, ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
+    "pic_dn_trainer_step_batch": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                                 ctypes.c_float, ctypes.POINTER(ctypes.c_double)]),
+    "pic_dn_trainer_eval": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                           ctypes.POINTER(ctypes.c_double)]),
+    "pic_dn_trainer_freeze_biases": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "pic_dn_trainer_last_error": (ctypes.c_char_p, [_vp]),
     "pic_dn_trainer_destroy": (None, [_vp]),
     "pic_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32]),
@@ -481,9 +486,9 @@ def unpack_params(w, b):
 
 
 class DenoiserTrainer:
-    """Adam training of the current denoiser on crops of ``crop`` = (nx, ny, nz) cells."""
+    """Adam training of the current denoiser on crops of ``crop`` = (nx, ny, nz) cells of size ``cell``."""
 
-    def __init__(self, crop, device="cuda:0", stream=None):
+    def __init__(self, crop, cell=(1.0, 1.0, 1.0), device="cuda:0", stream=None):
         self.crop = tuple(int(v) for v in crop)
         self.device = torch.device(device)
         c = (ctypes.c_int32 * 3)(*self.crop)
@@ -494,7 +499,8 @@ class DenoiserTrainer:
         base = self.workspace.data_ptr()
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
-        st = lib().pic_dn_trainer_create(ctypes.byref(h), c, ctypes.c_void_p(base + (-base) % 256), nbytes,
+        cd = (ctypes.c_double * 3)(*[float(v) for v in cell])
+        st = lib().pic_dn_trainer_create(ctypes.byref(h), c, cd, ctypes.c_void_p(base + (-base) % 256), nbytes,
                                          ctypes.c_void_p(self.stream.cuda_stream))
         if st != PIC_OK:
             raise PicError(st, "pic_dn_trainer_create failed")
@@ -530,6 +536,31 @@ class DenoiserTrainer:
         self._check(lib().pic_dn_trainer_step(self.handle, self._arr3(inp), self._arr3(target), float(lr),
                                               ctypes.byref(loss) if want_loss else None))
         return loss.value if want_loss else None
+
+    @staticmethod
+    def _ptrs(ts):
+        out = []
+        for t in ts:
+            assert t.dtype == torch.float32 and t.is_contiguous() and t.shape[0] == 3
+            out += [t[a].data_ptr() for a in range(3)]
+        return (_vp * len(out))(*out)
+
+    def step_batch(self, inps, targets, lr, want_loss=True):
+        """One Adam step on the mean gradient over lists of crops."""
+        loss = ctypes.c_double()
+        self._check(lib().pic_dn_trainer_step_batch(self.handle, len(inps), self._ptrs(inps), self._ptrs(targets),
+                                                    float(lr), ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def eval(self, inps, targets):
+        """Mean loss over lists of crops."""
+        loss = ctypes.c_double()
+        self._check(lib().pic_dn_trainer_eval(self.handle, len(inps), self._ptrs(inps), self._ptrs(targets),
+                                              ctypes.byref(loss)))
+        return loss.value
+
+    def freeze_biases(self, freeze=True):
+        self._check(lib().pic_dn_trainer_freeze_biases(self.handle, 1 if freeze else 0))
 
     def grad(self, inp, target):
         loss = ctypes.c_double()

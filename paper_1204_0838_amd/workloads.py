@@ -63,7 +63,8 @@ def initial_particles(cfg: dict) -> int:
     return cells_x * ny * nz * ppc
 
 
-def build(cfg: dict, capacity_factor: float = 1.05, device="cuda:0", tuned: bool = True, **tiling):
+def build(cfg: dict, capacity_factor: float = 1.05, device="cuda:0", tuned: bool = True, jpost: str = "none",
+          **tiling):
     """A Simulation holding the workload at t = 0 (plasma loaded, laser and window set).
 
     Tiling: explicit keyword arguments, else the autotuner's cached choice
@@ -79,7 +80,7 @@ def build(cfg: dict, capacity_factor: float = 1.05, device="cuda:0", tuned: bool
     # counts them all) with headroom for electrons swept along with the window
     cap = int((nx - 3) * ny * nz * ppc * capacity_factor) + 4 * ny * nz * ppc
     sim = pic.Simulation(cfg["n"], cfg["d"], cfg["dt"], solver=cfg["solver"], bc_x=1, max_particles=cap,
-                         device=device, **tiling)
+                         device=device, jpost=jpost, **tiling)
     sim.add_empty_species(cap)
     sim.set_plasma(0, p["x_start"], p["ramp"], p["n_plateau"], p["ppc"])
     sim.inject_plasma(0, 0, nx - 3)

@@ -45,7 +45,8 @@ def test_trainer_gradients_match_oracle(crop):
     J = J.astype(np.float32)
     T = T.astype(np.float32)
     P = _params(32)
-    tr = pic.DenoiserTrainer(crop)
+    d = (0.25, 0.5, 0.4)
+    tr = pic.DenoiserTrainer(crop, cell=d)
     tr.set_params(P, SCALE)
     inp = torch.as_tensor(J).cuda().contiguous()
     tgt = torch.as_tensor(T).cuda().contiguous()
@@ -54,36 +55,46 @@ def test_trainer_gradients_match_oracle(crop):
     # the network's input is bf16(J / s) by definition; the rest of the
     # oracle's pass is exact (the GPU rounds activations and backward signals)
     x = _bf16_array(J.astype(np.float64) / s)
-    r = (T.astype(np.float64) - J.astype(np.float64)) / s
-    ref_loss, ref_G = O.denoise_grad(x, r, P, bc=("zero", "zero", "zero"))
+    ref_loss, ref_G = O.denoise_grad(J.astype(np.float64), x, T.astype(np.float64), SCALE, P, d=d,
+                                     bc=("zero", "zero", "zero"))
     assert abs(loss - ref_loss) <= 1e-2 * ref_loss
     for name, g, gr in zip(("W1", "b1", "W2", "b2", "W3", "b3"), G, ref_G):
         assert np.all(np.isfinite(g)), name
         assert rel_l2(g, gr) <= 3e-2, (name, rel_l2(g, gr))
 
 
-def test_training_learns_a_linear_filter():
+def test_training_learns_a_divergence_free_correction():
+    """Target: B(J) + sigma curl(J / s), which the network reaches with an
+    identity path (relu(x) - relu(-x)); training from a small random start
+    must cut the loss tenfold."""
     crop = (32, 8, 16)
     nx, ny, nz = crop
+    d = (0.25, 0.5, 0.5)
     rng = np.random.default_rng(41)
     J = rng.standard_normal((3, nz, ny, nx))
-    w1 = np.array([0.25, 0.5, 0.25])
-    k = np.einsum("i,j,k->ijk", w1, w1, w1)
-    W = np.zeros((3, 3, 3, 3, 3))
+    D = np.zeros((3, 3, 3))
+    D[1, 1, 1] = 1.0
+    Pid = [np.zeros((32, 3, 3, 3, 3)), np.zeros(32), np.zeros((32, 32, 3, 3, 3)), np.zeros(32),
+           np.zeros((3, 32, 3, 3, 3)), np.zeros(3)]
     for c in range(3):
-        W[c, c] = k
-    T = O.conv3d(J, W, bc=("zero", "zero", "zero"))          # target: the binomial filter of J
-    tr = pic.DenoiserTrainer(crop)
+        Pid[0][c, c] = D
+        Pid[0][3 + c, c] = -D
+        Pid[2][c, c] = D
+        Pid[2][3 + c, 3 + c] = D
+        Pid[4][c, c] = D
+        Pid[4][c, 3 + c] = -D
+    T, _ = O.denoise(J, [1.0, 1.0, 1.0], Pid, d=d, bc=("zero", "zero", "zero"), round_bf16=False)
+    tr = pic.DenoiserTrainer(crop, cell=d)
     tr.set_params(_params(42, amp=0.3), [1.0, 1.0, 1.0])
     inp = torch.as_tensor(J.astype(np.float32)).cuda().contiguous()
     tgt = torch.as_tensor(T.astype(np.float32)).cuda().contiguous()
     first = tr.step(inp, tgt, 2e-3)
-    for _ in range(250):
-        last = tr.step(inp, tgt, 2e-3, want_loss=False)
+    for _ in range(300):
+        tr.step(inp, tgt, 2e-3, want_loss=False)
     last = tr.step(inp, tgt, 2e-3)
     assert np.isfinite(last) and last < 0.1 * first, (first, last)
     P = tr.get_params()
     assert all(np.all(np.isfinite(p)) for p in P)
     # the learned parameters plug into the production denoiser
-    sim = pic.Simulation(crop, (0.2, 0.2, 0.2), 0.05, jpost="denoiser")
+    sim = pic.Simulation(crop, d, 0.1, jpost="denoiser")
     sim.set_denoiser(P, [1.0, 1.0, 1.0])

@@ -2,8 +2,9 @@
 than by the oracle itself: bfloat16 rounding of known values, the
 convolution theorem (FFT) for periodic and zero-padded cross-correlation, a
 shifted delta kernel, the separable binomial kernel against the (separately
-pinned) binomial current filter, the moving-window seam, the residual
-identity, and finite differences of the training loss for every gradient."""
+pinned) binomial current filter, the moving-window seam, the binomial filter
+as the zero-correction network, the vanishing divergence of the correction,
+and finite differences of the training loss for every gradient."""
 import numpy as np
 import pytest
 
@@ -107,14 +108,53 @@ def _params(rng, H, amp=0.3):
             amp * rng.standard_normal((3, H, 3, 3, 3)), 0.1 * rng.standard_normal(3)]
 
 
-def test_residual_identity_with_zero_last_layer():
+def test_zero_last_layer_is_the_binomial_filter():
     rng = np.random.default_rng(6)
     P = _params(rng, 4)
     P[4][:] = 0.0
     P[5][:] = 0.0
     J = rng.standard_normal((3, 3, 4, 5))
+    g = O.make_grid((5, 4, 3), (0.2, 0.2, 0.2), 0.05)
     Jout, y = O.denoise(J, [2.0, 3.0, 0.5], P)
-    assert np.array_equal(Jout, J) and not y.any()
+    assert np.abs(Jout - O.binomial(g, J)).max() < 1e-14 and not y.any()
+
+
+@pytest.mark.parametrize("bc", [("periodic",) * 3])
+def test_correction_is_divergence_free(bc):
+    """The backward-difference divergence (the continuity equation's) of Jout - B(J) vanishes."""
+    rng = np.random.default_rng(9)
+    P = _params(rng, 4)
+    d = (0.25, 0.5, 0.4)
+    J = rng.standard_normal((3, 5, 6, 7))
+    Jout, y = O.denoise(J, [1.0, 2.0, 0.5], P, d=d, bc=bc)
+    P0 = [a.copy() for a in P]
+    P0[4][:] = 0.0
+    P0[5][:] = 0.0
+    Jb, _ = O.denoise(J, [1.0, 2.0, 0.5], P0, d=d, bc=bc)
+    C = Jout - Jb
+    assert np.abs(C).max() > 0.1
+    div = np.zeros(C.shape[1:])
+    for a, axis in ((0, 2), (1, 1), (2, 0)):      # component a varies along array axis `axis` of [z, y, x]
+        prev = np.roll(C[a], 1, axis=axis)
+        if bc[a] == "zero":
+            sl = [slice(None)] * 3
+            sl[axis] = 0
+            prev[tuple(sl)] = 0.0
+        div += (C[a] - prev) / d[a]
+    assert np.abs(div).max() < 1e-12 * np.abs(C).max() / min(d)
+
+
+def test_correction_has_no_nyquist_content():
+    """B removes the (pi, ., .) modes of the correction (checked on an even periodic grid)."""
+    rng = np.random.default_rng(10)
+    P = _params(rng, 4)
+    J = rng.standard_normal((3, 4, 6, 8))
+    Jout, _ = O.denoise(J, [1.0, 1.0, 1.0], P, d=(0.25, 0.5, 0.5))
+    for axis in (1, 2, 3):
+        sign = (-1.0) ** np.arange(J.shape[axis])
+        shape = [1, 1, 1, 1]
+        shape[axis] = -1
+        assert np.abs((Jout * sign.reshape(shape)).sum(axis=axis)).max() < 1e-12
 
 
 def test_denoise_rounds_input_and_scales_output():
@@ -138,16 +178,19 @@ def test_training_gradients_match_finite_differences():
     rng = np.random.default_rng(8)
     H = 3
     P = _params(rng, H)
-    x = rng.standard_normal((3, 3, 3, 4))
-    r = rng.standard_normal((3, 3, 3, 4))
+    J = rng.standard_normal((3, 3, 3, 4))
+    T = rng.standard_normal((3, 3, 3, 4))
+    s = np.array([0.7, 1.0, 1.4])
+    d = (0.25, 0.5, 0.4)
     bc = ("zero", "zero", "zero")
-    loss, G = O.denoise_grad(x, r, P, bc=bc)
+    x = J / s[:, None, None, None]
+    loss, G = O.denoise_grad(J, x, T, s, P, d=d, bc=bc)
 
     def fwd(Q):
-        _, y = O.denoise(x, [1.0, 1.0, 1.0], Q, bc=bc, round_bf16=False)
-        return np.mean((y - r) ** 2)
+        Jout, _ = O.denoise(J, s, Q, d=d, bc=bc, round_bf16=False)
+        return np.mean(((Jout - T) / s[:, None, None, None]) ** 2)
 
-    assert abs(fwd(P) - loss) < 1e-14 * max(1.0, loss)
+    assert abs(fwd(P) - loss) < 1e-13 * max(1.0, loss)
     h = 1e-6
     worst = 0.0
     for k, A in enumerate(P):
