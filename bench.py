@@ -32,7 +32,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 
 
-def cpu_baseline(cfg, crop=(64, 32, 32), steps=4):
+def cpu_baseline(cfg, crop=(64, 32, 32), steps=12):
     """Oracle gather+push+deposit rate on a crop of the workload (one thread)."""
     import numpy as np
 
@@ -166,6 +166,68 @@ def bench_c3(args):
     print(json.dumps(out), flush=True)
 
 
+DN_FLOP_PER_CELL = 2 * (27 * 3) * 32 + 2 * (27 * 32) * 32 + 2 * (27 * 32) * 3   # three conv layers (65,664)
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+
+
+def bench_c4(args):
+    """C4: the C1 geometry at 2 ppc with the learned current denoiser in every
+    step (W warm-up + K timed steps).  The roofline line is the denoiser's:
+    algorithmic conv flops per step over its measured time, against the dense
+    bf16 matrix-core peak.  Weights: the binomial start (zero last layer) with
+    random first layers -- the matrix-core work does not depend on the values."""
+    import numpy as np
+    import torch
+
+    from paper_1204_0838_amd import c4, workloads
+
+    cfg = c4._cfg(workloads.C1, c4.PPC2)
+    sim = workloads.build(cfg, jpost="denoiser", tuned=False)
+    sim.set_denoiser(c4.binomial_init(np.random.default_rng(0)), [0.01, 0.01, 0.01])
+    sim.step(args.warmup)
+    sim.sync()
+    n0 = sim.reduce()["n_particles"]
+    sim.profile_enable(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(sim.stream)
+    left = args.steps
+    while left > 0:
+        k = min(100, left)
+        sim.step(k)
+        left -= k
+        print(f"# {args.steps - left}/{args.steps} steps", file=sys.stderr, flush=True)
+    e1.record(sim.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    prof = sim.profile_read()
+    n1 = sim.reduce()["n_particles"]
+    npart = 0.5 * (n0 + n1)
+    ncell = cfg["n"][0] * cfg["n"][1] * cfg["n"][2]
+    K = args.steps
+    dn_ms = prof["jpost_ms"] / max(1, prof["steps"])
+    achieved = DN_FLOP_PER_CELL * ncell / (dn_ms * 1e-3) / 1e12
+    out = {
+        "metric": "steps/s of the 2-ppc denoised run (C4), denoiser matrix-core throughput",
+        "value": npart * K / (ms * 1e-3),
+        "unit": "particle-steps/s",
+        "n_gpus": 1, "steps": K, "warmup": args.warmup, "ms_per_step": ms / K, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16 conv / f32 PIC", "data": "synthetic",
+        "config": {"workload": "C4: C1 geometry 512x256x256 at 2 ppc (1x1x2 lattice) with the learned current "
+                               "denoiser (3x3x3 conv 3-32-32-3, bf16 MFMA) in every step",
+                   "particles": int(npart), "cells": ncell},
+        "phase_ms_per_step": {k[:-3]: prof[k] / max(1, prof["steps"]) for k in
+                              ("sort_ms", "tile_ms", "loose_ms", "jpost_ms", "field_ms", "window_ms")},
+        "roofline": {"bound": "mfma", "kernel": "denoiser (k_dn_c4, k_dn_c32, k_dn_c3 + output stage)",
+                     "achieved": achieved, "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / BF16_MFMA_PEAK_TFLOPS, "traffic": None,
+                     "alg_flop_per_step": DN_FLOP_PER_CELL * ncell, "mean_denoiser_ms": dn_ms},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,8 +240,9 @@ def main():
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-json", type=str, default="", help="per-launch HBM bytes from rocprofv3 counters")
-    ap.add_argument("--workload", type=str, default="c1", choices=["c1", "c3"],
-                    help="c1 (default): the LWFA slab; c3: the batched 64-member parameter scan")
+    ap.add_argument("--workload", type=str, default="c1", choices=["c1", "c3", "c4"],
+                    help="c1 (default): the LWFA slab; c3: the batched 64-member parameter scan; "
+                         "c4: the 2-ppc run with the learned denoiser")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 5 device copies of 1 GiB (reference for the FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
@@ -203,6 +266,11 @@ def main():
         if args.steps == 995:
             args.steps = 195
         bench_c3(args)
+        return
+    if args.workload == "c4":
+        if args.steps == 995:
+            args.steps = 200
+        bench_c4(args)
         return
 
     from paper_1204_0838_amd import workloads

@@ -85,6 +85,8 @@ __device__ __forceinline__ bool moved(const int c0[3], const int c1[3], const fl
 // Callers skip particles that did not move (every contribution is zero).
 template <class Emit>
 __device__ __forceinline__ void esirkepov(const Axis5 A[3], float qw, Emit& em) {
+    // (qw Y) 2^40 == (qw 2^40) Y bit for bit: scaling by a power of two is exact
+    const float qw40 = qw * PIC_FIX_SCALE;
     float M[3][5];
 #pragma unroll
     for (int d = 0; d < 3; ++d)
@@ -106,7 +108,7 @@ __device__ __forceinline__ void esirkepov(const Axis5 A[3], float qw, Emit& em) 
             for (int b = 0; b < 5; ++b) {
                 if (b >= lb) continue;
                 const float Y = fmaf(A[t1].dS[b] * A[t2].dS[cc], 1.0f / 12.0f, M[t1][b] * M[t2][cc]);
-                const float qy = (qw * Y) * 0x1p40f;
+                const float qy = qw40 * Y;
 #pragma unroll
                 for (int a = 0; a < 4; ++a) {
                     if (a >= la) continue;

@@ -90,24 +90,30 @@ __device__ __noinline__ int push_deposit_global(const Geom& g, const FieldPtrs& 
 }
 
 // Body of the fused step for one tile (the whole workgroup cooperates).
-template <int NT>
-__device__ __forceinline__ void tile_body(const Geom& g, const TileGeom& t, int guard, const FieldPtrs& f,
+// TX, TY, TZ > 0 and GD >= 0 fix the tile shape and guard at compile time:
+// every LDS stride is then a constant and each particle's current atomics
+// and field reads address LDS as one base register plus immediate offsets.
+// 0 (-1 for GD) takes them from t and guard_rt.
+template <int NT, int TX = 0, int TY = 0, int TZ = 0, int GD = -1>
+__device__ __forceinline__ void tile_body(const Geom& g, const TileGeom& t, int guard_rt, const FieldPtrs& f,
                                           const SpeciesDev& s, const int* __restrict__ toff,
                                           unsigned long long* __restrict__ acc, int* __restrict__ d_err,
                                           unsigned long long* lds_u64, int tile) {
+    const int T[3] = {TX > 0 ? TX : t.T[0], TY > 0 ? TY : t.T[1], TZ > 0 ? TZ : t.T[2]};
+    const int guard = GD >= 0 ? GD : guard_rt;
     const int tz = tile / (t.nt[0] * t.nt[1]);
     const int tr = tile - tz * t.nt[0] * t.nt[1];
     const int ty = tr / t.nt[0];
     const int tx = tr - ty * t.nt[0];
-    const int t0[3] = {tx * t.T[0], ty * t.T[1], tz * t.T[2]};
+    const int t0[3] = {tx * T[0], ty * T[1], tz * T[2]};
     int te[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) te[d] = min(t.T[d], g.n[d] - t0[d]);
+    for (int d = 0; d < 3; ++d) te[d] = min(T[d], g.n[d] - t0[d]);
     const int H = guard + 2;
     // LDS geometry (region sizes use the full tile size T, ragged tiles use part of it)
-    const int fx = t.T[0] + 2 * H, fy = t.T[1] + 2 * H, fz = t.T[2] + 2 * H;
+    const int fx = T[0] + 2 * H, fy = T[1] + 2 * H, fz = T[2] + 2 * H;
     const int fr = fx * fy * fz;
-    const int jx = t.T[0] + 2 * guard + 5, jy = t.T[1] + 2 * guard + 5, jz = t.T[2] + 2 * guard + 5;
+    const int jx = T[0] + 2 * guard + 5, jy = T[1] + 2 * guard + 5, jz = T[2] + 2 * guard + 5;
     const int jr = jx * jy * jz;
     unsigned long long* Jl = lds_u64;
     float* Fl = reinterpret_cast<float*>(lds_u64 + 3 * jr);
@@ -242,14 +248,14 @@ __device__ __forceinline__ void tile_body(const Geom& g, const TileGeom& t, int 
     }
 }
 
-template <int NT>
+template <int NT, int TX = 0, int TY = 0, int TZ = 0, int GD = -1>
 __global__ void __launch_bounds__(NT) k_pic_tile(Geom g, TileGeom t, int guard, FieldPtrs f, SpeciesDev s,
                                                  const int* __restrict__ toff, unsigned long long* __restrict__ acc,
                                                  int* __restrict__ d_err) {
     extern __shared__ unsigned long long lds_u64[];
     const int tile = xcd_tile(blockIdx.x, t.ntiles);
     if (tile >= t.ntiles) return;
-    tile_body<NT>(g, t, guard, f, s, toff, acc, d_err, lds_u64, tile);
+    tile_body<NT, TX, TY, TZ, GD>(g, t, guard, f, s, toff, acc, d_err, lds_u64, tile);
 }
 
 // Batched form: the work list is the concatenation of every member's tiles
@@ -317,26 +323,42 @@ size_t tile_lds_bytes(const TileGeom& t, int guard) {
     return 3 * jr * 8 + 6 * fr * 4;
 }
 
-template <int NT>
+template <int NT, int TX = 0, int TY = 0, int TZ = 0, int GD = -1>
 static hipError_t launch_tile_nt(const Geom& g, const TileGeom& t, int guard, const FieldPtrs& f,
                                  const SpeciesDev& s, const int* toff, unsigned long long* acc,
                                  int* d_err, hipStream_t st) {
     const size_t lds = tile_lds_bytes(t, guard);
     const int nb = ((t.ntiles + 7) / 8) * 8;
-    hipError_t e = hipFuncSetAttribute((const void*)k_pic_tile<NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
+    hipError_t e = hipFuncSetAttribute((const void*)k_pic_tile<NT, TX, TY, TZ, GD>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_pic_tile<NT>, dim3(nb), dim3(NT), lds, st, g, t, guard, f, s, toff, acc, d_err);
+    hipLaunchKernelGGL((k_pic_tile<NT, TX, TY, TZ, GD>), dim3(nb), dim3(NT), lds, st, g, t, guard, f, s, toff, acc,
+                       d_err);
     return hipGetLastError();
+}
+
+// Tile shapes with a compile-time specialisation (the library default and
+// the autotuner's usual picks); every other shape runs the general body.
+template <int NT>
+static hipError_t launch_tile_shape(const Geom& g, const TileGeom& t, int guard, const FieldPtrs& f,
+                                    const SpeciesDev& s, const int* toff, unsigned long long* acc, int* d_err,
+                                    hipStream_t st) {
+    if (t.T[0] == 8 && t.T[1] == 8 && t.T[2] == 8) {
+        if (guard == 1) return launch_tile_nt<NT, 8, 8, 8, 1>(g, t, guard, f, s, toff, acc, d_err, st);
+        if (guard == 0) return launch_tile_nt<NT, 8, 8, 8, 0>(g, t, guard, f, s, toff, acc, d_err, st);
+    }
+    if (t.T[0] == 8 && t.T[1] == 8 && t.T[2] == 4 && guard == 1)
+        return launch_tile_nt<NT, 8, 8, 4, 1>(g, t, guard, f, s, toff, acc, d_err, st);
+    return launch_tile_nt<NT>(g, t, guard, f, s, toff, acc, d_err, st);
 }
 
 hipError_t launch_pic_tile(const Geom& g, const TileGeom& t, int guard, int threads, const FieldPtrs& f,
                            const SpeciesDev& s, const int* toff, unsigned long long* acc,
                            int* d_err, hipStream_t st) {
     switch (threads) {
-        case 256: return launch_tile_nt<256>(g, t, guard, f, s, toff, acc, d_err, st);
-        case 1024: return launch_tile_nt<1024>(g, t, guard, f, s, toff, acc, d_err, st);
-        default: return launch_tile_nt<512>(g, t, guard, f, s, toff, acc, d_err, st);
+        case 256: return launch_tile_shape<256>(g, t, guard, f, s, toff, acc, d_err, st);
+        case 1024: return launch_tile_shape<1024>(g, t, guard, f, s, toff, acc, d_err, st);
+        default: return launch_tile_shape<512>(g, t, guard, f, s, toff, acc, d_err, st);
     }
 }
 
