@@ -149,19 +149,28 @@ __device__ __forceinline__ void tile_body(const Geom& g, const TileGeom& t, int 
     // current particle is processed
     int pn = pb + (int)threadIdx.x, celln = -1;
     float oxn = 0.f, oyn = 0.f, ozn = 0.f, uxn = 0.f, uyn = 0.f, uzn = 0.f, wn = 0.f;
-    if ((int)threadIdx.x < n) {
+    if (NT < 1024 && (int)threadIdx.x < n) {
         celln = s.cell[pn];
         oxn = s.off[0][pn], oyn = s.off[1][pn], ozn = s.off[2][pn];
         uxn = s.u[0][pn], uyn = s.u[1][pn], uzn = s.u[2][pn];
         wn = s.w[pn];
     }
     for (int q = threadIdx.x; q < n; q += NT) {
+        if (NT >= 1024) {
+            pn = pb + q;
+            celln = s.cell[pn];
+            oxn = s.off[0][pn], oyn = s.off[1][pn], ozn = s.off[2][pn];
+            uxn = s.u[0][pn], uyn = s.u[1][pn], uzn = s.u[2][pn];
+            wn = s.w[pn];
+        }
         const int p = pn;
         const int cell = celln;
         float o[3] = {oxn, oyn, ozn};
         float u[3] = {uxn, uyn, uzn};
         const float wq = s.mq * wn;
-        if (q + NT < n) {
+        // (1024-thread workgroups keep four waves per SIMD; there the hardware
+        // hides the load latency and the prefetch registers would spill)
+        if (NT < 1024 && q + NT < n) {
             pn = p + NT;
             celln = s.cell[pn];
             oxn = s.off[0][pn], oyn = s.off[1][pn], ozn = s.off[2][pn];

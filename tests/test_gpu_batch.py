@@ -110,3 +110,15 @@ def test_batch_rejects_mismatched_members():
         pic.Batch([a, b])          # b has no species
     with pytest.raises(pic.PicError):
         pic.Batch([a, a])          # the same member twice
+
+
+def test_batch_rejects_denoiser_members():
+    g = inputs.Grid((16, 8, 8), (0.2, 0.2, 0.2), 0.05)
+    sims = []
+    for jpost in ("none", "denoiser"):
+        s = pic.Simulation(g.n, g.d, g.dt, jpost=jpost, max_particles=g.ncells)
+        s.add_particles(inputs.uniform_random_plasma(g, ppc=1, seed=3))
+        sims.append(s)
+    b = pic.Batch(sims)
+    with pytest.raises(pic.PicError):
+        b.step(1)

@@ -98,3 +98,26 @@ def test_training_learns_a_divergence_free_correction():
     # the learned parameters plug into the production denoiser
     sim = pic.Simulation(crop, d, 0.1, jpost="denoiser")
     sim.set_denoiser(P, [1.0, 1.0, 1.0])
+
+
+def test_batched_step_and_eval_agree_with_single_crop_losses():
+    crop = (32, 8, 16)
+    rng = np.random.default_rng(51)
+    pairs = []
+    for _ in range(3):
+        J = rng.standard_normal((3, 16, 8, 32)).astype(np.float32)
+        T = (J + 0.3 * rng.standard_normal(J.shape)).astype(np.float32)
+        pairs.append((torch.as_tensor(J).cuda().contiguous(), torch.as_tensor(T).cuda().contiguous()))
+    tr = pic.DenoiserTrainer(crop, cell=(0.25, 0.5, 0.5))
+    tr.set_params(_params(52), SCALE)
+    single = [tr.grad(a, b)[0] for a, b in pairs]
+    ev = tr.eval([a for a, _ in pairs], [b for _, b in pairs])
+    assert abs(ev - np.mean(single)) <= 1e-9 * max(1.0, ev)
+    before = tr.step_batch([a for a, _ in pairs], [b for _, b in pairs], 1e-3)
+    assert abs(before - ev) <= 1e-9 * max(1.0, ev)
+    after = tr.eval([a for a, _ in pairs], [b for _, b in pairs])
+    assert after < before                     # one Adam step on the mean gradient lowers the mean loss
+    tr.freeze_biases(True)
+    b0 = tr.get_params()[1].copy()
+    tr.step_batch([a for a, _ in pairs], [b for _, b in pairs], 1e-3)
+    assert np.array_equal(tr.get_params()[1], b0)
