@@ -180,7 +180,7 @@ typedef struct {
 typedef struct {
     double sort_ms;      /* cell sorts */
     double tile_ms;      /* fused tiled gather + push + deposit launches */
-    double loose_ms;     /* particles appended since the last sort */
+    double loose_ms;     /* rest pass: particles beyond their tile's guard or appended since the last sort */
     double jpost_ms;     /* current read-out and post-processing */
     double field_ms;     /* B half step, E step, B half step (+ laser source) */
     double window_ms;    /* window motion and plasma injection */

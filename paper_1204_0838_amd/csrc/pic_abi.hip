@@ -150,7 +150,6 @@ struct Species {
     pic_species_bufs alt;    // the other set
     int64_t base;            // offset into per-particle workspace arrays
     int64_t bound;           // host upper bound of the particle count
-    int64_t loose;           // host upper bound of particles appended since the last sort
     int64_t sort_step;       // step of the last sort
     bool sorted;             // tile ranges valid
     bool prev_valid;         // x^n of the last split gather_push kept
@@ -450,13 +449,10 @@ pic_status field_update(pic_ctx* c, float* const Juse[3]) {
 
 // Exact particle count of a species (synchronises); refreshes the host bounds.
 pic_status refresh_bound(pic_ctx* c, int32_t s) {
-    int v[2] = {0, 0};
-    HIPCHK(c, hipMemcpyAsync(&v[0], &small_of(c)->count[s], sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(&v[1], &small_of(c)->sorted[s], sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    int v = 0;
+    HIPCHK(c, hipMemcpyAsync(&v, &small_of(c)->count[s], sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    Species& sp = c->sp[s];
-    sp.bound = v[0];
-    if (sp.sorted) sp.loose = v[0] - v[1] > 0 ? v[0] - v[1] : 0;
+    c->sp[s].bound = v;
     return PIC_OK;
 }
 
@@ -474,7 +470,6 @@ pic_status inject_slab(pic_ctx* c, int32_t s, int32_t xb, int32_t xe) {
     HIPCHK(c, launch_inject(c->g, P, dev_of(c, sp), (long long)c->shift, xb, xe, &small_of(c)->count[s],
                             (int)sp.user.capacity, &small_of(c)->err, c->stream));
     sp.bound += most;
-    sp.loose += most;
     return PIC_OK;
 }
 
@@ -514,7 +509,6 @@ pic_status sort_species(pic_ctx* c, int32_t s) {
     std::swap(sp.cur, sp.alt);
     sp.sorted = true;
     sp.sort_step = c->step;
-    sp.loose = 0;
     sp.prev_valid = false;
     return PIC_OK;
 }
@@ -727,7 +721,7 @@ pic_status bend(pic_batch* b, int phase, hipEvent_t e) {
 }
 
 // One step of every member: per species sort (members due), tiled step and
-// loose particles; then current read-out, field update with laser planes and
+// rest pass; then current read-out, field update with laser planes and
 // window motion with injection.  The host bookkeeping mirrors pic_step.
 pic_status batch_one_step(pic_batch* b) {
     const int n = (int)b->m.size();
@@ -736,7 +730,7 @@ pic_status batch_one_step(pic_batch* b) {
     for (int32_t s = 0; s < b->nsp; ++s) {
         int total = 0;
         PICCHK(upload_tables(b, s, &dtab, &dbegin, &total));
-        int max_sort = 0, max_keys1 = 0, max_tiles1 = 0, max_loose = 0;
+        int max_sort = 0, max_keys1 = 0, max_tiles1 = 0, max_count = 0;
         bool any_sort = false;
         size_t lds = 0;
         for (int i = 0; i < n; ++i) {
@@ -751,10 +745,9 @@ pic_status batch_one_step(pic_batch* b) {
                 std::swap(sp.cur, sp.alt);
                 sp.sorted = true;
                 sp.sort_step = c->step;
-                sp.loose = 0;
             }
             sp.prev_valid = false;
-            max_loose = (int)std::max<int64_t>(max_loose, sp.loose);
+            max_count = (int)std::max<int64_t>(max_count, sp.bound);
             lds = std::max(lds, tile_lds_bytes(c->tl.t, c->tl.guard));
         }
         hipEvent_t t0, t1, t2;
@@ -768,9 +761,9 @@ pic_status batch_one_step(pic_batch* b) {
         BHIPCHK(b, launch_batch_tile(dtab, dbegin, n, total, b->m[0]->tl.threads, lds, b->stream));
         PICCHK(bend(b, PH_TILE, t1));
         if (b->prof.on) b->prof.tiles += 1;
-        if (max_loose > 0) {
+        if (max_count > 0) {
             PICCHK(bmark(b, &t2));
-            BHIPCHK(b, launch_batch_loose(dtab, n, max_loose, b->stream));
+            BHIPCHK(b, launch_batch_rest(dtab, n, max_count, b->stream));
             PICCHK(bend(b, PH_LOOSE, t2));
         }
         // the window phase below needs each species' table; keep species 0's
@@ -821,7 +814,6 @@ pic_status batch_one_step(pic_batch* b) {
                                      i, s, (long long)sp.bound, (long long)most, (long long)sp.user.capacity);
                 }
                 sp.bound += most;
-                sp.loose += most;
                 max_cand = std::max<long long>(max_cand, most);
                 any = true;
             }
@@ -933,7 +925,6 @@ pic_status pic_init_species(pic_ctx* c, const pic_species_bufs* bufs, int64_t n,
     s.cur = *bufs;
     s.base = c->pused;
     s.bound = n;
-    s.loose = 0;
     s.sort_step = 0;
     s.sorted = false;
     s.prev_valid = false;
@@ -1005,12 +996,10 @@ pic_status pic_step(pic_ctx* c, int32_t nsteps) {
                                       toff_of(c, s), acc_of(c), &sm->err, c->stream));
             PICCHK(prof_end(c, PH_TILE, t1));
             if (c->prof.on) c->prof.tiles += 1;
-            if (sp.loose > 0) {
-                PICCHK(prof_mark(c, &t2));
-                HIPCHK(c, launch_push_deposit_range(c->g, fields_of(c), dev_of(c, sp), &sm->sorted[s],
-                                                    &sm->count[s], (int)sp.loose, acc_of(c), &sm->err, c->stream));
-                PICCHK(prof_end(c, PH_LOOSE, t2));
-            }
+            PICCHK(prof_mark(c, &t2));
+            HIPCHK(c, launch_tile_rest(c->g, fields_of(c), dev_of(c, sp), &sm->sorted[s], &sm->count[s],
+                                       (int)sp.bound, acc_of(c), &sm->err, c->stream));
+            PICCHK(prof_end(c, PH_LOOSE, t2));
             sp.prev_valid = false;
         }
         PICCHK(finish_step(c));

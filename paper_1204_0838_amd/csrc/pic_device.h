@@ -65,17 +65,18 @@ struct PrevDev {
 // device error flags (bit set)
 enum { ERR_CFL = 1, ERR_NONFINITE = 2, ERR_OVERFLOW = 4 };
 
-// round(x) as int64, round-half-even, for |x| < 2^51 (x is a current
-// contribution already scaled by 2^40, so the result is round(v * 2^40)).
-// Adding the exact double of x to M = 1.5 * 2^52, where doubles are spaced
-// exactly 1 apart, rounds once, half to even, to an integer; that integer is
-// the difference of the bit patterns of the sum and of M (same exponent while
-// |x| < 2^51).  Three VALU instructions instead of a general float -> int64
-// conversion.
-__device__ __forceinline__ long long to_fix(float x) {
+// round(a b) as int64, round-half-even, for FP32 values a, b with |a b| < 2^51
+// (a is a current contribution already scaled by 2^40, so the result is
+// round(a b 2^40) on the 2^-40 grid).  The product of two FP32 values is exact
+// in FP64, so one FMA onto M = 1.5 * 2^52, where doubles are spaced exactly 1
+// apart, rounds the exact product once, half to even, to an integer; that
+// integer is the difference of the bit patterns of the sum and of M (same
+// exponent while |a b| < 2^51).  Two VALU instructions (the FMA and a 32-bit
+// add on the high word, the low word of M being zero) instead of a float
+// multiply and a general float -> int64 conversion.
+__device__ __forceinline__ long long fix_mul(double a, double b) {
     const double M = 0x1.8p52;
-    const double d = (double)x + M;
-    return __double_as_longlong(d) - __double_as_longlong(M);
+    return __double_as_longlong(fma(a, b, M)) - __double_as_longlong(M);
 }
 
 __device__ __forceinline__ int wrapi(int i, int n) {

@@ -72,7 +72,7 @@ hipError_t launch_batch_sort(const InstDesc* d, int n, int max_particles, int ma
                              hipStream_t st);
 hipError_t launch_batch_tile(const InstDesc* d, const int* tile_begin, int n, int total_tiles, int threads,
                              size_t lds_bytes, hipStream_t st);
-hipError_t launch_batch_loose(const InstDesc* d, int n, int max_loose, hipStream_t st);
+hipError_t launch_batch_rest(const InstDesc* d, int n, int max_count, hipStream_t st);
 hipError_t launch_batch_jfinal(const InstDesc* d, int n, int max_cells, hipStream_t st);
 hipError_t launch_batch_binomial(const InstDesc* d, int n, int max_cells, hipStream_t st);
 hipError_t launch_batch_bhalf(const InstDesc* d, int n, int max_cells, hipStream_t st);
@@ -133,9 +133,10 @@ size_t tile_lds_bytes(const TileGeom& t, int guard);
 // toff: tile ranges of the species' last sort
 hipError_t launch_pic_tile(const Geom& g, const TileGeom& t, int guard, int threads, const FieldPtrs& f,
                            const SpeciesDev& s, const int* toff, unsigned long long* acc, int* d_err, hipStream_t st);
-hipError_t launch_push_deposit_range(const Geom& g, const FieldPtrs& f, const SpeciesDev& s, const int* d_begin,
-                                     const int* d_count, int max_n, unsigned long long* acc, int* d_err,
-                                     hipStream_t st);
+// rest pass after the tile kernel: particles it marked as beyond their tile's
+// guard (cell -2 - c) and those appended after the last sort (index >= sorted)
+hipError_t launch_tile_rest(const Geom& g, const FieldPtrs& f, const SpeciesDev& s, const int* d_sorted,
+                            const int* d_count, int max_count, unsigned long long* acc, int* d_err, hipStream_t st);
 
 // field kernels (pic_fields.hip)
 hipError_t launch_bhalf(const Geom& g, int pd, const PDCoef& c, float* const E[3], float* const B[3], float h,

@@ -80,8 +80,10 @@ __device__ __forceinline__ bool moved(const int c0[3], const int c1[3], const fl
 //   J_x[a][b][c] += (-q w) * P_x[a] * (M_y[b] M_z[c] + dS_y[b] dS_z[c] / 12)
 // with P_x the running sum of dS_x along x and M = S0 + dS/2 (this product form
 // equals dS_x (S0y S0z + dSy S0z/2 + S0y dSz/2 + dSy dSz/3) summed along x).
-// Emit::add(comp, jx, jy, jz, value) receives each contribution scaled by
-// 2^40 (exact), (jx, jy, jz) being union-node indices 0..4 along x, y, z.
+// Emit::add(comp, jx, jy, jz, k) receives each contribution as the int64
+// k = round(2^40 (-q w) P Y) (the FP32 factors (-q w 2^40) Y and P multiplied
+// exactly and rounded once), (jx, jy, jz) being union-node indices 0..4 along
+// x, y, z.
 // Callers skip particles that did not move (every contribution is zero).
 template <class Emit>
 __device__ __forceinline__ void esirkepov(const Axis5 A[3], float qw, Emit& em) {
@@ -100,6 +102,9 @@ __device__ __forceinline__ void esirkepov(const Axis5 A[3], float qw, Emit& em) 
         P[0] = A[comp].dS[0];
 #pragma unroll
         for (int a = 1; a < 4; ++a) P[a] = P[a - 1] + A[comp].dS[a];
+        double Pd[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) Pd[a] = (double)P[a];
         const int la = A[comp].len - 1, lb = A[t1].len, lc = A[t2].len;
 #pragma unroll
         for (int cc = 0; cc < 5; ++cc) {
@@ -108,17 +113,17 @@ __device__ __forceinline__ void esirkepov(const Axis5 A[3], float qw, Emit& em) 
             for (int b = 0; b < 5; ++b) {
                 if (b >= lb) continue;
                 const float Y = fmaf(A[t1].dS[b] * A[t2].dS[cc], 1.0f / 12.0f, M[t1][b] * M[t2][cc]);
-                const float qy = qw40 * Y;
+                const double qy = (double)(qw40 * Y);
 #pragma unroll
                 for (int a = 0; a < 4; ++a) {
                     if (a >= la) continue;
-                    const float v = qy * P[a];
+                    const long long k = fix_mul(qy, Pd[a]);
                     if (comp == 0)
-                        em.add(0, a, b, cc, v);
+                        em.add(0, a, b, cc, k);
                     else if (comp == 1)
-                        em.add(1, cc, a, b, v);
+                        em.add(1, cc, a, b, k);
                     else
-                        em.add(2, b, cc, a, v);
+                        em.add(2, b, cc, a, k);
                 }
             }
         }

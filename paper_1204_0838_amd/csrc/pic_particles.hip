@@ -56,8 +56,8 @@ struct GlobalEmit {
     unsigned long long* acc;
     int ncell;
     int X[5], Y[5], Z[5];
-    __device__ __forceinline__ void add(int comp, int jx, int jy, int jz, float v) const {
-        atomicAdd(acc + ((size_t)comp * ncell + X[jx] + Y[jy] + Z[jz]), (unsigned long long)to_fix(v));
+    __device__ __forceinline__ void add(int comp, int jx, int jy, int jz, long long k) const {
+        atomicAdd(acc + ((size_t)comp * ncell + X[jx] + Y[jy] + Z[jz]), (unsigned long long)k);
     }
 };
 

@@ -6,9 +6,11 @@
 // cells, and then streams its particles (coalesced SoA loads):
 //   particles still within `guard` cells of the tile: gather from LDS,
 //     deposit with LDS 64-bit atomics;
-//   particles that drifted further since the last sort: gather from global
-//     memory and deposit with global atomics (the same arithmetic, in a
-//     separate non-inlined function to keep the hot loop's code small).
+//   particles that drifted further since the last sort: left for a second
+//     kernel (their cell index is replaced by -2 - cell), which gathers from
+//     global memory and deposits with global atomics (the same arithmetic).
+//     Keeping that path out of the tile kernel keeps its loop free of calls,
+//     so the kernel arguments stay in scalar registers.
 // Finally the non-zero LDS current is added to the global fixed-point
 // accumulator in one atomic pass.  Every value goes through the same device
 // functions as the split kernels, so the fused and split paths agree bit for
@@ -26,8 +28,8 @@ struct LdsEmit {
     unsigned long long* J;   // LDS current tile, 3 components of jr nodes
     int jr;
     int X[5], Y[5], Z[5];
-    __device__ __forceinline__ void add(int comp, int jx, int jy, int jz, float v) const {
-        atomicAdd(J + (comp * jr + X[jx] + Y[jy] + Z[jz]), (unsigned long long)to_fix(v));
+    __device__ __forceinline__ void add(int comp, int jx, int jy, int jz, long long k) const {
+        atomicAdd(J + (comp * jr + X[jx] + Y[jy] + Z[jz]), (unsigned long long)k);
     }
 };
 
@@ -35,8 +37,8 @@ struct GlobalEmitT {
     unsigned long long* acc;
     int ncell;
     int X[5], Y[5], Z[5];
-    __device__ __forceinline__ void add(int comp, int jx, int jy, int jz, float v) const {
-        atomicAdd(acc + ((size_t)comp * ncell + X[jx] + Y[jy] + Z[jz]), (unsigned long long)to_fix(v));
+    __device__ __forceinline__ void add(int comp, int jx, int jy, int jz, long long k) const {
+        atomicAdd(acc + ((size_t)comp * ncell + X[jx] + Y[jy] + Z[jz]), (unsigned long long)k);
     }
 };
 
@@ -47,7 +49,7 @@ __device__ __forceinline__ int xcd_tile(int b, int ntiles) {
 
 // One particle (index p, cell coordinates c) through global memory: gather,
 // push, move, store, deposit with global atomics.  Returns error flags.
-__device__ __noinline__ int push_deposit_global(const Geom& g, const FieldPtrs& f, const SpeciesDev& s, int p,
+__device__ __forceinline__ int push_deposit_global(const Geom& g, const FieldPtrs& f, const SpeciesDev& s, int p,
                                                 const int c[3], unsigned long long* acc) {
     const int gstride[3] = {1, g.n[0], g.nxy};
     float o[3] = {s.off[0][p], s.off[1][p], s.off[2][p]};
@@ -194,8 +196,8 @@ __device__ __forceinline__ void tile_body(const Geom& g, const TileGeom& t, int 
             lc[d] = l;
             inside = inside && l >= -guard && l < te[d] + guard;
         }
-        if (!inside) {
-            errs |= push_deposit_global(g, f, s, p, c, acc);
+        if (!inside) {   // beyond the guard: the rest pass takes it
+            s.cell[p] = -2 - cell;
             continue;
         }
         const float o0[3] = {o[0], o[1], o[2]};
@@ -289,40 +291,45 @@ __global__ void __launch_bounds__(NT) k_batch_tile(const InstDesc* __restrict__ 
     tile_body<NT>(g, t, d.guard, f, s, d.toff, d.acc, d.err, lds_u64, ft - tile_begin[lo]);
 }
 
-// Particles appended after the last sort (not in any tile range): the same
-// step through global memory.
-__device__ __forceinline__ void loose_one(const Geom& g, const FieldPtrs& f, const SpeciesDev& s, int p,
-                                          unsigned long long* acc, int* d_err) {
-    const int cell = s.cell[p];
-    if ((unsigned)cell >= (unsigned)g.ncell) return;
+// The rest pass, after the tile kernel: particles marked by it (cell -2 - c,
+// below the sorted count) and particles appended after the last sort (not in
+// any tile range, index >= sorted) take the same step through global memory.
+__device__ __forceinline__ void rest_one(const Geom& g, const FieldPtrs& f, const SpeciesDev& s, int p, int sorted,
+                                         unsigned long long* acc, int* d_err) {
+    int cell = s.cell[p];
     int c[3];
-    decompose(g, cell, c);
-    if (window_killed(g, c[0])) {
-        s.cell[p] = -1;
-        return;
+    if (p < sorted) {
+        if (cell > -2) return;
+        cell = -2 - cell;   // the tile kernel already applied the window cut
+        decompose(g, cell, c);
+    } else {
+        if ((unsigned)cell >= (unsigned)g.ncell) return;
+        decompose(g, cell, c);
+        if (window_killed(g, c[0])) {
+            s.cell[p] = -1;
+            return;
+        }
     }
     const int errs = push_deposit_global(g, f, s, p, c, acc);
     if (errs) atomicOr(d_err, errs);
 }
 
-__global__ void __launch_bounds__(256) k_push_deposit_range(Geom g, FieldPtrs f, SpeciesDev s,
-                                                            const int* __restrict__ d_begin,
-                                                            const int* __restrict__ d_count,
-                                                            unsigned long long* __restrict__ acc,
-                                                            int* __restrict__ d_err) {
-    const int p = *d_begin + blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256) k_tile_rest(Geom g, FieldPtrs f, SpeciesDev s, const int* __restrict__ d_sorted,
+                                                   const int* __restrict__ d_count,
+                                                   unsigned long long* __restrict__ acc, int* __restrict__ d_err) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= *d_count) return;
-    loose_one(g, f, s, p, acc, d_err);
+    rest_one(g, f, s, p, *d_sorted, acc, d_err);
 }
 
-__global__ void __launch_bounds__(256) k_batch_loose(const InstDesc* __restrict__ tab) {
+__global__ void __launch_bounds__(256) k_batch_rest(const InstDesc* __restrict__ tab) {
     const InstDesc& d = tab[blockIdx.y];
-    const int p = *d.sorted + blockIdx.x * blockDim.x + threadIdx.x;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= *d.count) return;
     const Geom g = d.g;
     const FieldPtrs f = d.f;
     const SpeciesDev s = step_arrays(d);
-    loose_one(g, f, s, p, d.acc, d.err);
+    rest_one(g, f, s, p, *d.sorted, d.acc, d.err);
 }
 
 size_t tile_lds_bytes(const TileGeom& t, int guard) {
@@ -392,18 +399,17 @@ hipError_t launch_batch_tile(const InstDesc* d, const int* tile_begin, int n, in
     }
 }
 
-hipError_t launch_batch_loose(const InstDesc* d, int n, int max_loose, hipStream_t st) {
-    if (n <= 0 || max_loose <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_batch_loose, dim3((max_loose + 255) / 256, n), dim3(256), 0, st, d);
+hipError_t launch_batch_rest(const InstDesc* d, int n, int max_count, hipStream_t st) {
+    if (n <= 0 || max_count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_rest, dim3((max_count + 255) / 256, n), dim3(256), 0, st, d);
     return hipGetLastError();
 }
 
-hipError_t launch_push_deposit_range(const Geom& g, const FieldPtrs& f, const SpeciesDev& s, const int* d_begin,
-                                     const int* d_count, int max_n, unsigned long long* acc, int* d_err,
-                                     hipStream_t st) {
-    if (max_n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_push_deposit_range, dim3((max_n + 255) / 256), dim3(256), 0, st, g, f, s, d_begin, d_count,
-                       acc, d_err);
+hipError_t launch_tile_rest(const Geom& g, const FieldPtrs& f, const SpeciesDev& s, const int* d_sorted,
+                            const int* d_count, int max_count, unsigned long long* acc, int* d_err, hipStream_t st) {
+    if (max_count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tile_rest, dim3((max_count + 255) / 256), dim3(256), 0, st, g, f, s, d_sorted, d_count, acc,
+                       d_err);
     return hipGetLastError();
 }
 

@@ -137,3 +137,37 @@ def test_two_species_keep_their_own_tile_ranges():
         assert np.array_equal(pa["id"][ia], pb["id"][ib])
         assert np.array_equal(pa["u"][:, ia], pb["u"][:, ib])
         assert np.array_equal(pa["cell"][ia], pb["cell"][ib])
+
+
+def _fast_beam(grid, seed, ux):
+    pl = inputs.uniform_random_plasma(grid, ppc=4, seed=seed, temperature_ev=1000.0)
+    pl.u[0] += np.float32(ux)
+    return pl
+
+
+def _share_beyond_guard(pl, grid, tile_x, steps):
+    """Share of particles whose x drift over `steps` steps leaves the tile of
+    their cell at the last sort (guard 0), from the initial state."""
+    v = float(pl.u[0].mean()) / np.sqrt(1.0 + float(pl.u[0].mean()) ** 2)
+    cx = pl.cell % grid.n[0]
+    local = (cx % tile_x) + pl.off[0]
+    return float(np.mean(local + v * grid.dt / grid.d[0] * steps >= tile_x))
+
+
+def test_particles_beyond_the_guard_take_the_rest_pass():
+    """A drift of about half a cell per step carries many particles out of their
+    tile between sorts (guard 0, sort every 4 steps); the tile kernel leaves
+    them to the global-memory rest pass and the result is still the split
+    kernels' bit for bit."""
+    grid = inputs.Grid(n=(16, 8, 12), d=(0.25, 0.3, 0.3), dt=0.15)
+    pl = _fast_beam(grid, 47, 2.0)
+    assert _share_beyond_guard(pl, grid, 4, 3) > 0.25
+    for threads in (256, 1024):
+        a, b = _pair(grid, pl, tile=(4, 4, 4), guard=0, interleave=1, sort_interval=4, threads=threads)
+        a.step(9)
+        for _ in range(9):
+            b.gather_push(0)
+            b.deposit(0)
+            b.field_step()
+        _assert_same(a, b)
+        assert float(a.J.abs().max()) > 0.0
