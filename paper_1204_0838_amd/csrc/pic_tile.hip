@@ -19,6 +19,8 @@
 // Workgroups are mapped to tiles XCD by XCD: consecutive workgroup indices go
 // round-robin over the 8 XCDs, so tile = (b % 8) * ceil(ntiles/8) + b / 8
 // gives each XCD a contiguous range of tiles whose halos share its L2.
+#include <algorithm>
+
 #include "pic_internal.h"
 #include "pic_particle_ops.h"
 
@@ -294,16 +296,18 @@ __global__ void __launch_bounds__(NT) k_batch_tile(const InstDesc* __restrict__ 
 // The rest pass, after the tile kernel: particles marked by it (cell -2 - c,
 // below the sorted count) and particles appended after the last sort (not in
 // any tile range, index >= sorted) take the same step through global memory.
+__device__ __forceinline__ bool rest_needed(const Geom& g, int p, int sorted, int cell) {
+    return p < sorted ? cell <= -2 : (unsigned)cell < (unsigned)g.ncell;
+}
+
 __device__ __forceinline__ void rest_one(const Geom& g, const FieldPtrs& f, const SpeciesDev& s, int p, int sorted,
                                          unsigned long long* acc, int* d_err) {
     int cell = s.cell[p];
     int c[3];
     if (p < sorted) {
-        if (cell > -2) return;
         cell = -2 - cell;   // the tile kernel already applied the window cut
         decompose(g, cell, c);
     } else {
-        if ((unsigned)cell >= (unsigned)g.ncell) return;
         decompose(g, cell, c);
         if (window_killed(g, c[0])) {
             s.cell[p] = -1;
@@ -314,22 +318,59 @@ __device__ __forceinline__ void rest_one(const Geom& g, const FieldPtrs& f, cons
     if (errs) atomicOr(d_err, errs);
 }
 
-__global__ void __launch_bounds__(256) k_tile_rest(Geom g, FieldPtrs f, SpeciesDev s, const int* __restrict__ d_sorted,
-                                                   const int* __restrict__ d_count,
-                                                   unsigned long long* __restrict__ acc, int* __restrict__ d_err) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= *d_count) return;
-    rest_one(g, f, s, p, *d_sorted, acc, d_err);
+// Grid-stride scan of the cell indices of [0, count): each thread keeps
+// kRestLoads coalesced loads in flight, then runs the (rare) particles that
+// need the global path one at a time.
+constexpr int kRestLoads = 8;
+constexpr int kRestThreads = 256;
+
+__device__ __forceinline__ void rest_scan(const Geom& g, const FieldPtrs& f, const SpeciesDev& s, int sorted,
+                                          int count, unsigned long long* acc, int* d_err) {
+    const long long stride = (long long)gridDim.x * kRestThreads;
+    for (long long p0 = (long long)blockIdx.x * kRestThreads + threadIdx.x; p0 < count; p0 += kRestLoads * stride) {
+        int v[kRestLoads];
+#pragma unroll
+        for (int k = 0; k < kRestLoads; ++k) {
+            const long long p = p0 + k * stride;
+            v[k] = p < count ? s.cell[p] : -1;
+        }
+        unsigned need = 0;
+#pragma unroll
+        for (int k = 0; k < kRestLoads; ++k) {
+            const long long p = p0 + k * stride;
+            need |= (p < count && rest_needed(g, (int)p, sorted, v[k]) ? 1u : 0u) << k;
+        }
+        while (need) {
+            const int k = __ffs(need) - 1;
+            need &= need - 1;
+            rest_one(g, f, s, (int)(p0 + k * stride), sorted, acc, d_err);
+        }
+    }
 }
 
-__global__ void __launch_bounds__(256) k_batch_rest(const InstDesc* __restrict__ tab) {
+__global__ void __launch_bounds__(kRestThreads) k_tile_rest(Geom g, FieldPtrs f, SpeciesDev s,
+                                                            const int* __restrict__ d_sorted,
+                                                            const int* __restrict__ d_count,
+                                                            unsigned long long* __restrict__ acc,
+                                                            int* __restrict__ d_err) {
+    rest_scan(g, f, s, *d_sorted, *d_count, acc, d_err);
+}
+
+__global__ void __launch_bounds__(kRestThreads) k_batch_rest(const InstDesc* __restrict__ tab) {
     const InstDesc& d = tab[blockIdx.y];
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= *d.count) return;
     const Geom g = d.g;
     const FieldPtrs f = d.f;
     const SpeciesDev s = step_arrays(d);
-    rest_one(g, f, s, p, *d.sorted, d.acc, d.err);
+    rest_scan(g, f, s, *d.sorted, *d.count, d.acc, d.err);
+}
+
+// Blocks of the rest scan: enough for about kRestLoads loads per thread and
+// pass, at most 2048 in all (eight per compute unit).
+static int rest_blocks(int max_count, int members) {
+    const long long per = (long long)kRestThreads * kRestLoads;
+    const long long want = (max_count + per - 1) / per;
+    const long long cap = std::max(1, 2048 / std::max(1, members));
+    return (int)std::max(1LL, std::min(want, cap));
 }
 
 size_t tile_lds_bytes(const TileGeom& t, int guard) {
@@ -401,15 +442,15 @@ hipError_t launch_batch_tile(const InstDesc* d, const int* tile_begin, int n, in
 
 hipError_t launch_batch_rest(const InstDesc* d, int n, int max_count, hipStream_t st) {
     if (n <= 0 || max_count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_batch_rest, dim3((max_count + 255) / 256, n), dim3(256), 0, st, d);
+    hipLaunchKernelGGL(k_batch_rest, dim3(rest_blocks(max_count, n), n), dim3(kRestThreads), 0, st, d);
     return hipGetLastError();
 }
 
 hipError_t launch_tile_rest(const Geom& g, const FieldPtrs& f, const SpeciesDev& s, const int* d_sorted,
                             const int* d_count, int max_count, unsigned long long* acc, int* d_err, hipStream_t st) {
     if (max_count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tile_rest, dim3((max_count + 255) / 256), dim3(256), 0, st, g, f, s, d_sorted, d_count, acc,
-                       d_err);
+    hipLaunchKernelGGL(k_tile_rest, dim3(rest_blocks(max_count, 1)), dim3(kRestThreads), 0, st, g, f, s, d_sorted,
+                       d_count, acc, d_err);
     return hipGetLastError();
 }
 
