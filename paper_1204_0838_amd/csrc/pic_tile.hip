@@ -17,8 +17,11 @@
 // bit (integer sums are order-independent).
 //
 // Workgroups are mapped to tiles XCD by XCD: consecutive workgroup indices go
-// round-robin over the 8 XCDs, so tile = (b % 8) * ceil(ntiles/8) + b / 8
-// gives each XCD a contiguous range of tiles whose halos share its L2.
+// round-robin over the 8 XCDs, and the tiles are dealt to the XCDs in chunks
+// (a row of tiles along x for one grid, 8 tiles of the concatenated list for a
+// batch): XCD k takes chunks k, k + 8, k + 16, ...  Neighbouring tiles of a
+// row share their halos in that XCD's L2, while a dense region (the wake on
+// the axis) is spread over all XCDs instead of loading one of them.
 #include <algorithm>
 
 #include "pic_internal.h"
@@ -44,10 +47,21 @@ struct GlobalEmitT {
     }
 };
 
-__device__ __forceinline__ int xcd_tile(int b, int ntiles) {
-    const int per = (ntiles + 7) / 8;
-    return (b % 8) * per + b / 8;
+// Tile of workgroup b when chunks of `chunk` consecutive tiles are dealt
+// round-robin to the 8 XCDs (>= ntiles: no tile; grid = xcd_blocks).
+__device__ __forceinline__ int xcd_tile(int b, int ntiles, int chunk) {
+    const int k = b % 8, j = b / 8;
+    const int c = k + 8 * (j / chunk);
+    const long long tile = (long long)c * chunk + j % chunk;
+    return tile < ntiles ? (int)tile : ntiles;
 }
+
+static int xcd_blocks(int ntiles, int chunk) {
+    const int nchunks = (ntiles + chunk - 1) / chunk;
+    return 8 * ((nchunks + 7) / 8) * chunk;
+}
+
+constexpr int kBatchChunk = 8;
 
 // One particle (index p, cell coordinates c) through global memory: gather,
 // push, move, store, deposit with global atomics.  Returns error flags.
@@ -266,7 +280,7 @@ __global__ void __launch_bounds__(NT) k_pic_tile(Geom g, TileGeom t, int guard, 
                                                  const int* __restrict__ toff, unsigned long long* __restrict__ acc,
                                                  int* __restrict__ d_err) {
     extern __shared__ unsigned long long lds_u64[];
-    const int tile = xcd_tile(blockIdx.x, t.ntiles);
+    const int tile = xcd_tile(blockIdx.x, t.ntiles, t.nt[0]);
     if (tile >= t.ntiles) return;
     tile_body<NT, TX, TY, TZ, GD>(g, t, guard, f, s, toff, acc, d_err, lds_u64, tile);
 }
@@ -278,7 +292,7 @@ template <int NT>
 __global__ void __launch_bounds__(NT) k_batch_tile(const InstDesc* __restrict__ tab,
                                                    const int* __restrict__ tile_begin, int n, int total) {
     extern __shared__ unsigned long long lds_u64[];
-    const int ft = xcd_tile(blockIdx.x, total);
+    const int ft = xcd_tile(blockIdx.x, total, kBatchChunk);
     if (ft >= total) return;
     int lo = 0, hi = n - 1;   // last member whose range starts at or before ft
     while (lo < hi) {
@@ -385,7 +399,7 @@ static hipError_t launch_tile_nt(const Geom& g, const TileGeom& t, int guard, co
                                  const SpeciesDev& s, const int* toff, unsigned long long* acc,
                                  int* d_err, hipStream_t st) {
     const size_t lds = tile_lds_bytes(t, guard);
-    const int nb = ((t.ntiles + 7) / 8) * 8;
+    const int nb = xcd_blocks(t.ntiles, t.nt[0]);
     hipError_t e = hipFuncSetAttribute((const void*)k_pic_tile<NT, TX, TY, TZ, GD>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -422,7 +436,7 @@ hipError_t launch_pic_tile(const Geom& g, const TileGeom& t, int guard, int thre
 template <int NT>
 static hipError_t launch_batch_tile_nt(const InstDesc* d, const int* tile_begin, int n, int total, size_t lds,
                                        hipStream_t st) {
-    const int nb = ((total + 7) / 8) * 8;
+    const int nb = xcd_blocks(total, kBatchChunk);
     hipError_t e = hipFuncSetAttribute((const void*)k_batch_tile<NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
     if (e != hipSuccess) return e;
