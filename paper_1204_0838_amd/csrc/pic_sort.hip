@@ -26,28 +26,61 @@ __device__ __forceinline__ int tile_key(const TileGeom& t, const int c[3]) {
     return tile * t.tcells + lx + t.T[0] * (ly + t.T[1] * lz);
 }
 
-__device__ __forceinline__ void count_one(const Geom& g, const TileGeom& t, const int* __restrict__ cell, int p,
-                                          int* __restrict__ hist, int* __restrict__ rank) {
-    const int cl = cell[p];
-    if ((unsigned)cl >= (unsigned)g.ncell) {
-        rank[p] = -1;
-        return;
-    }
+__device__ __forceinline__ int sort_key(const Geom& g, const TileGeom& t, int cl) {
+    if ((unsigned)cl >= (unsigned)g.ncell) return -1;
     int c[3];
     decompose(g, cl, c);
-    if (window_killed(g, c[0])) {
-        rank[p] = -1;
-        return;
-    }
-    rank[p] = atomicAdd(hist + tile_key(t, c), 1);
+    if (window_killed(g, c[0])) return -1;
+    return tile_key(t, c);
 }
+
+// Histogram and rank of the kCountRows particles p0 + 64 r (r = 0..7): after a
+// sort these are the rows of one lane of a transposed block, i.e. mostly the
+// particles of one cell, so one atomic per distinct key serves them all and
+// the ranks follow the row order (particles that kept their cell then mostly
+// keep their place, which keeps the scatter's stores coalesced).  Any
+// grouping is correct: a rank is a place among the particles of one key.
+constexpr int kCountRows = 8;
+
+__device__ __forceinline__ void count_column(const Geom& g, const TileGeom& t, const int* __restrict__ cell, int p0,
+                                             int n, int* __restrict__ hist, int* __restrict__ rank) {
+    int key[kCountRows];
+#pragma unroll
+    for (int r = 0; r < kCountRows; ++r) {
+        const int p = p0 + 64 * r;
+        key[r] = p < n ? sort_key(g, t, cell[p]) : -2;
+    }
+    int rk[kCountRows];
+#pragma unroll
+    for (int r = 0; r < kCountRows; ++r) rk[r] = -1;
+#pragma unroll
+    for (int r = 0; r < kCountRows; ++r) {
+        if (key[r] < 0 || rk[r] >= 0) continue;   // removed, or ranked with an earlier row
+        int cnt = 0;
+#pragma unroll
+        for (int q = r; q < kCountRows; ++q) cnt += key[q] == key[r];
+        int base = atomicAdd(hist + key[r], cnt);
+#pragma unroll
+        for (int q = r; q < kCountRows; ++q)
+            if (key[q] == key[r]) rk[q] = base++;
+    }
+#pragma unroll
+    for (int r = 0; r < kCountRows; ++r) {
+        const int p = p0 + 64 * r;
+        if (p < n) rank[p] = rk[r];
+    }
+}
+
+// Thread i counts the column p0 = (i / 64) * 512 + i % 64.
+__device__ __forceinline__ int column_of(int i) { return (i >> 6) * (64 * kCountRows) + (i & 63); }
 
 __global__ void __launch_bounds__(256) k_sort_count(Geom g, TileGeom t, const int* __restrict__ cell,
                                                     const int* __restrict__ d_count, int* __restrict__ hist,
                                                     int* __restrict__ rank) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= *d_count) return;
-    count_one(g, t, cell, p, hist, rank);
+    const int p0 = column_of(blockIdx.x * blockDim.x + threadIdx.x);
+    const int n = *d_count;
+    if (p0 >= n) return;
+    count_column(g, t, cell, p0, n, hist, rank);
 }
 
 // Exclusive scan, phase 1: per-block totals of 1024-element blocks.
@@ -189,11 +222,13 @@ __global__ void __launch_bounds__(256) k_batch_zero_hist(const InstDesc* __restr
 
 __global__ void __launch_bounds__(256) k_batch_sort_count(const InstDesc* __restrict__ tab) {
     const InstDesc& d = tab[blockIdx.y];
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (!d.sorting || p >= *d.count) return;
+    const int p0 = column_of(blockIdx.x * blockDim.x + threadIdx.x);
+    if (!d.sorting) return;
+    const int n = *d.count;
+    if (p0 >= n) return;
     const Geom g = d.g;
     const TileGeom t = d.t;
-    count_one(g, t, d.s.cell, p, d.hist, d.rank);
+    count_column(g, t, d.s.cell, p0, n, d.hist, d.rank);
 }
 
 __global__ void __launch_bounds__(1024) k_batch_scan_reduce(const InstDesc* __restrict__ tab) {
@@ -243,7 +278,8 @@ hipError_t launch_batch_sort(const InstDesc* d, int n, int max_particles, int ma
     const int np = max_particles > 0 ? max_particles : 1;
     const int nb = (max_keys1 + 1023) / 1024;
     hipLaunchKernelGGL(k_batch_zero_hist, dim3((max_keys1 + 255) / 256, n), dim3(256), 0, st, d);
-    hipLaunchKernelGGL(k_batch_sort_count, dim3((np + 255) / 256, n), dim3(256), 0, st, d);
+    const int ncol = (np + kCountRows - 1) / kCountRows + 64;   // whole 512-particle blocks of columns
+    hipLaunchKernelGGL(k_batch_sort_count, dim3((ncol + 255) / 256, n), dim3(256), 0, st, d);
     hipLaunchKernelGGL(k_batch_scan_reduce, dim3(nb, n), dim3(1024), 0, st, d);
     hipLaunchKernelGGL(k_batch_scan_sums, dim3(1, n), dim3(1024), 0, st, d);
     hipLaunchKernelGGL(k_batch_scan_apply, dim3(nb, n), dim3(1024), 0, st, d);
@@ -259,7 +295,8 @@ hipError_t launch_sort(const Geom& g, const TileGeom& t, const SpeciesDev& src, 
     hipError_t e = hipMemsetAsync(hist, 0, ((size_t)nkeys + 1) * sizeof(int), st);
     if (e != hipSuccess) return e;
     const int np = max_count > 0 ? max_count : 1;
-    hipLaunchKernelGGL(k_sort_count, dim3((np + 255) / 256), dim3(256), 0, st, g, t, src.cell, d_count, hist, rank);
+    const int ncol = (np + kCountRows - 1) / kCountRows + 64;   // whole 512-particle blocks of columns
+    hipLaunchKernelGGL(k_sort_count, dim3((ncol + 255) / 256), dim3(256), 0, st, g, t, src.cell, d_count, hist, rank);
     const int n = nkeys + 1;
     const int nb = (n + 1023) / 1024;
     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(1024), 0, st, hist, n, sums);
