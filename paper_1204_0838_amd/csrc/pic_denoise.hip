@@ -5,6 +5,8 @@
 // with respect to the activations (a transposed convolution is a
 // convolution with the taps mirrored and the channel roles swapped) with a
 // relu-mask epilogue, and the output stage with the loss.
+#include <algorithm>
+
 #include "pic_dn_common.h"
 
 namespace pic {
@@ -49,21 +51,32 @@ __global__ void __launch_bounds__(DN_THREADS) k_dn_c4(DnArgs a) {
         const uint4* src = reinterpret_cast<const uint4*>(a.w);
         for (int g = threadIdx.x; g < 32 * 16; g += DN_THREADS) reinterpret_cast<uint4*>(wl)[g] = src[g];
     }
-    for (int c = threadIdx.x; c < DN_HCELLS; c += DN_THREADS) {
-        const int hx = c % DN_HX, r = c / DN_HX, hy = r % DN_HY, hz = r / DN_HY;
-        bf16x4 v = {(__bf16)0.0f, (__bf16)0.0f, (__bf16)0.0f, (__bf16)0.0f};
-        if (hx < DN_TX + 2) {
-            const int s = dn_halo_src(a, t0, hx, hy, hz);
-            if (s >= 0) {
-                if (IN == 0) {
+    {
+        // every global load of the thread first, then the LDS stores
+        constexpr int PER = (DN_HCELLS + DN_THREADS - 1) / DN_THREADS;
+        bf16x4 v[PER];
 #pragma unroll
-                    for (int d = 0; d < 3; ++d) v[d] = (__bf16)(a.J[d][s] * a.inv_scale[d]);
-                } else {
-                    v = reinterpret_cast<const bf16x4*>(a.c4_in)[s];
+        for (int k = 0; k < PER; ++k) {
+            const int c = threadIdx.x + k * DN_THREADS;
+            const int hx = c % DN_HX, r = c / DN_HX, hy = r % DN_HY, hz = r / DN_HY;
+            v[k] = bf16x4{(__bf16)0.0f, (__bf16)0.0f, (__bf16)0.0f, (__bf16)0.0f};
+            if (c < DN_HCELLS && hx < DN_TX + 2) {
+                const int s = dn_halo_src(a, t0, hx, hy, hz);
+                if (s >= 0) {
+                    if (IN == 0) {
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) v[k][d] = (__bf16)(a.J[d][s] * a.inv_scale[d]);
+                    } else {
+                        v[k] = reinterpret_cast<const bf16x4*>(a.c4_in)[s];
+                    }
                 }
             }
         }
-        *reinterpret_cast<bf16x4*>(xin + c * 8) = v;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int c = threadIdx.x + k * DN_THREADS;
+            if (c < DN_HCELLS) *reinterpret_cast<bf16x4*>(xin + c * 8) = v[k];
+        }
     }
     __syncthreads();
     const int l = threadIdx.x & 63, lz = threadIdx.x >> 6;
@@ -103,51 +116,62 @@ __global__ void __launch_bounds__(DN_THREADS) k_dn_c4(DnArgs a) {
     dn_store32<EPI>(a, t0, acc);
 }
 
-// 32 -> 32 channels.
-template <int EPI>
-__global__ void __launch_bounds__(DN_THREADS) k_dn_c32(DnArgs a) {
+// Layers with a 32-channel input: 32 -> 32 channels (KIND 0: relu(acc + b),
+// 1: mask epilogue) or 32 -> 3 (KIND 2, 16 computed: y = acc + b as FP32
+// components into a.Jout).  Persistent: one workgroup per compute unit stages
+// the weights once and walks the tiles t = blockIdx.x, + gridDim.x, ...; the
+// next tile's input halo is loaded into registers while the current tile's
+// matrix work runs.
+template <int KIND>
+__global__ void __launch_bounds__(DN_THREADS) k_dn_conv32(DnArgs a) {
+    constexpr int NH = KIND == 2 ? 1 : 2;
     extern __shared__ __attribute__((aligned(16))) char dlds[];
     char* act = dlds;
     char* wl = dlds + DN_HCELLS * 64;
+    int ntx, nty;
+    const int ntiles = dn_ntiles(a.n, &ntx, &nty);
+    dn_stage_weights<27 * 16 * NH>(a.w, wl);
+    int tile = blockIdx.x;
     int t0[3];
-    dn_tile(t0);
-    dn_stage_weights(a.w, 27 * 32, wl);
-    dn_stage_act(a, t0, act);
-    __syncthreads();
-    f32x4 acc[4][2];
-#pragma unroll
-    for (int blk = 0; blk < 4; ++blk)
-#pragma unroll
-        for (int h = 0; h < 2; ++h) acc[blk][h] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    dn_mma32<2>(act, wl, acc);
-    dn_store32<EPI>(a, t0, acc);
-}
-
-// 32 -> 3 channels (16 computed): y = acc + b as FP32 components into a.Jout.
-__global__ void __launch_bounds__(DN_THREADS) k_dn_c3(DnArgs a) {
-    extern __shared__ __attribute__((aligned(16))) char dlds[];
-    char* act = dlds;
-    char* wl = dlds + DN_HCELLS * 64;
-    int t0[3];
-    dn_tile(t0);
-    dn_stage_weights(a.w, 27 * 16, wl);
-    dn_stage_act(a, t0, act);
-    __syncthreads();
-    f32x4 acc[4][1];
-#pragma unroll
-    for (int blk = 0; blk < 4; ++blk) acc[blk][0] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    dn_mma32<1>(act, wl, acc);
-    const int l = threadIdx.x & 63, lz = threadIdx.x >> 6;
-    const int co = l & 15, rq = l >> 4;
-    if (co >= 3) return;
-    const float b = a.bias[co];
-#pragma unroll
-    for (int blk = 0; blk < 4; ++blk)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int cell = dn_out_cell(a, t0, lz, blk, rq * 4 + j);
-            if (cell >= 0) a.Jout[co][cell] = acc[blk][0][j] + b;
+    uint4 v[DN_ACT_PER];
+    if (tile < ntiles) {
+        dn_tile_of(tile, ntx, nty, t0);
+        dn_load_act(a, t0, v);
+    }
+    while (tile < ntiles) {
+        __syncthreads();   // the previous tile's LDS reads are done (first pass: nothing)
+        dn_store_act(v, act);
+        __syncthreads();   // halo (and, first pass, weights) staged
+        const int cur[3] = {t0[0], t0[1], t0[2]};
+        const int next = tile + gridDim.x;
+        if (next < ntiles) {
+            dn_tile_of(next, ntx, nty, t0);
+            dn_load_act(a, t0, v);
         }
+        f32x4 acc[4][NH];
+#pragma unroll
+        for (int blk = 0; blk < 4; ++blk)
+#pragma unroll
+            for (int h = 0; h < NH; ++h) acc[blk][h] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        dn_mma32<NH>(act, wl, acc);
+        if constexpr (KIND == 2) {
+            const int l = threadIdx.x & 63, lz = threadIdx.x >> 6;
+            const int co = l & 15, rq = l >> 4;
+            if (co < 3) {
+                const float b = a.bias[co];
+#pragma unroll
+                for (int blk = 0; blk < 4; ++blk)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int cell = dn_out_cell(a, cur, lz, blk, rq * 4 + j);
+                        if (cell >= 0) a.Jout[co][cell] = acc[blk][0][j] + b;
+                    }
+            }
+        } else {
+            dn_store32<KIND>(a, cur, acc);
+        }
+        tile = next;
+    }
 }
 
 // Window/box coordinates of cell index i (x fastest), its storage index,
@@ -290,13 +314,31 @@ static hipError_t dn_launch(K kern, size_t lds, const DnArgs& a, hipStream_t st)
     return hipGetLastError();
 }
 
+// Persistent layers: one workgroup per compute unit (their LDS allows one),
+// never more than there are tiles.
+template <class K>
+static hipError_t dn_launch_persistent(K kern, size_t lds, const DnArgs& a, hipStream_t st) {
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    int dev = 0, ncu = 0;
+    e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    const dim3 g = dn_grid(a.n);
+    const long long ntiles = (long long)g.x * g.y * g.z;
+    const int nb = (int)std::max(1LL, std::min<long long>(ntiles, ncu > 0 ? ncu : 256));
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(DN_THREADS), lds, st, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_dn_layer(int kind, const DnArgs& a, hipStream_t st) {
     switch (kind) {
         case DN_L1_J_ACT: return dn_launch(k_dn_c4<0, 0>, 0, a, st);
         case DN_L1_C4_MASK: return dn_launch(k_dn_c4<1, 1>, 0, a, st);
-        case DN_L2_ACT: return dn_launch(k_dn_c32<0>, dn_lds(32), a, st);
-        case DN_L2_MASK: return dn_launch(k_dn_c32<1>, dn_lds(32), a, st);
-        case DN_L3_Y: return dn_launch(k_dn_c3, dn_lds(16), a, st);
+        case DN_L2_ACT: return dn_launch_persistent(k_dn_conv32<0>, dn_lds(32), a, st);
+        case DN_L2_MASK: return dn_launch_persistent(k_dn_conv32<1>, dn_lds(32), a, st);
+        case DN_L3_Y: return dn_launch_persistent(k_dn_conv32<2>, dn_lds(16), a, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -125,11 +125,25 @@ __device__ __forceinline__ void dn_tile(int t0[3]) {
     t0[2] = blockIdx.z * DN_TZ;
 }
 
-// Copy `rows` 64-byte rows of packed weights into LDS (swizzled).
-__device__ __forceinline__ void dn_stage_weights(const __bf16* __restrict__ w, int rows, char* lds) {
+// Copy ROWS 64-byte rows of packed weights into LDS (swizzled).  Each thread
+// issues all its global loads before its first LDS store, so the staging
+// waits for one memory latency rather than one per chunk.
+template <int ROWS>
+__device__ __forceinline__ void dn_stage_weights(const __bf16* __restrict__ w, char* lds) {
+    constexpr int N = ROWS * 4, PER = (N + DN_THREADS - 1) / DN_THREADS;
     const uint4* src = reinterpret_cast<const uint4*>(w);
-    for (int g = threadIdx.x; g < rows * 4; g += DN_THREADS)
-        *reinterpret_cast<uint4*>(lds + dn_chunk(g >> 2, g & 3)) = src[g];
+    uint4 v[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int g = threadIdx.x + k * DN_THREADS;
+        v[k] = make_uint4(0u, 0u, 0u, 0u);
+        if (g < N) v[k] = src[g];
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int g = threadIdx.x + k * DN_THREADS;
+        if (g < N) *reinterpret_cast<uint4*>(lds + dn_chunk(g >> 2, g & 3)) = v[k];
+    }
 }
 
 // Storage cell index of halo cell (hx, hy, hz) of the tile, or -1 for zero.
@@ -141,19 +155,48 @@ __device__ __forceinline__ int dn_halo_src(const DnArgs& a, const int t0[3], int
     return x + a.n[0] * (y + a.n[1] * z);
 }
 
-// Stage a 32-channel bf16 activation halo.
-__device__ __forceinline__ void dn_stage_act(const DnArgs& a, const int t0[3], char* lds) {
+// A 32-channel bf16 activation halo in two phases: every global load of the
+// thread into registers (they can stay in flight while the previous tile's
+// matrix work runs), then the LDS stores.
+constexpr int DN_ACT_PER = (DN_HCELLS * 4 + DN_THREADS - 1) / DN_THREADS;
+
+__device__ __forceinline__ void dn_load_act(const DnArgs& a, const int t0[3], uint4 v[DN_ACT_PER]) {
+    constexpr int N = DN_HCELLS * 4;
     const uint4* src = reinterpret_cast<const uint4*>(a.act_in);
-    for (int g = threadIdx.x; g < DN_HCELLS * 4; g += DN_THREADS) {
+#pragma unroll
+    for (int k = 0; k < DN_ACT_PER; ++k) {
+        const int g = threadIdx.x + k * DN_THREADS;
         const int c = g >> 2, q = g & 3;
         const int hx = c % DN_HX, r = c / DN_HX, hy = r % DN_HY, hz = r / DN_HY;
-        uint4 v = make_uint4(0u, 0u, 0u, 0u);
-        if (hx < DN_TX + 2) {
+        v[k] = make_uint4(0u, 0u, 0u, 0u);
+        if (g < N && hx < DN_TX + 2) {
             const int s = dn_halo_src(a, t0, hx, hy, hz);
-            if (s >= 0) v = src[(size_t)s * 4 + q];
+            if (s >= 0) v[k] = src[(size_t)s * 4 + q];
         }
-        *reinterpret_cast<uint4*>(lds + dn_chunk(c, q)) = v;
     }
+}
+
+__device__ __forceinline__ void dn_store_act(const uint4 v[DN_ACT_PER], char* lds) {
+    constexpr int N = DN_HCELLS * 4;
+#pragma unroll
+    for (int k = 0; k < DN_ACT_PER; ++k) {
+        const int g = threadIdx.x + k * DN_THREADS;
+        if (g < N) *reinterpret_cast<uint4*>(lds + dn_chunk(g >> 2, g & 3)) = v[k];
+    }
+}
+
+// Output tiles of the box and the origin of tile t (x fastest).
+__device__ __forceinline__ int dn_ntiles(const int n[3], int* ntx, int* nty) {
+    *ntx = (n[0] + DN_TX - 1) / DN_TX;
+    *nty = (n[1] + DN_TY - 1) / DN_TY;
+    return *ntx * *nty * ((n[2] + DN_TZ - 1) / DN_TZ);
+}
+
+__device__ __forceinline__ void dn_tile_of(int t, int ntx, int nty, int t0[3]) {
+    const int bx = t % ntx, r = t / ntx;
+    t0[0] = bx * DN_TX;
+    t0[1] = (r % nty) * DN_TY;
+    t0[2] = (r / nty) * DN_TZ;
 }
 
 // Storage cell of output row block `blk` (y row), lane row m, plane lz; -1 outside the box.
