@@ -207,24 +207,35 @@ __device__ __forceinline__ int dn_out_cell(const DnArgs& a, const int t0[3], int
     return xs + a.n[0] * (y + a.n[1] * z);
 }
 
-// Accumulate the 27 taps x 32 input channels of a 32-channel layer.
+// Accumulate the 27 taps x 32 input channels of a 32-channel layer.  Per tap
+// column (dz, dx) the wavefront reads the 6 halo rows its 4 output rows need
+// once and reuses each for the three dy taps (row blk + dy): 6 A reads per 12
+// row-block MFMA steps instead of 12.
 template <int NH>
 __device__ __forceinline__ void dn_mma32(const char* act, const char* wl, f32x4 acc[4][NH]) {
     const int l = threadIdx.x & 63, lz = threadIdx.x >> 6;
     const int m = l & 15, q = l >> 4;
 #pragma unroll 1
-    for (int tap = 0; tap < 27; ++tap) {
-        const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;   // 0..2 = offset + 1
-        bf16x8 B[NH];
+    for (int zx = 0; zx < 9; ++zx) {
+        const int dz = zx / 3, dx = zx % 3;   // 0..2 = offset + 1
+        bf16x8 A[DN_HY];
 #pragma unroll
-        for (int h = 0; h < NH; ++h)
-            B[h] = *reinterpret_cast<const bf16x8*>(wl + dn_chunk(tap * 16 * NH + h * 16 + m, q));
+        for (int r = 0; r < DN_HY; ++r) {
+            const int c = ((lz + dz) * DN_HY + r) * DN_HX + (m + dx);
+            A[r] = *reinterpret_cast<const bf16x8*>(act + dn_chunk(c, q));
+        }
 #pragma unroll
-        for (int blk = 0; blk < 4; ++blk) {
-            const int c = ((lz + dz) * DN_HY + (blk + dy)) * DN_HX + (m + dx);
-            const bf16x8 A = *reinterpret_cast<const bf16x8*>(act + dn_chunk(c, q));
+        for (int dy = 0; dy < 3; ++dy) {
+            const int tap = dz * 9 + dy * 3 + dx;
+            bf16x8 B[NH];
 #pragma unroll
-            for (int h = 0; h < NH; ++h) acc[blk][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B[h], acc[blk][h], 0, 0, 0);
+            for (int h = 0; h < NH; ++h)
+                B[h] = *reinterpret_cast<const bf16x8*>(wl + dn_chunk(tap * 16 * NH + h * 16 + m, q));
+#pragma unroll
+            for (int blk = 0; blk < 4; ++blk)
+#pragma unroll
+                for (int h = 0; h < NH; ++h)
+                    acc[blk][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[blk + dy], B[h], acc[blk][h], 0, 0, 0);
         }
     }
 }
