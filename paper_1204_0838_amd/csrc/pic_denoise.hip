@@ -282,6 +282,82 @@ __global__ void __launch_bounds__(256) k_dn_curl_adjoint(DnCombine c) {
     reinterpret_cast<bf16x4*>(c.dy)[k.s] = out;
 }
 
+// Inference output stage fused in one pass over tiles of 32 x 8 x 4 cells:
+// J' = B(t), t = J + sigma curl(y), with t computed in LDS on the tile plus a
+// 1-cell halo (zero outside the box) from y staged with a further cell below
+// (the backward differences).  Same arithmetic, in the same order, as
+// k_dn_curl_add followed by k_dn_binomial<false>.
+constexpr int DO_TX = 32, DO_TY = 8, DO_TZ = 4, DO_THREADS = DO_TX * DO_TY * DO_TZ;
+constexpr int DO_YX = DO_TX + 3, DO_YY = DO_TY + 3, DO_YZ = DO_TZ + 3;   // y: cells -2 .. T
+constexpr int DO_SX = DO_TX + 2, DO_SY = DO_TY + 2, DO_SZ = DO_TZ + 2;   // t: cells -1 .. T
+
+__device__ __forceinline__ int do_src(const DnCombine& c, int x, int y, int z) {
+    const int sx = dn_axis(x, c.n[0], c.bc[0], c.origin);
+    const int sy = dn_axis(y, c.n[1], c.bc[1], 0);
+    const int sz = dn_axis(z, c.n[2], c.bc[2], 0);
+    if (sx < 0 || sy < 0 || sz < 0) return -1;
+    return sx + c.n[0] * (sy + c.n[1] * sz);
+}
+
+__global__ void __launch_bounds__(DO_THREADS) k_dn_output(DnCombine c) {
+    __shared__ float ys[3][DO_YZ * DO_YY * DO_YX];
+    __shared__ float ts[3][DO_SZ * DO_SY * DO_SX];
+    const int t0[3] = {(int)blockIdx.x * DO_TX, (int)blockIdx.y * DO_TY, (int)blockIdx.z * DO_TZ};
+    for (int i = threadIdx.x; i < DO_YZ * DO_YY * DO_YX; i += DO_THREADS) {
+        const int hx = i % DO_YX, r = i / DO_YX, hy = r % DO_YY, hz = r / DO_YY;
+        const int s = do_src(c, t0[0] - 2 + hx, t0[1] - 2 + hy, t0[2] - 2 + hz);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) ys[d][i] = dn_at(c.y[d], s);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < DO_SZ * DO_SY * DO_SX; i += DO_THREADS) {
+        const int hx = i % DO_SX, r = i / DO_SX, hy = r % DO_SY, hz = r / DO_SY;
+        const int s = do_src(c, t0[0] - 1 + hx, t0[1] - 1 + hy, t0[2] - 1 + hz);
+        const int yc = ((hz + 1) * DO_YY + (hy + 1)) * DO_YX + (hx + 1);   // the same cell in ys
+        const int ym[3] = {yc - 1, yc - DO_YX, yc - DO_YX * DO_YY};          // one cell lower along x, y, z
+#pragma unroll
+        for (int comp = 0; comp < 3; ++comp) {
+            const int t1 = (comp + 1) % 3, t2 = (comp + 2) % 3;
+            float v = 0.0f;
+            if (s >= 0) {
+                const float cu = (ys[t2][yc] - ys[t2][ym[t1]]) * c.inv_d[t1] - (ys[t1][yc] - ys[t1][ym[t2]]) * c.inv_d[t2];
+                v = fmaf(c.sigma, cu, c.src[comp][s]);
+            }
+            ts[comp][i] = v;
+        }
+    }
+    __syncthreads();
+    const int lx = threadIdx.x % DO_TX, ly = (threadIdx.x / DO_TX) % DO_TY, lz = threadIdx.x / (DO_TX * DO_TY);
+    const int x = t0[0] + lx, y = t0[1] + ly, z = t0[2] + lz;
+    if (x >= c.n[0] || y >= c.n[1] || z >= c.n[2]) return;
+    const int s = do_src(c, x, y, z);
+    const float w[3] = {0.25f, 0.5f, 0.25f};
+#pragma unroll
+    for (int comp = 0; comp < 3; ++comp) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int zc = 0; zc < 3; ++zc) {
+            float ay = 0.0f;
+#pragma unroll
+            for (int yb = 0; yb < 3; ++yb) {
+                float ax = 0.0f;
+                const int row = ((lz + zc) * DO_SY + (ly + yb)) * DO_SX + lx;
+#pragma unroll
+                for (int xa = 0; xa < 3; ++xa) ax = fmaf(w[xa], ts[comp][row + xa], ax);
+                ay = fmaf(w[yb], ax, ay);
+            }
+            acc = fmaf(w[zc], ay, acc);
+        }
+        c.dst[comp][s] = acc;
+    }
+}
+
+hipError_t launch_dn_output(const DnCombine& c, hipStream_t st) {
+    const dim3 g((c.n[0] + DO_TX - 1) / DO_TX, (c.n[1] + DO_TY - 1) / DO_TY, (c.n[2] + DO_TZ - 1) / DO_TZ);
+    hipLaunchKernelGGL(k_dn_output, g, dim3(DO_THREADS), 0, st, c);
+    return hipGetLastError();
+}
+
 static dim3 dn_cells_grid(const DnCombine& c) { return dim3((c.n[0] * c.n[1] * c.n[2] + 255) / 256); }
 
 hipError_t launch_dn_curl_add(const DnCombine& c, hipStream_t st) {
@@ -375,26 +451,20 @@ hipError_t launch_denoise(const Geom& g, const int bc[3], const DenoiseWeights& 
     for (int d = 0; d < 3; ++d) a.Jout[d] = y + d * N;
     e = launch_dn_layer(DN_L3_Y, a, st);
     if (e != hipSuccess) return e;
-    // t = J + sigma curl(y) in the second activation buffer, then J' = B(t)
-    float* t = reinterpret_cast<float*>(h2);
+    // J' = B(J + sigma curl(y)) in one pass (Jout must not alias Jin: tiles
+    // read their neighbours' J)
     DnCombine c{};
     for (int d = 0; d < 3; ++d) {
         c.n[d] = g.n[d];
         c.bc[d] = bc[d];
         c.src[d] = Jin[d];
         c.y[d] = y + d * N;
-        c.dst[d] = t + d * N;
+        c.dst[d] = Jout[d];
         c.inv_d[d] = w.inv_d[d];
     }
     c.origin = a.origin;
     c.sigma = w.sigma;
-    e = launch_dn_curl_add(c, st);
-    if (e != hipSuccess) return e;
-    for (int d = 0; d < 3; ++d) {
-        c.src[d] = t + d * N;
-        c.dst[d] = Jout[d];
-    }
-    return launch_dn_binomial(c, false, st);
+    return launch_dn_output(c, st);
 }
 
 }  // namespace pic
