@@ -11,9 +11,15 @@
 
 namespace pic {
 
-// 32 output channels: EPI 0 = bf16 relu(acc + bias), 1 = bf16 acc where the mask activation is > 0.
+// 32 output channels: EPI 0 = bf16 relu(acc + bias), 1 = bf16 acc where the
+// mask activation is > 0.  The tile's 512 x 32 bf16 outputs are first placed
+// in the LDS buffer ob (32 KB, rows swizzled like the inputs, so the 16 lanes
+// of one cell and the 4 cells of one write hit different banks), then stored
+// to HBM as whole 16-byte chunks of each cell.  The caller guarantees that no
+// wavefront still reads ob; the function ends with ob free again only after
+// the caller's next barrier.
 template <int EPI>
-__device__ __forceinline__ void dn_store32(const DnArgs& a, const int t0[3], const f32x4 acc[4][2]) {
+__device__ __forceinline__ void dn_store32(const DnArgs& a, const int t0[3], const f32x4 acc[4][2], char* ob) {
     const int l = threadIdx.x & 63, lz = threadIdx.x >> 6;
     const int col = l & 15, rq = l >> 4;
 #pragma unroll
@@ -24,15 +30,28 @@ __device__ __forceinline__ void dn_store32(const DnArgs& a, const int t0[3], con
         for (int blk = 0; blk < 4; ++blk)
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const int cell = dn_out_cell(a, t0, lz, blk, rq * 4 + j);
-                if (cell < 0) continue;
+                const int m = rq * 4 + j;
                 float v;
-                if (EPI == 0)
+                if (EPI == 0) {
                     v = fmaxf(acc[blk][h][j] + b, 0.0f);
-                else
-                    v = (float)a.mask[(size_t)cell * 32 + co] > 0.0f ? acc[blk][h][j] : 0.0f;
-                a.act_out[(size_t)cell * 32 + co] = (__bf16)v;
+                } else {
+                    const int cell = dn_out_cell(a, t0, lz, blk, m);
+                    v = cell >= 0 && (float)a.mask[(size_t)cell * 32 + co] > 0.0f ? acc[blk][h][j] : 0.0f;
+                }
+                const int lc = (lz * DN_TY + blk) * DN_TX + m;
+                *reinterpret_cast<__bf16*>(ob + dn_chunk(lc, co >> 3) + (co & 7) * 2) = (__bf16)v;
             }
+    }
+    __syncthreads();
+    constexpr int NCH = DN_TX * DN_TY * DN_TZ * 4;
+#pragma unroll
+    for (int k = 0; k < NCH / DN_THREADS; ++k) {
+        const int g = threadIdx.x + k * DN_THREADS;
+        const int lc = g >> 2, q = g & 3;
+        const int m = lc % DN_TX, r = lc / DN_TX, blk = r % DN_TY, pz = r / DN_TY;
+        const int cell = dn_out_cell(a, t0, pz, blk, m);
+        if (cell >= 0)
+            reinterpret_cast<uint4*>(a.act_out)[(size_t)cell * 4 + q] = *reinterpret_cast<const uint4*>(ob + dn_chunk(lc, q));
     }
 }
 
@@ -42,9 +61,10 @@ __device__ __forceinline__ void dn_store32(const DnArgs& a, const int t0[3], con
 // rounded to bf16 here); IN 1: a bf16 [cell][4] array.
 template <int IN, int EPI>
 __global__ void __launch_bounds__(DN_THREADS) k_dn_c4(DnArgs a) {
-    __shared__ __attribute__((aligned(16))) char lds[DN_HCELLS * 8 + 32 * 256];
+    __shared__ __attribute__((aligned(16))) char lds[DN_HCELLS * 8 + 32 * 256 + DN_TX * DN_TY * DN_TZ * 64];
     char* xin = lds;                       // [halo cell][4] bf16
     char* wl = lds + DN_HCELLS * 8;        // [co][128] bf16, 256 B rows
+    char* ob = wl + 32 * 256;              // output tile (dn_store32)
     int t0[3];
     dn_tile(t0);
     {
@@ -113,7 +133,7 @@ __global__ void __launch_bounds__(DN_THREADS) k_dn_c4(DnArgs a) {
                 acc[blk][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B[h], acc[blk][h], 0, 0, 0);
         }
     }
-    dn_store32<EPI>(a, t0, acc);
+    dn_store32<EPI>(a, t0, acc, ob);
 }
 
 // Layers with a 32-channel input: 32 -> 32 channels (KIND 0: relu(acc + b),
@@ -168,7 +188,8 @@ __global__ void __launch_bounds__(DN_THREADS) k_dn_conv32(DnArgs a) {
                     }
             }
         } else {
-            dn_store32<KIND>(a, cur, acc);
+            __syncthreads();   // every wavefront is done reading the halo: reuse it for the output tile
+            dn_store32<KIND>(a, cur, acc, act);
         }
         tile = next;
     }
