@@ -147,26 +147,42 @@ __global__ void __launch_bounds__(DN_THREADS) k_dn_conv32(DnArgs a) {
     constexpr int NH = KIND == 2 ? 1 : 2;
     extern __shared__ __attribute__((aligned(16))) char dlds[];
     char* act = dlds;
-    char* wl = dlds + DN_HCELLS * 64;
+    char* wl = dlds + DN_ACT_LDS;
     int ntx, nty;
     const int ntiles = dn_ntiles(a.n, &ntx, &nty);
     dn_stage_weights<27 * 16 * NH>(a.w, wl);
-    int tile = blockIdx.x;
-    int t0[3];
-    uint4 v[DN_ACT_PER];
-    if (tile < ntiles) {
-        dn_tile_of(tile, ntx, nty, t0);
-        dn_load_act(a, t0, v);
+    // XCD-aware walk (workgroups go round-robin over the 8 XCDs): the
+    // workgroups of one XCD share a contiguous range of tiles and walk it
+    // together, so the halos they share stay in that XCD's L2
+    int tile, stride, end;
+    if (gridDim.x % 8 == 0) {
+        const int per = (ntiles + 7) / 8, k = blockIdx.x % 8;
+        tile = k * per + blockIdx.x / 8;
+        stride = gridDim.x / 8;
+        end = min(ntiles, (k + 1) * per);
+    } else {
+        tile = blockIdx.x;
+        stride = gridDim.x;
+        end = ntiles;
     }
-    while (tile < ntiles) {
+    int t0[3];
+    int hc[DN_ACT_PER];
+    dn_halo_coords(hc);
+    const DnBox box = dn_box(a);
+    uint4 v[DN_ACT_PER];
+    if (tile < end) {
+        dn_tile_of(tile, ntx, nty, t0);
+        dn_load_act(a, box, t0, hc, v);
+    }
+    while (tile < end) {
         __syncthreads();   // the previous tile's LDS reads are done (first pass: nothing)
         dn_store_act(v, act);
         __syncthreads();   // halo (and, first pass, weights) staged
         const int cur[3] = {t0[0], t0[1], t0[2]};
-        const int next = tile + gridDim.x;
-        if (next < ntiles) {
+        const int next = tile + stride;
+        if (next < end) {
             dn_tile_of(next, ntx, nty, t0);
-            dn_load_act(a, t0, v);
+            dn_load_act(a, box, t0, hc, v);
         }
         f32x4 acc[4][NH];
 #pragma unroll
@@ -178,13 +194,16 @@ __global__ void __launch_bounds__(DN_THREADS) k_dn_conv32(DnArgs a) {
             const int l = threadIdx.x & 63, lz = threadIdx.x >> 6;
             const int co = l & 15, rq = l >> 4;
             if (co < 3) {
+                // pick the component's pointer among the three (indexing the
+                // argument array with a lane value would re-read it from memory)
+                float* out = co == 0 ? a.Jout[0] : (co == 1 ? a.Jout[1] : a.Jout[2]);
                 const float b = a.bias[co];
 #pragma unroll
                 for (int blk = 0; blk < 4; ++blk)
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         const int cell = dn_out_cell(a, cur, lz, blk, rq * 4 + j);
-                        if (cell >= 0) a.Jout[co][cell] = acc[blk][0][j] + b;
+                        if (cell >= 0) out[cell] = acc[blk][0][j] + b;
                     }
             }
         } else {
@@ -399,7 +418,7 @@ hipError_t launch_dn_curl_adjoint(const DnCombine& c, hipStream_t st) {
     return hipGetLastError();
 }
 
-static size_t dn_lds(int cout) { return (size_t)DN_HCELLS * 64 + (size_t)27 * cout * 64; }
+static size_t dn_lds(int cout) { return (size_t)DN_ACT_LDS + (size_t)27 * cout * 64; }
 
 template <class K>
 static hipError_t dn_launch(K kern, size_t lds, const DnArgs& a, hipStream_t st) {
@@ -424,8 +443,9 @@ static hipError_t dn_launch_persistent(K kern, size_t lds, const DnArgs& a, hipS
     if (e != hipSuccess) return e;
     const dim3 g = dn_grid(a.n);
     const long long ntiles = (long long)g.x * g.y * g.z;
-    const int nb = (int)std::max(1LL, std::min<long long>(ntiles, ncu > 0 ? ncu : 256));
-    hipLaunchKernelGGL(kern, dim3(nb), dim3(DN_THREADS), lds, st, a);
+    long long nb = std::max(1LL, std::min<long long>(ntiles, ncu > 0 ? ncu : 256));
+    if (nb >= 8) nb -= nb % 8;   // a multiple of the 8 XCDs: the XCD-aware walk
+    hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(DN_THREADS), lds, st, a);
     return hipGetLastError();
 }
 

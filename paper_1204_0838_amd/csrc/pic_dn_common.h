@@ -25,9 +25,13 @@
 // holds column l%16, rows 4(l/16)..4(l/16)+3.  A row = a cell, K = input
 // channels, B column = an output channel.
 //
-// LDS rows of 64 B (a cell's 32 channels, or a weight row) are stored as four
-// 16-byte chunks rotated by rot(r) = ((r >> 1) ^ (r >> 2)) & 3, so that the 16
-// consecutive rows one A or B read touches spread over all banks.
+// Weight rows of 64 B are stored in LDS as four 16-byte chunks rotated by
+// rot(r) = ((r >> 1) ^ (r >> 2)) & 3, so that the consecutive rows one B read
+// touches spread over all banks; rot(r + 16 k) = rot(r), so the rows of every
+// tap are the first 16 rows moved by a constant.  The input halo's cell rows
+// are padded to 80 B instead (8 consecutive cells, one 16-byte read each,
+// fall in disjoint bank quadruples), so every A read of a wavefront is one
+// base address plus a constant per tap.
 #pragma once
 
 #include "pic_internal.h"
@@ -42,6 +46,8 @@ constexpr int DN_TX = 16, DN_TY = 4, DN_TZ = 8;        // output tile
 constexpr int DN_HX = 20, DN_HY = DN_TY + 2, DN_HZ = DN_TZ + 2;   // halo tile (x padded)
 constexpr int DN_HCELLS = DN_HX * DN_HY * DN_HZ;
 constexpr int DN_THREADS = 512;
+constexpr int DN_ROWB = 80;                               // LDS bytes per halo cell row
+constexpr int DN_ACT_LDS = DN_HCELLS * DN_ROWB;
 
 __device__ __forceinline__ int dn_rot(int r) { return ((r >> 1) ^ (r >> 2)) & 3; }
 
@@ -157,23 +163,61 @@ __device__ __forceinline__ int dn_halo_src(const DnArgs& a, const int t0[3], int
 
 // A 32-channel bf16 activation halo in two phases: every global load of the
 // thread into registers (they can stay in flight while the previous tile's
-// matrix work runs), then the LDS stores.
+// matrix work runs), then the LDS stores.  The halo coordinates of the
+// thread's chunks do not depend on the tile: dn_halo_coords packs them once
+// (hx | hy << 8 | hz << 16 | chunk << 24, or -1 for no load).
 constexpr int DN_ACT_PER = (DN_HCELLS * 4 + DN_THREADS - 1) / DN_THREADS;
 
-__device__ __forceinline__ void dn_load_act(const DnArgs& a, const int t0[3], uint4 v[DN_ACT_PER]) {
-    constexpr int N = DN_HCELLS * 4;
-    const uint4* src = reinterpret_cast<const uint4*>(a.act_in);
+__device__ __forceinline__ void dn_halo_coords(int hc[DN_ACT_PER]) {
 #pragma unroll
     for (int k = 0; k < DN_ACT_PER; ++k) {
         const int g = threadIdx.x + k * DN_THREADS;
         const int c = g >> 2, q = g & 3;
         const int hx = c % DN_HX, r = c / DN_HX, hy = r % DN_HY, hz = r / DN_HY;
-        v[k] = make_uint4(0u, 0u, 0u, 0u);
-        if (g < N && hx < DN_TX + 2) {
-            const int s = dn_halo_src(a, t0, hx, hy, hz);
-            if (s >= 0) v[k] = src[(size_t)s * 4 + q];
-        }
+        hc[k] = g < DN_HCELLS * 4 && hx < DN_TX + 2 ? hx | (hy << 8) | (hz << 16) | (q << 24) : -1;
     }
+}
+
+// Grid and boundary of a layer held in registers for the halo loads.
+struct DnBox {
+    int n[3], bc[3], origin;
+};
+
+__device__ __forceinline__ DnBox dn_box(const DnArgs& a) {
+    DnBox b;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        b.n[d] = a.n[d];
+        b.bc[d] = a.bc[d];
+    }
+    b.origin = a.origin;
+    return b;
+}
+
+// dn_axis for v in [-1, n] without branches (v one cell beyond the box at most).
+__device__ __forceinline__ int dn_axis_sel(int v, int n, int bc, int origin) {
+    const bool out = v < 0 || v >= n;
+    const int w = v < 0 ? v + n : (v >= n ? v - n : v);
+    int x = v + origin;
+    x = x >= n ? x - n : x;
+    const int r = bc == 0 ? w : (bc == 2 ? x : v);
+    return bc != 0 && out ? -1 : r;
+}
+
+__device__ __forceinline__ void dn_load_act(const DnArgs& a, const DnBox& b, const int t0[3],
+                                            const int hc[DN_ACT_PER], uint4 v[DN_ACT_PER]) {
+    const uint4* src = reinterpret_cast<const uint4*>(a.act_in);
+    long long off[DN_ACT_PER];
+#pragma unroll
+    for (int k = 0; k < DN_ACT_PER; ++k) {
+        const int x = dn_axis_sel(t0[0] - 1 + (hc[k] & 255), b.n[0], b.bc[0], b.origin);
+        const int y = dn_axis_sel(t0[1] - 1 + ((hc[k] >> 8) & 255), b.n[1], b.bc[1], 0);
+        const int z = dn_axis_sel(t0[2] - 1 + ((hc[k] >> 16) & 255), b.n[2], b.bc[2], 0);
+        const bool ok = hc[k] >= 0 && x >= 0 && y >= 0 && z >= 0;
+        off[k] = ok ? ((long long)x + (long long)b.n[0] * (y + (long long)b.n[1] * z)) * 4 + (hc[k] >> 24) : -1;
+    }
+#pragma unroll
+    for (int k = 0; k < DN_ACT_PER; ++k) v[k] = off[k] >= 0 ? src[off[k]] : make_uint4(0u, 0u, 0u, 0u);
 }
 
 __device__ __forceinline__ void dn_store_act(const uint4 v[DN_ACT_PER], char* lds) {
@@ -181,7 +225,7 @@ __device__ __forceinline__ void dn_store_act(const uint4 v[DN_ACT_PER], char* ld
 #pragma unroll
     for (int k = 0; k < DN_ACT_PER; ++k) {
         const int g = threadIdx.x + k * DN_THREADS;
-        if (g < N) *reinterpret_cast<uint4*>(lds + dn_chunk(g >> 2, g & 3)) = v[k];
+        if (g < N) *reinterpret_cast<uint4*>(lds + (g >> 2) * DN_ROWB + (g & 3) * 16) = v[k];
     }
 }
 
@@ -210,27 +254,28 @@ __device__ __forceinline__ int dn_out_cell(const DnArgs& a, const int t0[3], int
 // Accumulate the 27 taps x 32 input channels of a 32-channel layer.  Per tap
 // column (dz, dx) the wavefront reads the 6 halo rows its 4 output rows need
 // once and reuses each for the three dy taps (row blk + dy): 6 A reads per 12
-// row-block MFMA steps instead of 12.
+// row-block MFMA steps.  All taps are unrolled, so every LDS address is the
+// lane's base plus a constant.
 template <int NH>
 __device__ __forceinline__ void dn_mma32(const char* act, const char* wl, f32x4 acc[4][NH]) {
     const int l = threadIdx.x & 63, lz = threadIdx.x >> 6;
     const int m = l & 15, q = l >> 4;
-#pragma unroll 1
+    const char* abase = act + (lz * DN_HY * DN_HX + m) * DN_ROWB + q * 16;
+    const char* bbase = wl + dn_chunk(m, q);
+#pragma unroll
     for (int zx = 0; zx < 9; ++zx) {
         const int dz = zx / 3, dx = zx % 3;   // 0..2 = offset + 1
         bf16x8 A[DN_HY];
 #pragma unroll
-        for (int r = 0; r < DN_HY; ++r) {
-            const int c = ((lz + dz) * DN_HY + r) * DN_HX + (m + dx);
-            A[r] = *reinterpret_cast<const bf16x8*>(act + dn_chunk(c, q));
-        }
+        for (int r = 0; r < DN_HY; ++r)
+            A[r] = *reinterpret_cast<const bf16x8*>(abase + ((dz * DN_HY + r) * DN_HX + dx) * DN_ROWB);
 #pragma unroll
         for (int dy = 0; dy < 3; ++dy) {
             const int tap = dz * 9 + dy * 3 + dx;
             bf16x8 B[NH];
 #pragma unroll
             for (int h = 0; h < NH; ++h)
-                B[h] = *reinterpret_cast<const bf16x8*>(wl + dn_chunk(tap * 16 * NH + h * 16 + m, q));
+                B[h] = *reinterpret_cast<const bf16x8*>(bbase + (tap * NH + h) * 1024);
 #pragma unroll
             for (int blk = 0; blk < 4; ++blk)
 #pragma unroll
