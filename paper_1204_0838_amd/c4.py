@@ -8,11 +8,16 @@ the current plus a divergence-free learned correction, so the denoised
 current keeps the filtered current's charge balance and, like it, carries
 no grid-scale (Nyquist) modes.
 
-1. Training pairs.  A 32-ppc run (4x4x2 lattice, binomial filter, fused
-   production step) and a 2-ppc run (1x1x2 lattice, split path so its raw
-   current is visible, binomial filter in its field update) advance in
-   lockstep with the same laser and window.  At sampled steps, seeded crops
-   of the window give (input = raw 2-ppc J, target = filtered 32-ppc J).
+1. Training pairs, exactly aligned: one high-ppc run whose plasma is two
+   electron species on the same fields, the 32-ppc lattice (4x4x2) at 15/16
+   of the density and the 2-ppc lattice (1x1x2) at 1/16.  At a sampled step
+   the split path pushes both species and deposits the 2-ppc one first: 16 x
+   its current is exactly what a 2-ppc run deposits from this state (the
+   input); after the other species and the field step, J holds the filtered
+   total current of the same step (the target).  Seeded crops of the window
+   give the pairs; every other step is the fused production step.  (A 2-ppc
+   run advanced beside a 32-ppc run instead drifts to another state, and its
+   current then differs from the target by more than sampling noise.)
 2. Training: Adam on the matrix cores (pic_dn_trainer), per-component scale
    = RMS of the targets.
 3. Evaluation: a 2-ppc run with the trained denoiser (fused step) and a
@@ -66,33 +71,29 @@ def _rel(a, b):
 
 
 def collect_pairs(base, steps, sample_steps, crop, ncrops, seed):
-    """Lockstep 32-ppc / 2-ppc runs; returns (pairs, 32-ppc E_x checkpoints, 32-ppc ms/step, particles)."""
+    """Aligned pairs from the two-species high-ppc run (see the module doc)
+    and the plain 32-ppc run's E_x checkpoints, ms per step and particles."""
     import torch
 
     from . import workloads
 
-    big = workloads.build(_cfg(base, PPC32), jpost="binomial")
-    small = workloads.build(_cfg(base, PPC2), jpost="binomial", tuned=False)
-    big.profile_enable(True)
+    mixed = workloads.build(_cfg(base, PPC32), jpost="binomial", species=[(PPC32, 15.0 / 16.0), (PPC2, 1.0 / 16.0)])
     nx, ny, nz = base["n"]
     cx, cy, cz = crop
     rng = np.random.default_rng(seed)
     per = int(math.ceil(ncrops / max(1, len(sample_steps))))
     pairs = []
-    ex = {}
-    checkpoints = set(range(100, steps + 1, 100)) | {steps}
     t0 = time.perf_counter()
     for st in range(1, steps + 1):
-        _, org_b = big.window_state()    # the step's current is deposited in the frame before its window shift
-        big.step(1)
-        if st % 2 == 0:
-            small.sort(0)          # drops particles that left the window (the split path keeps them)
-        small.gather_push(0)
-        small.deposit(0)
         if st in sample_steps and len(pairs) < ncrops:
-            _, org_s = small.window_state()
-            jb = torch.roll(big.J, shifts=-org_b, dims=3)
-            js = torch.roll(small.J, shifts=-org_s, dims=3)
+            _, org = mixed.window_state()   # the step's current is deposited in the frame before its window shift
+            mixed.gather_push(0)
+            mixed.gather_push(1)
+            mixed.deposit(1)
+            js = 16.0 * torch.roll(mixed.J, shifts=-org, dims=3)
+            mixed.deposit(0)
+            mixed.field_step()
+            jb = torch.roll(mixed.J, shifts=-org, dims=3)
             for _ in range(per):
                 if len(pairs) >= ncrops:
                     break
@@ -101,17 +102,13 @@ def collect_pairs(base, steps, sample_steps, crop, ncrops, seed):
                 z0 = int(rng.integers(0, nz - cz + 1))
                 sl = (slice(None), slice(z0, z0 + cz), slice(y0, y0 + cy), slice(x0, x0 + cx))
                 pairs.append((js[sl].contiguous(), jb[sl].contiguous()))
-        small.field_step()
-        if st in checkpoints:
-            ex[st] = _ex_window(big)
+        else:
+            mixed.step(1)
         if st % 50 == 0:
             _log(f"pairs run step {st}/{steps}, {len(pairs)} crops, {time.perf_counter() - t0:.0f} s")
-    prof = big.profile_read()
-    ms = sum(prof[k] for k in ("sort_ms", "tile_ms", "loose_ms", "jpost_ms", "field_ms", "window_ms")) / steps
-    n_big = big.reduce()["n_particles"]
-    big.close()
-    small.close()
-    return pairs, ex, ms, n_big
+    mixed.close()
+    ex32, ms32, n32, _ = run_eval(base, PPC32, "binomial", steps)
+    return pairs, ex32, ms32, n32
 
 
 def binomial_init(rng, noise=0.3):

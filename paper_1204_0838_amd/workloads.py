@@ -64,26 +64,34 @@ def initial_particles(cfg: dict) -> int:
 
 
 def build(cfg: dict, capacity_factor: float = 1.05, device="cuda:0", tuned: bool = True, jpost: str = "none",
-          **tiling):
+          species=None, **tiling):
     """A Simulation holding the workload at t = 0 (plasma loaded, laser and window set).
 
-    Tiling: explicit keyword arguments, else the autotuner's cached choice
-    for this shape (when `tuned`), else the library defaults."""
+    species: optional list of (ppc lattice, density fraction), one electron
+    species each on the same density profile (default: the configuration's
+    lattice at the full density).  Tiling: explicit keyword arguments, else
+    the autotuner's cached choice for this shape (when `tuned`), else the
+    library defaults."""
     from . import autotune, pic
 
     if not tiling and tuned:
         tiling = autotune.load(cfg) or {}
     nx, ny, nz = cfg["n"]
     p = cfg["plasma"]
-    ppc = p["ppc"][0] * p["ppc"][1] * p["ppc"][2]
+    if species is None:
+        species = [(tuple(p["ppc"]), 1.0)]
     # every lattice slot of the window (the host-side bound of the initial load
     # counts them all) with headroom for electrons swept along with the window
-    cap = int((nx - 3) * ny * nz * ppc * capacity_factor) + 4 * ny * nz * ppc
-    sim = pic.Simulation(cfg["n"], cfg["d"], cfg["dt"], solver=cfg["solver"], bc_x=1, max_particles=cap,
+    caps = []
+    for lat, _ in species:
+        ppc = lat[0] * lat[1] * lat[2]
+        caps.append(int((nx - 3) * ny * nz * ppc * capacity_factor) + 4 * ny * nz * ppc)
+    sim = pic.Simulation(cfg["n"], cfg["d"], cfg["dt"], solver=cfg["solver"], bc_x=1, max_particles=sum(caps),
                          device=device, jpost=jpost, **tiling)
-    sim.add_empty_species(cap)
-    sim.set_plasma(0, p["x_start"], p["ramp"], p["n_plateau"], p["ppc"])
-    sim.inject_plasma(0, 0, nx - 3)
+    for s, ((lat, frac), cap) in enumerate(zip(species, caps)):
+        sim.add_empty_species(cap)
+        sim.set_plasma(s, p["x_start"], p["ramp"], p["n_plateau"] * frac, lat)
+        sim.inject_plasma(s, 0, nx - 3)
     L = cfg["laser"]
     sim.set_laser(L["a0"], L["omega0"], L["waist"], L["fwhm"], L["t_peak"], L["t_end"], ny * cfg["d"][1] / 2,
                   nz * cfg["d"][2] / 2, L["src_x"])
