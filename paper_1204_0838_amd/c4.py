@@ -70,9 +70,12 @@ def _rel(a, b):
     return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-30))
 
 
-def collect_pairs(base, steps, sample_steps, crop, ncrops, seed):
+def collect_pairs(base, steps, sample_steps, crop, ncrops, seed, axis_share=0.75):
     """Aligned pairs from the two-species high-ppc run (see the module doc)
-    and the plain 32-ppc run's E_x checkpoints, ms per step and particles."""
+    and the plain 32-ppc run's E_x checkpoints, ms per step and particles.
+    A share `axis_share` of the crops contains the laser axis, where the
+    wake and the strongest currents are (a uniform draw would put it in a
+    few percent of them); the rest are uniform over the window."""
     import torch
 
     from . import workloads
@@ -98,8 +101,12 @@ def collect_pairs(base, steps, sample_steps, crop, ncrops, seed):
                 if len(pairs) >= ncrops:
                     break
                 x0 = int(rng.integers(0, nx - cx + 1))
-                y0 = int(rng.integers(0, ny - cy + 1))
-                z0 = int(rng.integers(0, nz - cz + 1))
+                if rng.random() < axis_share:   # a crop that contains the laser axis (the wake)
+                    y0 = min(max(ny // 2 - cy // 2 + int(rng.integers(-(cy // 4), cy // 4 + 1)), 0), ny - cy)
+                    z0 = min(max(nz // 2 - cz // 2 + int(rng.integers(-(cz // 4), cz // 4 + 1)), 0), nz - cz)
+                else:
+                    y0 = int(rng.integers(0, ny - cy + 1))
+                    z0 = int(rng.integers(0, nz - cz + 1))
                 sl = (slice(None), slice(z0, z0 + cz), slice(y0, y0 + cy), slice(x0, x0 + cx))
                 pairs.append((js[sl].contiguous(), jb[sl].contiguous()))
         else:
@@ -232,6 +239,7 @@ def main():
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--out", type=str, default="c4_out")
     ap.add_argument("--no-floor", action="store_true", help="skip the second 32-ppc run (noise floor)")
+    ap.add_argument("--axis-share", type=float, default=0.75, help="share of training crops containing the laser axis")
     args = ap.parse_args()
     sys.path.insert(0, os.path.dirname(HERE))
     from paper_1204_0838_amd import workloads
@@ -244,7 +252,8 @@ def main():
     steps = args.steps
     sample_steps = set(np.linspace(steps // 20, steps - 1, 24).astype(int).tolist())
     _log(f"grid {base['n']}, {steps} steps, pairs from steps {min(sample_steps)}..{max(sample_steps)}")
-    pairs, ex32, ms32, n32 = collect_pairs(base, steps, sample_steps, crop, args.crops, seed=5)
+    pairs, ex32, ms32, n32 = collect_pairs(base, steps, sample_steps, crop, args.crops, seed=5,
+                                           axis_share=args.axis_share)
     _log(f"{len(pairs)} training pairs; 32-ppc run {ms32:.1f} ms/step, {n32} particles")
     t_train = time.perf_counter()
     params, scale, hist = train(pairs, crop, base["d"], args.epochs, args.lr, seed=6, batch=args.batch)
@@ -260,7 +269,8 @@ def main():
         floor = {str(k): _rel(exf[k], ex32[k]) for k in sorted(exf)}
     out = {
         "grid": list(base["n"]), "steps": steps, "crop": list(crop), "crops": args.crops,
-        "epochs": args.epochs, "batch": args.batch, "lr": args.lr, "train_seconds": t_train, "training": hist,
+        "epochs": args.epochs, "batch": args.batch, "lr": args.lr, "axis_share": args.axis_share,
+        "train_seconds": t_train, "training": hist,
         "scale": scale.tolist(),
         "ms_per_step": {"ppc32_binomial": ms32, "ppc2_denoiser": msd, "ppc2_binomial": msb},
         "particles": {"ppc32": n32, "ppc2_denoiser": nd, "ppc2_binomial": nb},
