@@ -60,6 +60,7 @@ struct Small {
     int pad0;
     int count[kMaxSpecies];    // live + removed-but-not-yet-dropped particles
     int sorted[kMaxSpecies];   // particles covered by the tile ranges of the last sort
+    int rest_n[kMaxSpecies];   // entries on the rest list of the last tile launch
     double red[4];
     unsigned long long live;
     unsigned long long contmax;
@@ -654,6 +655,7 @@ void fill_desc(pic_ctx* c, int32_t s, InstDesc& d) {
     d.err = &sm->err;
     d.count = &sm->count[s];
     d.sorted = &sm->sorted[s];
+    d.rest_n = &sm->rest_n[s];
     d.capacity = (int)sp.user.capacity;
     d.hdt = (float)(0.5 * c->desc.dt);
     jscale(c, d.jscale);
@@ -730,7 +732,7 @@ pic_status batch_one_step(pic_batch* b) {
     for (int32_t s = 0; s < b->nsp; ++s) {
         int total = 0;
         PICCHK(upload_tables(b, s, &dtab, &dbegin, &total));
-        int max_sort = 0, max_keys1 = 0, max_tiles1 = 0, max_count = 0;
+        int max_sort = 0, max_keys1 = 0, max_tiles1 = 0;
         bool any_sort = false;
         size_t lds = 0;
         for (int i = 0; i < n; ++i) {
@@ -747,7 +749,6 @@ pic_status batch_one_step(pic_batch* b) {
                 sp.sort_step = c->step;
             }
             sp.prev_valid = false;
-            max_count = (int)std::max<int64_t>(max_count, sp.bound);
             lds = std::max(lds, tile_lds_bytes(c->tl.t, c->tl.guard));
         }
         hipEvent_t t0, t1, t2;
@@ -761,11 +762,9 @@ pic_status batch_one_step(pic_batch* b) {
         BHIPCHK(b, launch_batch_tile(dtab, dbegin, n, total, b->m[0]->tl.threads, lds, b->stream));
         PICCHK(bend(b, PH_TILE, t1));
         if (b->prof.on) b->prof.tiles += 1;
-        if (max_count > 0) {
-            PICCHK(bmark(b, &t2));
-            BHIPCHK(b, launch_batch_rest(dtab, n, max_count, b->stream));
-            PICCHK(bend(b, PH_LOOSE, t2));
-        }
+        PICCHK(bmark(b, &t2));
+        BHIPCHK(b, launch_batch_rest(dtab, n, b->stream));
+        PICCHK(bend(b, PH_LOOSE, t2));
         // the window phase below needs each species' table; keep species 0's
         // for the field phase and re-stage the others then
     }
@@ -992,13 +991,14 @@ pic_status pic_step(pic_ctx* c, int32_t nsteps) {
             }
             Small* sm = small_of(c);
             PICCHK(prof_mark(c, &t1));
+            int* rest_idx = reinterpret_cast<int*>(c->ws + c->L.sort_rank) + sp.base;
             HIPCHK(c, launch_pic_tile(c->g, c->tl.t, c->tl.guard, c->tl.threads, fields_of(c), dev_of(c, sp),
-                                      toff_of(c, s), acc_of(c), &sm->err, c->stream));
+                                      toff_of(c, s), acc_of(c), &sm->err, &sm->rest_n[s], rest_idx, c->stream));
             PICCHK(prof_end(c, PH_TILE, t1));
             if (c->prof.on) c->prof.tiles += 1;
             PICCHK(prof_mark(c, &t2));
             HIPCHK(c, launch_tile_rest(c->g, fields_of(c), dev_of(c, sp), &sm->sorted[s], &sm->count[s],
-                                       (int)sp.bound, acc_of(c), &sm->err, c->stream));
+                                       &sm->rest_n[s], rest_idx, acc_of(c), &sm->err, c->stream));
             PICCHK(prof_end(c, PH_LOOSE, t2));
             sp.prev_valid = false;
         }

@@ -112,14 +112,110 @@ __device__ __forceinline__ void bhalf_cell(const Geom& g, const PDCoef& c, const
     Bz[idx] -= h * (dxEy - dyEx);
 }
 
+// LDS-tiled form of the B half step (the single-grid production path): E is
+// staged on a tile of BT_X x BT_Y x BT_Z cells plus a one-cell halo, in window
+// coordinates, with zeros beyond the window's two ends (or periodic images);
+// a neighbour across the window seam is then exactly a zero-filled halo cell,
+// as in bhalf_cell.  Every smoothed value and difference is the same
+// expression in the same order as bhalf_cell, so the results are identical.
+constexpr int BT_X = 32, BT_Y = 8, BT_Z = 4, BT_THREADS = 256;
+constexpr int BS_X = BT_X + 2, BS_Y = BT_Y + 2, BS_Z = BT_Z + 2, BS_N = BS_X * BS_Y * BS_Z;
+
+template <int AXIS>
+__device__ __forceinline__ float smooth_l(const PDCoef& c, const float* F, int o) {
+    constexpr int X = 1, Y = BS_X, Z = BS_X * BS_Y;
+    const float ctr = F[o];
+    if (AXIS == 0) {
+        const float ny = F[o + Y] + F[o - Y];
+        const float nz = F[o + Z] + F[o - Z];
+        const float cr = (F[o + Y + Z] + F[o - Y + Z]) + (F[o + Y - Z] + F[o - Y - Z]);
+        return fmaf(c.gam[0], cr, fmaf(c.beta[2], nz, fmaf(c.beta[1], ny, c.alpha[0] * ctr)));
+    } else if (AXIS == 1) {
+        const float nz = F[o + Z] + F[o - Z];
+        const float nx = F[o + X] + F[o - X];
+        const float cr = (F[o + X + Z] + F[o - X + Z]) + (F[o + X - Z] + F[o - X - Z]);
+        return fmaf(c.gam[1], cr, fmaf(c.beta[0], nx, fmaf(c.beta[2], nz, c.alpha[1] * ctr)));
+    } else {
+        const float nx = F[o + X] + F[o - X];
+        const float ny = F[o + Y] + F[o - Y];
+        const float cr = (F[o + X + Y] + F[o - X + Y]) + (F[o + X - Y] + F[o - X - Y]);
+        return fmaf(c.gam[2], cr, fmaf(c.beta[1], ny, fmaf(c.beta[0], nx, c.alpha[2] * ctr)));
+    }
+}
+
+template <bool PD, int AXIS>
+__device__ __forceinline__ float sval_l(const PDCoef& c, const float* F, int o) {
+    if (PD) return smooth_l<AXIS>(c, F, o);
+    return F[o];
+}
+
 template <bool PD>
-__global__ void __launch_bounds__(256) k_bhalf(Geom g, PDCoef c, const float* __restrict__ Ex,
-                                               const float* __restrict__ Ey, const float* __restrict__ Ez,
-                                               float* __restrict__ Bx, float* __restrict__ By,
-                                               float* __restrict__ Bz, float h) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= g.ncell) return;
-    bhalf_cell<PD>(g, c, Ex, Ey, Ez, Bx, By, Bz, h, idx);
+__global__ void __launch_bounds__(BT_THREADS) k_bhalf_tiled(Geom g, PDCoef c, const float* __restrict__ Ex,
+                                                           const float* __restrict__ Ey,
+                                                           const float* __restrict__ Ez, float* __restrict__ Bx,
+                                                           float* __restrict__ By, float* __restrict__ Bz, float h) {
+    __shared__ float El[3][BS_N];
+    const int t0[3] = {(int)blockIdx.x * BT_X, (int)blockIdx.y * BT_Y, (int)blockIdx.z * BT_Z};
+    const int origin = g.window ? g.origin : 0;
+    constexpr int PER = (BS_N + BT_THREADS - 1) / BT_THREADS;
+    float v[PER][3];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int i = threadIdx.x + q * BT_THREADS;
+        const int hx = i % BS_X, r = i / BS_X, hy = r % BS_Y, hz = r / BS_Y;
+        int xw = t0[0] - 1 + hx, y = t0[1] - 1 + hy, z = t0[2] - 1 + hz;
+        y = ((y % g.n[1]) + g.n[1]) % g.n[1];
+        z = ((z % g.n[2]) + g.n[2]) % g.n[2];
+        bool ok = i < BS_N;
+        if (g.window) {
+            ok = ok && xw >= 0 && xw < g.n[0];
+        } else {
+            xw = ((xw % g.n[0]) + g.n[0]) % g.n[0];
+        }
+        int xs = xw + origin;
+        xs = xs >= g.n[0] ? xs - g.n[0] : xs;
+        const int s = xs + g.n[0] * (y + g.n[1] * z);
+        v[q][0] = ok ? Ex[s] : 0.0f;
+        v[q][1] = ok ? Ey[s] : 0.0f;
+        v[q][2] = ok ? Ez[s] : 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int i = threadIdx.x + q * BT_THREADS;
+        if (i < BS_N) {
+            El[0][i] = v[q][0];
+            El[1][i] = v[q][1];
+            El[2][i] = v[q][2];
+        }
+    }
+    __syncthreads();
+    const float* lx = El[0];
+    const float* ly = El[1];
+    const float* lz = El[2];
+    const int x = threadIdx.x % BT_X, y = threadIdx.x / BT_X;
+    const int xw = t0[0] + x, yy = t0[1] + y;
+    if (xw >= g.n[0] || yy >= g.n[1]) return;
+    int xs = xw + origin;
+    xs = xs >= g.n[0] ? xs - g.n[0] : xs;
+#pragma unroll
+    for (int zl = 0; zl < BT_Z; ++zl) {
+        const int zz = t0[2] + zl;
+        if (zz >= g.n[2]) break;
+        const int o = ((zl + 1) * BS_Y + (y + 1)) * BS_X + (x + 1);
+        const int idx = xs + g.n[0] * (yy + g.n[1] * zz);
+        constexpr int X = 1, Y = BS_X, Z = BS_X * BS_Y;
+        const float dyEz = (sval_l<PD, 1>(c, lz, o + Y) - sval_l<PD, 1>(c, lz, o)) * g.inv_d[1];
+        const float dzEy = (sval_l<PD, 2>(c, ly, o + Z) - sval_l<PD, 2>(c, ly, o)) * g.inv_d[2];
+        const float dzEx = (sval_l<PD, 2>(c, lx, o + Z) - sval_l<PD, 2>(c, lx, o)) * g.inv_d[2];
+        const float ezp = sval_l<PD, 0>(c, lz, o + X);
+        const float eyp = sval_l<PD, 0>(c, ly, o + X);
+        const float dxEz = (ezp - sval_l<PD, 0>(c, lz, o)) * g.inv_d[0];
+        const float dxEy = (eyp - sval_l<PD, 0>(c, ly, o)) * g.inv_d[0];
+        const float dyEx = (sval_l<PD, 1>(c, lx, o + Y) - sval_l<PD, 1>(c, lx, o)) * g.inv_d[1];
+        Bx[idx] -= h * (dyEz - dzEy);
+        By[idx] -= h * (dzEx - dxEz);
+        Bz[idx] -= h * (dxEy - dyEx);
+    }
 }
 
 // E += dt (curl B - J) with backward differences.
@@ -231,11 +327,13 @@ __global__ void k_zero_u64(unsigned long long* p, int64_t n) {
 
 hipError_t launch_bhalf(const Geom& g, int pd, const PDCoef& c, float* const E[3], float* const B[3], float h,
                         hipStream_t st) {
-    const int nb = (g.ncell + 255) / 256;
+    const dim3 nb((g.n[0] + BT_X - 1) / BT_X, (g.n[1] + BT_Y - 1) / BT_Y, (g.n[2] + BT_Z - 1) / BT_Z);
     if (pd)
-        hipLaunchKernelGGL(k_bhalf<true>, dim3(nb), dim3(256), 0, st, g, c, E[0], E[1], E[2], B[0], B[1], B[2], h);
+        hipLaunchKernelGGL(k_bhalf_tiled<true>, nb, dim3(BT_THREADS), 0, st, g, c, E[0], E[1], E[2], B[0], B[1], B[2],
+                           h);
     else
-        hipLaunchKernelGGL(k_bhalf<false>, dim3(nb), dim3(256), 0, st, g, c, E[0], E[1], E[2], B[0], B[1], B[2], h);
+        hipLaunchKernelGGL(k_bhalf_tiled<false>, nb, dim3(BT_THREADS), 0, st, g, c, E[0], E[1], E[2], B[0], B[1],
+                           B[2], h);
     return hipGetLastError();
 }
 

@@ -46,6 +46,7 @@ struct InstDesc {
     int* err;
     int* count;              // particles in the arrays
     int* sorted;             // particles inside the tile ranges of the last sort
+    int* rest_n;             // entries on the species' rest list (the list is `rank`, idle between sorts)
     int capacity;
     float hdt;               // dt / 2
     double jscale[3];
@@ -72,7 +73,7 @@ hipError_t launch_batch_sort(const InstDesc* d, int n, int max_particles, int ma
                              hipStream_t st);
 hipError_t launch_batch_tile(const InstDesc* d, const int* tile_begin, int n, int total_tiles, int threads,
                              size_t lds_bytes, hipStream_t st);
-hipError_t launch_batch_rest(const InstDesc* d, int n, int max_count, hipStream_t st);
+hipError_t launch_batch_rest(const InstDesc* d, int n, hipStream_t st);
 hipError_t launch_batch_jfinal(const InstDesc* d, int n, int max_cells, hipStream_t st);
 hipError_t launch_batch_binomial(const InstDesc* d, int n, int max_cells, hipStream_t st);
 hipError_t launch_batch_bhalf(const InstDesc* d, int n, int max_cells, hipStream_t st);
@@ -131,12 +132,16 @@ hipError_t launch_sort(const Geom& g, const TileGeom& t, const SpeciesDev& src, 
 // fused tile kernel (pic_tile.hip)
 size_t tile_lds_bytes(const TileGeom& t, int guard);
 // toff: tile ranges of the species' last sort
+// rest_n / rest_idx: the species' rest list (counter zeroed here, indices appended by the kernel)
 hipError_t launch_pic_tile(const Geom& g, const TileGeom& t, int guard, int threads, const FieldPtrs& f,
-                           const SpeciesDev& s, const int* toff, unsigned long long* acc, int* d_err, hipStream_t st);
-// rest pass after the tile kernel: particles it marked as beyond their tile's
-// guard (cell -2 - c) and those appended after the last sort (index >= sorted)
+                           const SpeciesDev& s, const int* toff, unsigned long long* acc, int* d_err, int* rest_n,
+                           int* rest_idx, hipStream_t st);
+// rest pass after the tile kernel: the particles on its rest list (beyond
+// their tile's guard, marked cell -2 - c) and those appended after the last
+// sort (index >= sorted)
 hipError_t launch_tile_rest(const Geom& g, const FieldPtrs& f, const SpeciesDev& s, const int* d_sorted,
-                            const int* d_count, int max_count, unsigned long long* acc, int* d_err, hipStream_t st);
+                            const int* d_count, const int* rest_n, const int* rest_idx, unsigned long long* acc,
+                            int* d_err, hipStream_t st);
 
 // field kernels (pic_fields.hip)
 hipError_t launch_bhalf(const Geom& g, int pd, const PDCoef& c, float* const E[3], float* const B[3], float h,

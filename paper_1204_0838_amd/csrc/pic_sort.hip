@@ -2,18 +2,19 @@
 //
 // Key of a particle = tile-major cell index: tile * Tcells + local cell.  A
 // histogram over keys (int atomics; the returned value is the particle's rank
-// within its cell), an exclusive scan of the histogram and a scatter place
-// every tile's particles contiguously.  Removed particles (cell < 0, or
-// outside a moving window) are dropped.
+// within its cell), an exclusive scan of the histogram, a scatter of each
+// particle's index to its destination and a gather of the particle data by
+// destination place every tile's particles contiguously.  Removed particles
+// (cell < 0, or outside a moving window) are dropped.
 //
 // Inside a tile the cell-sorted sequence is stored block-transposed: each full
 // block of 64*D particles (D = the interleave depth) is written as a D x 64
 // transpose, so the 64 lanes of a wavefront that reads the block in order see
 // particles D apart in cell order -- different cells at D >= particles per
 // cell -- and their LDS current atomics rarely hit the same address, while
-// the loads stay coalesced.  For particles that kept their cell since the last
-// sort the scatter is an in-place streaming copy (the same permutation is
-// recomputed from the same key and rank).
+// the loads stay coalesced.  Particles that kept their cell since the last
+// sort mostly keep their place (the histogram hands out ranks in row order),
+// so the gather is close to a streaming copy.
 #include "pic_internal.h"
 #include "pic_particle_ops.h"
 
@@ -180,14 +181,24 @@ __device__ __forceinline__ void scatter_one(const Geom& g, const TileGeom& t, co
             dest = tb + b0 + (k % depth) * 64 + k / depth;
         }
     }
-    dst.cell[dest] = cl;
+    dst.cell[dest] = p;   // the source index; k_sort_gather replaces it with the particle
+}
+
+// Second pass of the permutation, over destinations: dst.cell[i] holds the
+// source index (written by scatter_one), every array is copied from there.
+// The stores are coalesced, and so are most loads (particles that kept their
+// cell keep their place), where scattering all nine arrays from the source
+// side would scatter every store.
+__device__ __forceinline__ void gather_one(const SpeciesDev& src, const SpeciesDev& dst, int i) {
+    const int p = dst.cell[i];
+    dst.cell[i] = src.cell[p];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        dst.off[d][dest] = src.off[d][p];
-        dst.u[d][dest] = src.u[d][p];
+        dst.off[d][i] = src.off[d][p];
+        dst.u[d][i] = src.u[d][p];
     }
-    dst.w[dest] = src.w[p];
-    dst.id[dest] = src.id[p];
+    dst.w[i] = src.w[p];
+    dst.id[i] = src.id[p];
 }
 
 __global__ void __launch_bounds__(256) k_sort_scatter(Geom g, TileGeom t, SpeciesDev src, SpeciesDev dst,
@@ -196,6 +207,13 @@ __global__ void __launch_bounds__(256) k_sort_scatter(Geom g, TileGeom t, Specie
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= *d_count) return;
     scatter_one(g, t, src, dst, p, rank, off, depth);
+}
+
+__global__ void __launch_bounds__(256) k_sort_gather(SpeciesDev src, SpeciesDev dst, const int* __restrict__ off,
+                                                     int nkeys) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= off[nkeys]) return;
+    gather_one(src, dst, i);
 }
 
 // New live count = total of the histogram.
@@ -261,6 +279,14 @@ __global__ void __launch_bounds__(256) k_batch_sort_scatter(const InstDesc* __re
     scatter_one(g, t, src, dst, p, d.rank, d.hist, d.depth);
 }
 
+__global__ void __launch_bounds__(256) k_batch_sort_gather(const InstDesc* __restrict__ tab) {
+    const InstDesc& d = tab[blockIdx.y];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (!d.sorting || i >= d.hist[d.nkeys]) return;
+    const SpeciesDev src = d.s, dst = d.alt;
+    gather_one(src, dst, i);
+}
+
 __global__ void __launch_bounds__(256) k_batch_sort_finish(const InstDesc* __restrict__ tab) {
     const InstDesc& d = tab[blockIdx.y];
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -284,6 +310,7 @@ hipError_t launch_batch_sort(const InstDesc* d, int n, int max_particles, int ma
     hipLaunchKernelGGL(k_batch_scan_sums, dim3(1, n), dim3(1024), 0, st, d);
     hipLaunchKernelGGL(k_batch_scan_apply, dim3(nb, n), dim3(1024), 0, st, d);
     hipLaunchKernelGGL(k_batch_sort_scatter, dim3((np + 255) / 256, n), dim3(256), 0, st, d);
+    hipLaunchKernelGGL(k_batch_sort_gather, dim3((np + 255) / 256, n), dim3(256), 0, st, d);
     hipLaunchKernelGGL(k_batch_sort_finish, dim3((max_tiles1 + 255) / 256, n), dim3(256), 0, st, d);
     return hipGetLastError();
 }
@@ -304,6 +331,7 @@ hipError_t launch_sort(const Geom& g, const TileGeom& t, const SpeciesDev& src, 
     hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(1024), 0, st, hist, n, sums, hist);
     hipLaunchKernelGGL(k_sort_scatter, dim3((np + 255) / 256), dim3(256), 0, st, g, t, src, dst, d_count, rank, hist,
                        depth);
+    hipLaunchKernelGGL(k_sort_gather, dim3((np + 255) / 256), dim3(256), 0, st, src, dst, hist, nkeys);
     hipLaunchKernelGGL(k_sort_finish, dim3(1), dim3(1), 0, st, hist, nkeys, d_count, d_sorted);
     hipLaunchKernelGGL(k_tile_offsets, dim3((t.ntiles + 1 + 255) / 256), dim3(256), 0, st, hist, t.tcells, t.ntiles,
                        toff);

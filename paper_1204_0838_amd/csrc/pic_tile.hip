@@ -7,10 +7,11 @@
 //   particles still within `guard` cells of the tile: gather from LDS,
 //     deposit with LDS 64-bit atomics;
 //   particles that drifted further since the last sort: left for a second
-//     kernel (their cell index is replaced by -2 - cell), which gathers from
-//     global memory and deposits with global atomics (the same arithmetic).
-//     Keeping that path out of the tile kernel keeps its loop free of calls,
-//     so the kernel arguments stay in scalar registers.
+//     kernel (their cell index is replaced by -2 - cell and their index is
+//     appended to the species' rest list, one atomic per wavefront), which
+//     gathers from global memory and deposits with global atomics (the same
+//     arithmetic).  Keeping that path out of the tile kernel keeps its loop
+//     free of calls, so the kernel arguments stay in scalar registers.
 // Finally the non-zero LDS current is added to the global fixed-point
 // accumulator in one atomic pass.  Every value goes through the same device
 // functions as the split kernels, so the fused and split paths agree bit for
@@ -116,6 +117,7 @@ template <int NT, int TX = 0, int TY = 0, int TZ = 0, int GD = -1>
 __device__ __forceinline__ void tile_body(const Geom& g, const TileGeom& t, int guard_rt, const FieldPtrs& f,
                                           const SpeciesDev& s, const int* __restrict__ toff,
                                           unsigned long long* __restrict__ acc, int* __restrict__ d_err,
+                                          int* __restrict__ rest_n, int* __restrict__ rest_idx,
                                           unsigned long long* lds_u64, int tile) {
     const int T[3] = {TX > 0 ? TX : t.T[0], TY > 0 ? TY : t.T[1], TZ > 0 ? TZ : t.T[2]};
     const int guard = GD >= 0 ? GD : guard_rt;
@@ -214,6 +216,12 @@ __device__ __forceinline__ void tile_body(const Geom& g, const TileGeom& t, int 
         }
         if (!inside) {   // beyond the guard: the rest pass takes it
             s.cell[p] = -2 - cell;
+            const unsigned long long m = __ballot(1);   // the lanes in this branch
+            const int lane = __lane_id(), leader = __ffsll((long long)m) - 1;
+            int base = 0;
+            if (lane == leader) base = atomicAdd(rest_n, __popcll(m));
+            base = __shfl(base, leader);
+            rest_idx[base + __popcll(m & ((1ull << lane) - 1ull))] = p;
             continue;
         }
         const float o0[3] = {o[0], o[1], o[2]};
@@ -278,11 +286,12 @@ __device__ __forceinline__ void tile_body(const Geom& g, const TileGeom& t, int 
 template <int NT, int TX = 0, int TY = 0, int TZ = 0, int GD = -1>
 __global__ void __launch_bounds__(NT) k_pic_tile(Geom g, TileGeom t, int guard, FieldPtrs f, SpeciesDev s,
                                                  const int* __restrict__ toff, unsigned long long* __restrict__ acc,
-                                                 int* __restrict__ d_err) {
+                                                 int* __restrict__ d_err, int* __restrict__ rest_n,
+                                                 int* __restrict__ rest_idx) {
     extern __shared__ unsigned long long lds_u64[];
     const int tile = xcd_tile(blockIdx.x, t.ntiles, t.nt[0]);
     if (tile >= t.ntiles) return;
-    tile_body<NT, TX, TY, TZ, GD>(g, t, guard, f, s, toff, acc, d_err, lds_u64, tile);
+    tile_body<NT, TX, TY, TZ, GD>(g, t, guard, f, s, toff, acc, d_err, rest_n, rest_idx, lds_u64, tile);
 }
 
 // Batched form: the work list is the concatenation of every member's tiles
@@ -304,24 +313,25 @@ __global__ void __launch_bounds__(NT) k_batch_tile(const InstDesc* __restrict__ 
     const TileGeom t = d.t;
     const FieldPtrs f = d.f;
     const SpeciesDev s = step_arrays(d);
-    tile_body<NT>(g, t, d.guard, f, s, d.toff, d.acc, d.err, lds_u64, ft - tile_begin[lo]);
+    tile_body<NT>(g, t, d.guard, f, s, d.toff, d.acc, d.err, d.rest_n, d.rank, lds_u64, ft - tile_begin[lo]);
 }
 
-// The rest pass, after the tile kernel: particles marked by it (cell -2 - c,
-// below the sorted count) and particles appended after the last sort (not in
-// any tile range, index >= sorted) take the same step through global memory.
-__device__ __forceinline__ bool rest_needed(const Geom& g, int p, int sorted, int cell) {
-    return p < sorted ? cell <= -2 : (unsigned)cell < (unsigned)g.ncell;
-}
-
-__device__ __forceinline__ void rest_one(const Geom& g, const FieldPtrs& f, const SpeciesDev& s, int p, int sorted,
-                                         unsigned long long* acc, int* d_err) {
-    int cell = s.cell[p];
-    int c[3];
-    if (p < sorted) {
-        cell = -2 - cell;   // the tile kernel already applied the window cut
-        decompose(g, cell, c);
+// The rest pass, after the tile kernel: the particles on the species' rest
+// list (marked by the tile kernel with cell -2 - c) and those appended after
+// the last sort (index >= sorted, in no tile range) take the same step
+// through global memory.  Item i < n_rest is list entry i, item n_rest + j
+// is particle sorted + j.
+__device__ __forceinline__ void rest_item(const Geom& g, const FieldPtrs& f, const SpeciesDev& s, int i, int nrest,
+                                          int sorted, const int* __restrict__ rest_idx,
+                                          unsigned long long* acc, int* d_err) {
+    int p, c[3];
+    if (i < nrest) {
+        p = rest_idx[i];
+        decompose(g, -2 - s.cell[p], c);   // the tile kernel already applied the window cut
     } else {
+        p = sorted + (i - nrest);
+        const int cell = s.cell[p];
+        if ((unsigned)cell >= (unsigned)g.ncell) return;
         decompose(g, cell, c);
         if (window_killed(g, c[0])) {
             s.cell[p] = -1;
@@ -332,42 +342,19 @@ __device__ __forceinline__ void rest_one(const Geom& g, const FieldPtrs& f, cons
     if (errs) atomicOr(d_err, errs);
 }
 
-// Grid-stride scan of the cell indices of [0, count): each thread keeps
-// kRestLoads coalesced loads in flight, then runs the (rare) particles that
-// need the global path one at a time.
-constexpr int kRestLoads = 8;
 constexpr int kRestThreads = 256;
-
-__device__ __forceinline__ void rest_scan(const Geom& g, const FieldPtrs& f, const SpeciesDev& s, int sorted,
-                                          int count, unsigned long long* acc, int* d_err) {
-    const long long stride = (long long)gridDim.x * kRestThreads;
-    for (long long p0 = (long long)blockIdx.x * kRestThreads + threadIdx.x; p0 < count; p0 += kRestLoads * stride) {
-        int v[kRestLoads];
-#pragma unroll
-        for (int k = 0; k < kRestLoads; ++k) {
-            const long long p = p0 + k * stride;
-            v[k] = p < count ? s.cell[p] : -1;
-        }
-        unsigned need = 0;
-#pragma unroll
-        for (int k = 0; k < kRestLoads; ++k) {
-            const long long p = p0 + k * stride;
-            need |= (p < count && rest_needed(g, (int)p, sorted, v[k]) ? 1u : 0u) << k;
-        }
-        while (need) {
-            const int k = __ffs(need) - 1;
-            need &= need - 1;
-            rest_one(g, f, s, (int)(p0 + k * stride), sorted, acc, d_err);
-        }
-    }
-}
 
 __global__ void __launch_bounds__(kRestThreads) k_tile_rest(Geom g, FieldPtrs f, SpeciesDev s,
                                                             const int* __restrict__ d_sorted,
                                                             const int* __restrict__ d_count,
+                                                            const int* __restrict__ rest_n,
+                                                            const int* __restrict__ rest_idx,
                                                             unsigned long long* __restrict__ acc,
                                                             int* __restrict__ d_err) {
-    rest_scan(g, f, s, *d_sorted, *d_count, acc, d_err);
+    const int nrest = *rest_n, sorted = *d_sorted;
+    const int total = nrest + max(0, *d_count - sorted);
+    for (int i = blockIdx.x * kRestThreads + threadIdx.x; i < total; i += gridDim.x * kRestThreads)
+        rest_item(g, f, s, i, nrest, sorted, rest_idx, acc, d_err);
 }
 
 __global__ void __launch_bounds__(kRestThreads) k_batch_rest(const InstDesc* __restrict__ tab) {
@@ -375,16 +362,19 @@ __global__ void __launch_bounds__(kRestThreads) k_batch_rest(const InstDesc* __r
     const Geom g = d.g;
     const FieldPtrs f = d.f;
     const SpeciesDev s = step_arrays(d);
-    rest_scan(g, f, s, *d.sorted, *d.count, d.acc, d.err);
+    const int nrest = *d.rest_n, sorted = *d.sorted;
+    const int total = nrest + max(0, *d.count - sorted);
+    for (int i = blockIdx.x * kRestThreads + threadIdx.x; i < total; i += gridDim.x * kRestThreads)
+        rest_item(g, f, s, i, nrest, sorted, d.rank, d.acc, d.err);
 }
 
-// Blocks of the rest scan: enough for about kRestLoads loads per thread and
-// pass, at most 2048 in all (eight per compute unit).
-static int rest_blocks(int max_count, int members) {
-    const long long per = (long long)kRestThreads * kRestLoads;
-    const long long want = (max_count + per - 1) / per;
-    const long long cap = std::max(1, 2048 / std::max(1, members));
-    return (int)std::max(1LL, std::min(want, cap));
+// Rest-list counters start at zero before each tile launch (a kernel, not a
+// memset, so that a captured step stays valid).
+__global__ void k_zero_rest(int* rest_n) { *rest_n = 0; }
+
+__global__ void k_batch_zero_rest(const InstDesc* __restrict__ tab, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) *tab[i].rest_n = 0;
 }
 
 size_t tile_lds_bytes(const TileGeom& t, int guard) {
@@ -397,14 +387,15 @@ size_t tile_lds_bytes(const TileGeom& t, int guard) {
 template <int NT, int TX = 0, int TY = 0, int TZ = 0, int GD = -1>
 static hipError_t launch_tile_nt(const Geom& g, const TileGeom& t, int guard, const FieldPtrs& f,
                                  const SpeciesDev& s, const int* toff, unsigned long long* acc,
-                                 int* d_err, hipStream_t st) {
+                                 int* d_err, int* rest_n, int* rest_idx, hipStream_t st) {
     const size_t lds = tile_lds_bytes(t, guard);
     const int nb = xcd_blocks(t.ntiles, t.nt[0]);
     hipError_t e = hipFuncSetAttribute((const void*)k_pic_tile<NT, TX, TY, TZ, GD>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_zero_rest, dim3(1), dim3(1), 0, st, rest_n);
     hipLaunchKernelGGL((k_pic_tile<NT, TX, TY, TZ, GD>), dim3(nb), dim3(NT), lds, st, g, t, guard, f, s, toff, acc,
-                       d_err);
+                       d_err, rest_n, rest_idx);
     return hipGetLastError();
 }
 
@@ -413,23 +404,23 @@ static hipError_t launch_tile_nt(const Geom& g, const TileGeom& t, int guard, co
 template <int NT>
 static hipError_t launch_tile_shape(const Geom& g, const TileGeom& t, int guard, const FieldPtrs& f,
                                     const SpeciesDev& s, const int* toff, unsigned long long* acc, int* d_err,
-                                    hipStream_t st) {
+                                    int* rest_n, int* rest_idx, hipStream_t st) {
     if (t.T[0] == 8 && t.T[1] == 8 && t.T[2] == 8) {
-        if (guard == 1) return launch_tile_nt<NT, 8, 8, 8, 1>(g, t, guard, f, s, toff, acc, d_err, st);
-        if (guard == 0) return launch_tile_nt<NT, 8, 8, 8, 0>(g, t, guard, f, s, toff, acc, d_err, st);
+        if (guard == 1) return launch_tile_nt<NT, 8, 8, 8, 1>(g, t, guard, f, s, toff, acc, d_err, rest_n, rest_idx, st);
+        if (guard == 0) return launch_tile_nt<NT, 8, 8, 8, 0>(g, t, guard, f, s, toff, acc, d_err, rest_n, rest_idx, st);
     }
     if (t.T[0] == 8 && t.T[1] == 8 && t.T[2] == 4 && guard == 1)
-        return launch_tile_nt<NT, 8, 8, 4, 1>(g, t, guard, f, s, toff, acc, d_err, st);
-    return launch_tile_nt<NT>(g, t, guard, f, s, toff, acc, d_err, st);
+        return launch_tile_nt<NT, 8, 8, 4, 1>(g, t, guard, f, s, toff, acc, d_err, rest_n, rest_idx, st);
+    return launch_tile_nt<NT>(g, t, guard, f, s, toff, acc, d_err, rest_n, rest_idx, st);
 }
 
 hipError_t launch_pic_tile(const Geom& g, const TileGeom& t, int guard, int threads, const FieldPtrs& f,
                            const SpeciesDev& s, const int* toff, unsigned long long* acc,
-                           int* d_err, hipStream_t st) {
+                           int* d_err, int* rest_n, int* rest_idx, hipStream_t st) {
     switch (threads) {
-        case 256: return launch_tile_shape<256>(g, t, guard, f, s, toff, acc, d_err, st);
-        case 1024: return launch_tile_shape<1024>(g, t, guard, f, s, toff, acc, d_err, st);
-        default: return launch_tile_shape<512>(g, t, guard, f, s, toff, acc, d_err, st);
+        case 256: return launch_tile_shape<256>(g, t, guard, f, s, toff, acc, d_err, rest_n, rest_idx, st);
+        case 1024: return launch_tile_shape<1024>(g, t, guard, f, s, toff, acc, d_err, rest_n, rest_idx, st);
+        default: return launch_tile_shape<512>(g, t, guard, f, s, toff, acc, d_err, rest_n, rest_idx, st);
     }
 }
 
@@ -440,6 +431,7 @@ static hipError_t launch_batch_tile_nt(const InstDesc* d, const int* tile_begin,
     hipError_t e = hipFuncSetAttribute((const void*)k_batch_tile<NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
     if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_batch_zero_rest, dim3((n + 63) / 64), dim3(64), 0, st, d, n);
     hipLaunchKernelGGL(k_batch_tile<NT>, dim3(nb), dim3(NT), lds, st, d, tile_begin, n, total);
     return hipGetLastError();
 }
@@ -454,17 +446,19 @@ hipError_t launch_batch_tile(const InstDesc* d, const int* tile_begin, int n, in
     }
 }
 
-hipError_t launch_batch_rest(const InstDesc* d, int n, int max_count, hipStream_t st) {
-    if (n <= 0 || max_count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_batch_rest, dim3(rest_blocks(max_count, n), n), dim3(kRestThreads), 0, st, d);
+// Rest pass grids: a fixed number of blocks walking the items (list entries
+// plus appended particles, a small share of the species in a step).
+hipError_t launch_batch_rest(const InstDesc* d, int n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_rest, dim3(std::max(1, 1024 / n), n), dim3(kRestThreads), 0, st, d);
     return hipGetLastError();
 }
 
 hipError_t launch_tile_rest(const Geom& g, const FieldPtrs& f, const SpeciesDev& s, const int* d_sorted,
-                            const int* d_count, int max_count, unsigned long long* acc, int* d_err, hipStream_t st) {
-    if (max_count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tile_rest, dim3(rest_blocks(max_count, 1)), dim3(kRestThreads), 0, st, g, f, s, d_sorted,
-                       d_count, acc, d_err);
+                            const int* d_count, const int* rest_n, const int* rest_idx, unsigned long long* acc,
+                            int* d_err, hipStream_t st) {
+    hipLaunchKernelGGL(k_tile_rest, dim3(1024), dim3(kRestThreads), 0, st, g, f, s, d_sorted, d_count, rest_n,
+                       rest_idx, acc, d_err);
     return hipGetLastError();
 }
 
