@@ -769,11 +769,12 @@ pic_status batch_one_step(pic_batch* b) {
         // for the field phase and re-stage the others then
     }
     // current read-out and field update (member-wide parts of the last table)
-    int max_cells = 0, max_plane = 0;
+    int max_cells = 0, max_plane = 0, max_btiles = 0;
     bool any_bin = false, any_laser = false, any_move = false;
     for (int i = 0; i < n; ++i) {
         pic_ctx* c = b->m[i];
         max_cells = std::max(max_cells, c->g.ncell);
+        max_btiles = std::max(max_btiles, bhalf_tiles(c->g.n));
         max_plane = std::max(max_plane, c->g.n[1] * c->g.n[2]);
         any_bin = any_bin || c->desc.jpost == PIC_JPOST_BINOMIAL;
         const double t = c->step * c->desc.dt;
@@ -786,11 +787,11 @@ pic_status batch_one_step(pic_batch* b) {
     if (any_bin) BHIPCHK(b, launch_batch_binomial(dtab, n, max_cells, b->stream));
     PICCHK(bend(b, PH_JPOST, t3));
     PICCHK(bmark(b, &t4));
-    BHIPCHK(b, launch_batch_bhalf(dtab, n, max_cells, b->stream));
+    BHIPCHK(b, launch_batch_bhalf(dtab, n, max_btiles, b->stream));
     if (any_laser) BHIPCHK(b, launch_batch_laser(dtab, n, 0, max_plane, b->stream));
     BHIPCHK(b, launch_batch_efull(dtab, n, max_cells, b->stream));
     if (any_laser) BHIPCHK(b, launch_batch_laser(dtab, n, 1, max_plane, b->stream));
-    BHIPCHK(b, launch_batch_bhalf(dtab, n, max_cells, b->stream));
+    BHIPCHK(b, launch_batch_bhalf(dtab, n, max_btiles, b->stream));
     if (any_laser) BHIPCHK(b, launch_batch_laser(dtab, n, 2, max_plane, b->stream));
     PICCHK(bend(b, PH_FIELD, t4));
     PICCHK(bmark(b, &t5));

@@ -41,83 +41,17 @@ __device__ __forceinline__ Nbr neighbours(const Geom& g, int idx) {
 
 __device__ __forceinline__ int at(const Geom& g, int i, int j, int k) { return i + g.n[0] * (j + g.n[1] * k); }
 
-// Transverse smoothing S_axis of F at cell (i,j,k) (Section 2 stencil):
-// centre alpha_axis, +-t1 neighbours beta_t1, +-t2 neighbours beta_t2, the four
-// corners gamma_{t1 t2}; t1 = axis+1, t2 = axis+2 cyclically.  x neighbours
-// across the window seam read as zero.  Coordinates are of the evaluation
-// point, which may itself be the +1 neighbour of the cell being updated.
-template <int AXIS>
-__device__ __forceinline__ float smooth(const Geom& g, const PDCoef& c, const float* __restrict__ F, int i, int j,
-                                        int k) {
-    // neighbours of (i,j,k) along each axis, with seam handling on x
-    const int ip = i + 1 == g.n[0] ? 0 : i + 1, im = i == 0 ? g.n[0] - 1 : i - 1;
-    const int jp = j + 1 == g.n[1] ? 0 : j + 1, jm = j == 0 ? g.n[1] - 1 : j - 1;
-    const int kp = k + 1 == g.n[2] ? 0 : k + 1, km = k == 0 ? g.n[2] - 1 : k - 1;
-    bool xp = true, xm = true;
-    if (g.window) {
-        int xw = i - g.origin;
-        if (xw < 0) xw += g.n[0];
-        xp = xw != g.n[0] - 1;
-        xm = xw != 0;
-    }
-    const float ctr = F[at(g, i, j, k)];
-    if (AXIS == 0) {   // smoothing in y (beta_y) and z (beta_z), corners gamma_yz
-        const float ny = F[at(g, i, jp, k)] + F[at(g, i, jm, k)];
-        const float nz = F[at(g, i, j, kp)] + F[at(g, i, j, km)];
-        const float cr = (F[at(g, i, jp, kp)] + F[at(g, i, jm, kp)]) + (F[at(g, i, jp, km)] + F[at(g, i, jm, km)]);
-        return fmaf(c.gam[0], cr, fmaf(c.beta[2], nz, fmaf(c.beta[1], ny, c.alpha[0] * ctr)));
-    } else if (AXIS == 1) {   // smoothing in z (beta_z) and x (beta_x), corners gamma_zx
-        const float nz = F[at(g, i, j, kp)] + F[at(g, i, j, km)];
-        const float fxp = xp ? F[at(g, ip, j, k)] : 0.0f, fxm = xm ? F[at(g, im, j, k)] : 0.0f;
-        const float nx = fxp + fxm;
-        const float cr = ((xp ? F[at(g, ip, j, kp)] : 0.0f) + (xm ? F[at(g, im, j, kp)] : 0.0f)) +
-                         ((xp ? F[at(g, ip, j, km)] : 0.0f) + (xm ? F[at(g, im, j, km)] : 0.0f));
-        return fmaf(c.gam[1], cr, fmaf(c.beta[0], nx, fmaf(c.beta[2], nz, c.alpha[1] * ctr)));
-    } else {   // smoothing in x (beta_x) and y (beta_y), corners gamma_xy
-        const float fxp = xp ? F[at(g, ip, j, k)] : 0.0f, fxm = xm ? F[at(g, im, j, k)] : 0.0f;
-        const float nx = fxp + fxm;
-        const float ny = F[at(g, i, jp, k)] + F[at(g, i, jm, k)];
-        const float cr = ((xp ? F[at(g, ip, jp, k)] : 0.0f) + (xm ? F[at(g, im, jp, k)] : 0.0f)) +
-                         ((xp ? F[at(g, ip, jm, k)] : 0.0f) + (xm ? F[at(g, im, jm, k)] : 0.0f));
-        return fmaf(c.gam[2], cr, fmaf(c.beta[1], ny, fmaf(c.beta[0], nx, c.alpha[2] * ctr)));
-    }
-}
-
-// Value of S_axis F at (i,j,k), or F itself for the Yee scheme.
-template <bool PD, int AXIS>
-__device__ __forceinline__ float sval(const Geom& g, const PDCoef& c, const float* __restrict__ F, int i, int j,
-                                      int k) {
-    if (PD) return smooth<AXIS>(g, c, F, i, j, k);
-    return F[at(g, i, j, k)];
-}
-
-// B -= h curl' E with forward differences; curl'_x = D_y S_y E_z - D_z S_z E_y, cyclic.
-template <bool PD>
-__device__ __forceinline__ void bhalf_cell(const Geom& g, const PDCoef& c, const float* __restrict__ Ex,
-                                           const float* __restrict__ Ey, const float* __restrict__ Ez,
-                                           float* __restrict__ Bx, float* __restrict__ By, float* __restrict__ Bz,
-                                           float h, int idx) {
-    const Nbr n = neighbours(g, idx);
-    // E at the +x neighbour is zero across the window seam
-    const float dyEz = (sval<PD, 1>(g, c, Ez, n.i, n.jp, n.k) - sval<PD, 1>(g, c, Ez, n.i, n.j, n.k)) * g.inv_d[1];
-    const float dzEy = (sval<PD, 2>(g, c, Ey, n.i, n.j, n.kp) - sval<PD, 2>(g, c, Ey, n.i, n.j, n.k)) * g.inv_d[2];
-    const float dzEx = (sval<PD, 2>(g, c, Ex, n.i, n.j, n.kp) - sval<PD, 2>(g, c, Ex, n.i, n.j, n.k)) * g.inv_d[2];
-    const float ezp = n.xp_ok ? sval<PD, 0>(g, c, Ez, n.ip, n.j, n.k) : 0.0f;
-    const float eyp = n.xp_ok ? sval<PD, 0>(g, c, Ey, n.ip, n.j, n.k) : 0.0f;
-    const float dxEz = (ezp - sval<PD, 0>(g, c, Ez, n.i, n.j, n.k)) * g.inv_d[0];
-    const float dxEy = (eyp - sval<PD, 0>(g, c, Ey, n.i, n.j, n.k)) * g.inv_d[0];
-    const float dyEx = (sval<PD, 1>(g, c, Ex, n.i, n.jp, n.k) - sval<PD, 1>(g, c, Ex, n.i, n.j, n.k)) * g.inv_d[1];
-    Bx[idx] -= h * (dyEz - dzEy);
-    By[idx] -= h * (dzEx - dxEz);
-    Bz[idx] -= h * (dxEy - dyEx);
-}
-
-// LDS-tiled form of the B half step (the single-grid production path): E is
-// staged on a tile of BT_X x BT_Y x BT_Z cells plus a one-cell halo, in window
-// coordinates, with zeros beyond the window's two ends (or periodic images);
-// a neighbour across the window seam is then exactly a zero-filled halo cell,
-// as in bhalf_cell.  Every smoothed value and difference is the same
-// expression in the same order as bhalf_cell, so the results are identical.
+// B -= h curl' E with forward differences, curl'_x = D_y S_y E_z - D_z S_z E_y
+// (cyclic), where S_axis is the transverse smoothing of the Section 2 stencil
+// (identity for the Yee scheme): centre alpha_axis, +-t1 neighbours beta_t1,
+// +-t2 neighbours beta_t2, the four corners gamma_{t1 t2}, t1 = axis + 1 and
+// t2 = axis + 2 cyclically.  y and z are periodic; with the moving window,
+// x neighbours across the window seam read as zero.
+//
+// LDS-tiled: E is staged on a tile of BT_X x BT_Y x BT_Z cells plus a
+// one-cell halo, in window coordinates, with zeros beyond the window's two
+// ends (or periodic images without a window), so a neighbour across the seam
+// is exactly a zero-filled halo cell.
 constexpr int BT_X = 32, BT_Y = 8, BT_Z = 4, BT_THREADS = 256;
 constexpr int BS_X = BT_X + 2, BS_Y = BT_Y + 2, BS_Z = BT_Z + 2, BS_N = BS_X * BS_Y * BS_Z;
 
@@ -149,13 +83,13 @@ __device__ __forceinline__ float sval_l(const PDCoef& c, const float* F, int o) 
     return F[o];
 }
 
+// One tile (tile coordinates bx, by, bz) of the LDS-tiled B half step.
 template <bool PD>
-__global__ void __launch_bounds__(BT_THREADS) k_bhalf_tiled(Geom g, PDCoef c, const float* __restrict__ Ex,
-                                                           const float* __restrict__ Ey,
-                                                           const float* __restrict__ Ez, float* __restrict__ Bx,
-                                                           float* __restrict__ By, float* __restrict__ Bz, float h) {
-    __shared__ float El[3][BS_N];
-    const int t0[3] = {(int)blockIdx.x * BT_X, (int)blockIdx.y * BT_Y, (int)blockIdx.z * BT_Z};
+__device__ __forceinline__ void bhalf_tile(const Geom& g, const PDCoef& c, const float* __restrict__ Ex,
+                                           const float* __restrict__ Ey, const float* __restrict__ Ez,
+                                           float* __restrict__ Bx, float* __restrict__ By, float* __restrict__ Bz,
+                                           float h, int bx, int by, int bz, float (*El)[BS_N]) {
+    const int t0[3] = {bx * BT_X, by * BT_Y, bz * BT_Z};
     const int origin = g.window ? g.origin : 0;
     constexpr int PER = (BS_N + BT_THREADS - 1) / BT_THREADS;
     float v[PER][3];
@@ -216,6 +150,15 @@ __global__ void __launch_bounds__(BT_THREADS) k_bhalf_tiled(Geom g, PDCoef c, co
         By[idx] -= h * (dzEx - dxEz);
         Bz[idx] -= h * (dxEy - dyEx);
     }
+}
+
+template <bool PD>
+__global__ void __launch_bounds__(BT_THREADS) k_bhalf_tiled(Geom g, PDCoef c, const float* __restrict__ Ex,
+                                                           const float* __restrict__ Ey,
+                                                           const float* __restrict__ Ez, float* __restrict__ Bx,
+                                                           float* __restrict__ By, float* __restrict__ Bz, float h) {
+    __shared__ float El[3][BS_N];
+    bhalf_tile<PD>(g, c, Ex, Ey, Ez, Bx, By, Bz, h, blockIdx.x, blockIdx.y, blockIdx.z, El);
 }
 
 // E += dt (curl B - J) with backward differences.
@@ -292,16 +235,20 @@ __global__ void __launch_bounds__(256) k_binomial(Geom g, const float* __restric
 }
 
 // Batched field kernels: grid y = member.
-__global__ void __launch_bounds__(256) k_batch_bhalf(const InstDesc* __restrict__ tab) {
+// Grid x = tile (x fastest) of the member's grid, y = member.
+__global__ void __launch_bounds__(BT_THREADS) k_batch_bhalf(const InstDesc* __restrict__ tab) {
+    __shared__ float El[3][BS_N];
     const InstDesc& d = tab[blockIdx.y];
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= d.g.ncell) return;
     const Geom g = d.g;
+    const int tx = (g.n[0] + BT_X - 1) / BT_X, ty = (g.n[1] + BT_Y - 1) / BT_Y, tz = (g.n[2] + BT_Z - 1) / BT_Z;
+    const int t = blockIdx.x;
+    if (t >= tx * ty * tz) return;
     const PDCoef c = d.c;
+    const int bx = t % tx, by = (t / tx) % ty, bz = t / (tx * ty);
     if (d.pd)
-        bhalf_cell<true>(g, c, d.f.E[0], d.f.E[1], d.f.E[2], d.f.B[0], d.f.B[1], d.f.B[2], d.hdt, idx);
+        bhalf_tile<true>(g, c, d.f.E[0], d.f.E[1], d.f.E[2], d.f.B[0], d.f.B[1], d.f.B[2], d.hdt, bx, by, bz, El);
     else
-        bhalf_cell<false>(g, c, d.f.E[0], d.f.E[1], d.f.E[2], d.f.B[0], d.f.B[1], d.f.B[2], d.hdt, idx);
+        bhalf_tile<false>(g, c, d.f.E[0], d.f.E[1], d.f.E[2], d.f.B[0], d.f.B[1], d.f.B[2], d.hdt, bx, by, bz, El);
 }
 
 __global__ void __launch_bounds__(256) k_batch_efull(const InstDesc* __restrict__ tab) {
@@ -349,10 +296,14 @@ hipError_t launch_binomial(const Geom& g, float* const src[3], float* const dst[
     return hipGetLastError();
 }
 
-hipError_t launch_batch_bhalf(const InstDesc* d, int n, int max_cells, hipStream_t st) {
-    if (n <= 0 || max_cells <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_batch_bhalf, dim3((max_cells + 255) / 256, n), dim3(256), 0, st, d);
+hipError_t launch_batch_bhalf(const InstDesc* d, int n, int max_tiles, hipStream_t st) {
+    if (n <= 0 || max_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_bhalf, dim3(max_tiles, n), dim3(BT_THREADS), 0, st, d);
     return hipGetLastError();
+}
+
+int bhalf_tiles(const int n[3]) {
+    return ((n[0] + BT_X - 1) / BT_X) * ((n[1] + BT_Y - 1) / BT_Y) * ((n[2] + BT_Z - 1) / BT_Z);
 }
 
 hipError_t launch_batch_efull(const InstDesc* d, int n, int max_cells, hipStream_t st) {

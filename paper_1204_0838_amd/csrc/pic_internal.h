@@ -76,7 +76,9 @@ hipError_t launch_batch_tile(const InstDesc* d, const int* tile_begin, int n, in
 hipError_t launch_batch_rest(const InstDesc* d, int n, hipStream_t st);
 hipError_t launch_batch_jfinal(const InstDesc* d, int n, int max_cells, hipStream_t st);
 hipError_t launch_batch_binomial(const InstDesc* d, int n, int max_cells, hipStream_t st);
-hipError_t launch_batch_bhalf(const InstDesc* d, int n, int max_cells, hipStream_t st);
+// B half step over the members' tiles (max_tiles = the largest bhalf_tiles of a member)
+hipError_t launch_batch_bhalf(const InstDesc* d, int n, int max_tiles, hipStream_t st);
+int bhalf_tiles(const int n[3]);
 hipError_t launch_batch_efull(const InstDesc* d, int n, int max_cells, hipStream_t st);
 // which: 0, 1, 2 = the laser planes in the order they are applied
 hipError_t launch_batch_laser(const InstDesc* d, int n, int which, int max_plane, hipStream_t st);
