@@ -50,6 +50,12 @@ struct GlobalEmitT {
 
 // Tile of workgroup b when chunks of `chunk` consecutive tiles are dealt
 // round-robin to the 8 XCDs (>= ntiles: no tile; grid = xcd_blocks).
+// v mod n in [0, n) for any v; a single compare when v is already inside
+// (the staging and flush loops wrap only at the domain's faces).
+__device__ __forceinline__ int wrap_any(int v, int n) {
+    return (unsigned)v < (unsigned)n ? v : ((v % n) + n) % n;
+}
+
 __device__ __forceinline__ int xcd_tile(int b, int ntiles, int chunk) {
     const int k = b % 8, j = b / 8;
     const int c = k + 8 * (j / chunk);
@@ -146,9 +152,9 @@ __device__ __forceinline__ void tile_body(const Geom& g, const TileGeom& t, int 
         const int ly = rr / fx;
         const int lx = rr - ly * fx;
         int gx = t0[0] - H + lx, gy = t0[1] - H + ly, gz = t0[2] - H + lz;
-        gx = ((gx % g.n[0]) + g.n[0]) % g.n[0];
-        gy = ((gy % g.n[1]) + g.n[1]) % g.n[1];
-        gz = ((gz % g.n[2]) + g.n[2]) % g.n[2];
+        gx = wrap_any(gx, g.n[0]);
+        gy = wrap_any(gy, g.n[1]);
+        gz = wrap_any(gz, g.n[2]);
         const int gi = gx + g.n[0] * (gy + g.n[1] * gz);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -276,9 +282,9 @@ __device__ __forceinline__ void tile_body(const Geom& g, const TileGeom& t, int 
         const int ly = rr / jx;
         const int lx = rr - ly * jx;
         int gx = t0[0] - lo + lx, gy = t0[1] - lo + ly, gz = t0[2] - lo + lz;
-        gx = ((gx % g.n[0]) + g.n[0]) % g.n[0];
-        gy = ((gy % g.n[1]) + g.n[1]) % g.n[1];
-        gz = ((gz % g.n[2]) + g.n[2]) % g.n[2];
+        gx = wrap_any(gx, g.n[0]);
+        gy = wrap_any(gy, g.n[1]);
+        gz = wrap_any(gz, g.n[2]);
         atomicAdd(acc + ((size_t)comp * g.ncell + gx + g.n[0] * (gy + g.n[1] * gz)), v);
     }
 }
