@@ -41,13 +41,17 @@ def key_of(cfg: dict) -> str:
     return "{}x{}x{}|ppc{}|{}".format(*cfg["n"], p[0] * p[1] * p[2], cfg["solver"])
 
 
+def _pad_plane(p: int, m: int) -> int:
+    # the tile kernel pads each LDS z-plane to 8 (mod m) words
+    return p + ((8 - p % m) + m) % m
+
+
 def lds_bytes(c: dict) -> int:
     T, g = c["tile"], c["guard"]
-    fr = 1
-    jr = 1
-    for t in T:
-        fr *= t + 2 * (g + 2)
-        jr *= t + 2 * g + 5
+    f = [t + 2 * (g + 2) for t in T]
+    j = [t + 2 * g + 5 for t in T]
+    fr = _pad_plane(f[0] * f[1], 32) * f[2]
+    jr = _pad_plane(j[0] * j[1], 16) * j[2]
     return 24 * jr + 24 * fr
 
 

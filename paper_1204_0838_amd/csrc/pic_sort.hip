@@ -1,6 +1,7 @@
 // Counting sort of particles into tiles of Tx x Ty x Tz cells.
 //
-// Key of a particle = tile-major cell index: tile * Tcells + local cell.  A
+// Key of a particle = tile-major cell index: tile * Tcells + local cell (in
+// 8x2x4-cell bricks where the tile shape allows, see local_key).  A
 // histogram over keys (int atomics; the returned value is the particle's rank
 // within its cell), an exclusive scan of the histogram, a scatter of each
 // particle's index to its destination and a gather of the particle data by
@@ -20,11 +21,22 @@
 
 namespace pic {
 
+// Cell order inside a tile: for tiles of 8 x 2m x 4k cells, 64-cell bricks
+// of 8x2x4 cells (x fastest, then z, then y inside a brick; bricks y-major),
+// so that a wavefront reading one transposed block of such a brick has its
+// lanes in 8 x-cells of successive z-planes (the tile kernel pads its LDS
+// planes to match); plain x-fastest order for every other shape.
+__device__ __forceinline__ int local_key(const TileGeom& t, int lx, int ly, int lz) {
+    if (t.T[0] == 8 && (t.T[1] & 1) == 0 && (t.T[2] & 3) == 0)
+        return lx + 8 * (lz & 3) + 32 * (ly & 1) + 64 * ((ly >> 1) + (t.T[1] >> 1) * (lz >> 2));
+    return lx + t.T[0] * (ly + t.T[1] * lz);
+}
+
 __device__ __forceinline__ int tile_key(const TileGeom& t, const int c[3]) {
     const int tx = c[0] / t.T[0], ty = c[1] / t.T[1], tz = c[2] / t.T[2];
     const int lx = c[0] - tx * t.T[0], ly = c[1] - ty * t.T[1], lz = c[2] - tz * t.T[2];
     const int tile = tx + t.nt[0] * (ty + t.nt[1] * tz);
-    return tile * t.tcells + lx + t.T[0] * (ly + t.T[1] * lz);
+    return tile * t.tcells + local_key(t, lx, ly, lz);
 }
 
 __device__ __forceinline__ int sort_key(const Geom& g, const TileGeom& t, int cl) {

@@ -114,6 +114,16 @@ __device__ __forceinline__ int push_deposit_global(const Geom& g, const FieldPtr
     return errs;
 }
 
+// Plane (z) strides of the two LDS regions, padded so that one z step moves
+// the address by 8 banks: fields in 4-byte words mod 32, current in 8-byte
+// words mod 16.  The sort stores a tile's cells as 8x2x4 bricks (x, then 4 z,
+// then 2 y), so at 8 particles per cell the lanes of one LDS pass (32 for
+// the b32 field reads, 16 for the int64 atomics) sit in 8 x-cells of 4 (or
+// 2) successive z-planes and address disjoint banks.
+__host__ __device__ constexpr int pad_plane(int p, int m) { return p + ((8 - p % m) + m) % m; }
+__host__ __device__ constexpr int field_plane(int fx, int fy) { return pad_plane(fx * fy, 32); }
+__host__ __device__ constexpr int cur_plane(int jx, int jy) { return pad_plane(jx * jy, 16); }
+
 // Body of the fused step for one tile (the whole workgroup cooperates).
 // TX, TY, TZ > 0 and GD >= 0 fix the tile shape and guard at compile time:
 // every LDS stride is then a constant and each particle's current atomics
@@ -138,15 +148,17 @@ __device__ __forceinline__ void tile_body(const Geom& g, const TileGeom& t, int 
     const int H = guard + 2;
     // LDS geometry (region sizes use the full tile size T, ragged tiles use part of it)
     const int fx = T[0] + 2 * H, fy = T[1] + 2 * H, fz = T[2] + 2 * H;
-    const int fr = fx * fy * fz;
+    const int fpl = field_plane(fx, fy);
+    const int fr = fpl * fz;
     const int jx = T[0] + 2 * guard + 5, jy = T[1] + 2 * guard + 5, jz = T[2] + 2 * guard + 5;
-    const int jr = jx * jy * jz;
+    const int jpl = cur_plane(jx, jy);
+    const int jr = jpl * jz;
     unsigned long long* Jl = lds_u64;
     float* Fl = reinterpret_cast<float*>(lds_u64 + 3 * jr);
 
     for (int i = threadIdx.x; i < 3 * jr; i += NT) Jl[i] = 0ull;
     // stage E, B (tile + halo, periodic wrap in storage coordinates)
-    for (int i = threadIdx.x; i < fr; i += NT) {
+    for (int i = threadIdx.x; i < fx * fy * fz; i += NT) {
         const int lz = i / (fx * fy);
         const int rr = i - lz * fx * fy;
         const int ly = rr / fx;
@@ -156,18 +168,19 @@ __device__ __forceinline__ void tile_body(const Geom& g, const TileGeom& t, int 
         gy = wrap_any(gy, g.n[1]);
         gz = wrap_any(gz, g.n[2]);
         const int gi = gx + g.n[0] * (gy + g.n[1] * gz);
+        const int li = lz * fpl + rr;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            Fl[c * fr + i] = f.E[c][gi];
-            Fl[(3 + c) * fr + i] = f.B[c][gi];
+            Fl[c * fr + li] = f.E[c][gi];
+            Fl[(3 + c) * fr + li] = f.B[c][gi];
         }
     }
     __syncthreads();
 
     float* const El[3] = {Fl, Fl + fr, Fl + 2 * fr};
     float* const Bl[3] = {Fl + 3 * fr, Fl + 4 * fr, Fl + 5 * fr};
-    const int fstride[3] = {1, fx, fx * fy};
-    const int jstride[3] = {1, jx, jx * jy};
+    const int fstride[3] = {1, fx, fpl};
+    const int jstride[3] = {1, jx, jpl};
     const int pb = toff[tile];
     const int n = toff[tile + 1] - pb;
     int errs = 0;
@@ -274,11 +287,11 @@ __device__ __forceinline__ void tile_body(const Geom& g, const TileGeom& t, int 
     const int lo = guard + 2;
     for (int i = threadIdx.x; i < 3 * jr; i += NT) {
         const unsigned long long v = Jl[i];
-        if (v == 0ull) continue;
+        if (v == 0ull) continue;   // (the padding of each plane stays zero)
         const int comp = i / jr;
         const int k = i - comp * jr;
-        const int lz = k / (jx * jy);
-        const int rr = k - lz * jx * jy;
+        const int lz = k / jpl;
+        const int rr = k - lz * jpl;
         const int ly = rr / jx;
         const int lx = rr - ly * jx;
         int gx = t0[0] - lo + lx, gy = t0[1] - lo + ly, gz = t0[2] - lo + lz;
@@ -384,9 +397,9 @@ __global__ void k_batch_zero_rest(const InstDesc* __restrict__ tab, int n) {
 }
 
 size_t tile_lds_bytes(const TileGeom& t, int guard) {
-    const size_t H = guard + 2;
-    const size_t fr = (t.T[0] + 2 * H) * (t.T[1] + 2 * H) * (t.T[2] + 2 * H);
-    const size_t jr = (size_t)(t.T[0] + 2 * guard + 5) * (t.T[1] + 2 * guard + 5) * (t.T[2] + 2 * guard + 5);
+    const int H = guard + 2;
+    const size_t fr = (size_t)field_plane(t.T[0] + 2 * H, t.T[1] + 2 * H) * (t.T[2] + 2 * H);
+    const size_t jr = (size_t)cur_plane(t.T[0] + 2 * guard + 5, t.T[1] + 2 * guard + 5) * (t.T[2] + 2 * guard + 5);
     return 3 * jr * 8 + 6 * fr * 4;
 }
 
