@@ -32,7 +32,9 @@ def test_window_start_and_initial_load_of_c1():
 
 def test_autotuner_space_respects_lds():
     assert autotune.feasible(autotune.DEFAULT)
-    assert autotune.lds_bytes(dict(tile=(8, 8, 8), guard=1)) == 146856
+    # fields: 14 z-planes of 14x14 words padded to 200 (8 banks per z step), 6 components x 4 B;
+    # current: 15 z-planes of 15x15 padded to 232 (8 mod 16 int64 words), 3 components x 8 B
+    assert autotune.lds_bytes(dict(tile=(8, 8, 8), guard=1)) == 14 * 200 * 24 + 15 * 232 * 24 == 150720
     assert not autotune.feasible(dict(tile=(16, 8, 8), guard=2))
     assert autotune.class_key("M", workloads.C1) == "batch|M|ppc8|pd"
 
