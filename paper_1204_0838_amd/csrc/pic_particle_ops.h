@@ -7,9 +7,10 @@
 namespace pic {
 
 __device__ __forceinline__ void decompose(const Geom& g, int cell, int c[3]) {
-    const int cz = cell / g.nxy;
+    // cell >= 0 at every call
+    const int cz = fdiv(cell, g.fd_nxy);
     const int r = cell - cz * g.nxy;
-    const int cy = r / g.n[0];
+    const int cy = fdiv(r, g.fd_nx);
     c[0] = r - cy * g.n[0];
     c[1] = cy;
     c[2] = cz;
