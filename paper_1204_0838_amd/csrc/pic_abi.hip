@@ -40,8 +40,6 @@ Tiling tiling_of(const pic_grid_desc* d) {
     }
     r.t.ntiles = r.t.nt[0] * r.t.nt[1] * r.t.nt[2];
     r.t.tcells = r.t.T[0] * r.t.T[1] * r.t.T[2];
-    for (int a = 0; a < 3; ++a) r.t.fd_T[a] = make_fastdiv(r.t.T[a]);
-    r.t.fd_tcells = make_fastdiv(r.t.tcells);
     r.guard = d->guard < 0 ? 1 : d->guard;
     r.threads = d->threads > 0 ? d->threads : 512;
     r.interleave = d->interleave > 0 ? d->interleave : 8;
@@ -894,8 +892,6 @@ pic_status pic_init_grid(pic_ctx** out, const pic_grid_desc* desc, const pic_fie
     }
     g.nxy = desc->n[0] * desc->n[1];
     g.ncell = (int)ncell;
-    g.fd_nx = make_fastdiv(g.n[0]);
-    g.fd_nxy = make_fastdiv(g.nxy);
     g.window = desc->bc_x == PIC_BC_MOVING_WINDOW;
     g.origin = 0;
     g.kill_lo = kKillMargin;

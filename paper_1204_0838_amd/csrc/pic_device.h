@@ -18,36 +18,10 @@ namespace pic {
 #define PIC_FIX_INV 0x1p-40
 
 // Kernel-side view of the grid.
-// Division by a divisor d >= 1 fixed when the grid is set up, for dividends
-// n in [0, 2^31): floor(n / d) = (n m) >> s with s = 31 + ceil(log2 d) and
-// m = ceil(2^s / d) < 2^33 (Granlund and Montgomery, "Division by invariant
-// integers using multiplication", PLDI 1994, Theorem 4.2: m d - 2^s < d <=
-// 2^(s-31)).  A 32x64-bit multiply and a shift, where a general integer
-// division takes some forty instructions.
-struct FastDiv {
-    unsigned long long m;
-    int s;
-};
-
-inline FastDiv make_fastdiv(int d) {
-    if (d < 1) return FastDiv{0ull, 0};   // (invalid sizes are rejected before any launch)
-    int l = 0;
-    while ((1ll << l) < (long long)d) ++l;
-    FastDiv f;
-    f.s = 31 + l;
-    f.m = ((1ull << f.s) + (unsigned long long)d - 1ull) / (unsigned long long)d;
-    return f;
-}
-
-__device__ __forceinline__ int fdiv(int n, const FastDiv& f) {
-    return (int)(((unsigned long long)(unsigned)n * f.m) >> f.s);
-}
-
 struct Geom {
     int n[3];
     int nxy;
     int ncell;
-    FastDiv fd_nx, fd_nxy;   // division by n[0] and by nxy
     int window;    // 1: x is a moving-window circular buffer
     int origin;    // storage x index of window cell 0
     int kill_lo;   // window mode: particles in window cells < kill_lo are removed
@@ -64,7 +38,6 @@ struct TileGeom {
     int nt[3];
     int ntiles;
     int tcells;
-    FastDiv fd_T[3], fd_tcells;   // division by T[d] and by tcells
 };
 
 // Stencil coefficients of the transverse smoothing S_d (perfect dispersion).

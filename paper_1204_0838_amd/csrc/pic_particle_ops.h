@@ -7,10 +7,9 @@
 namespace pic {
 
 __device__ __forceinline__ void decompose(const Geom& g, int cell, int c[3]) {
-    // cell >= 0 at every call
-    const int cz = fdiv(cell, g.fd_nxy);
+    const int cz = cell / g.nxy;
     const int r = cell - cz * g.nxy;
-    const int cy = fdiv(r, g.fd_nx);
+    const int cy = r / g.n[0];
     c[0] = r - cy * g.n[0];
     c[1] = cy;
     c[2] = cz;

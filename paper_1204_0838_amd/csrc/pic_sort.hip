@@ -33,7 +33,7 @@ __device__ __forceinline__ int local_key(const TileGeom& t, int lx, int ly, int 
 }
 
 __device__ __forceinline__ int tile_key(const TileGeom& t, const int c[3]) {
-    const int tx = fdiv(c[0], t.fd_T[0]), ty = fdiv(c[1], t.fd_T[1]), tz = fdiv(c[2], t.fd_T[2]);
+    const int tx = c[0] / t.T[0], ty = c[1] / t.T[1], tz = c[2] / t.T[2];
     const int lx = c[0] - tx * t.T[0], ly = c[1] - ty * t.T[1], lz = c[2] - tz * t.T[2];
     const int tile = tx + t.nt[0] * (ty + t.nt[1] * tz);
     return tile * t.tcells + local_key(t, lx, ly, lz);
@@ -183,23 +183,14 @@ __device__ __forceinline__ void scatter_one(const Geom& g, const TileGeom& t, co
     const int key = tile_key(t, c);
     int dest = off[key] + r;
     if (depth > 1) {
-        const int tile = fdiv(key, t.fd_tcells);
+        const int tile = key / t.tcells;
         const int tb = off[tile * t.tcells];
         const int blk = 64 * depth;
+        const int nfull = (off[(tile + 1) * t.tcells] - tb) / blk * blk;
         const int j = dest - tb;
-        if ((depth & (depth - 1)) == 0) {   // the usual depths: shifts
-            const int sh = __ffs(depth) - 1;
-            const int nfull = ((off[(tile + 1) * t.tcells] - tb) >> (6 + sh)) << (6 + sh);
-            if (j < nfull) {
-                const int b0 = (j >> (6 + sh)) << (6 + sh), k = j - b0;
-                dest = tb + b0 + (k & (depth - 1)) * 64 + (k >> sh);
-            }
-        } else {
-            const int nfull = (off[(tile + 1) * t.tcells] - tb) / blk * blk;
-            if (j < nfull) {
-                const int b0 = j - j % blk, k = j - b0;
-                dest = tb + b0 + (k % depth) * 64 + k / depth;
-            }
+        if (j < nfull) {
+            const int b0 = j - j % blk, k = j - b0;
+            dest = tb + b0 + (k % depth) * 64 + k / depth;
         }
     }
     dst.cell[dest] = p;   // the source index; k_sort_gather replaces it with the particle
