@@ -108,6 +108,42 @@ def test_sort_groups_particles_by_tile_and_keeps_them():
     assert np.all(np.diff(tile) >= 0)   # tiles are contiguous and in order
 
 
+def _brick_key(c, n, T):
+    """(tile, in-tile key) of cells c: 8x2x4-cell bricks, x fastest, then z,
+    then y inside a brick, bricks y-major (the order the sort stores tiles of
+    8 x 2m x 4k cells in)."""
+    x, y, z = c % n[0], (c // n[0]) % n[1], c // (n[0] * n[1])
+    nt = [(n[d] + T[d] - 1) // T[d] for d in range(3)]
+    tile = x // T[0] + nt[0] * (y // T[1] + nt[1] * (z // T[2]))
+    lx, ly, lz = x % T[0], y % T[1], z % T[2]
+    return tile, lx + 8 * (lz % 4) + 32 * (ly % 2) + 64 * (ly // 2 + (T[1] // 2) * (lz // 4))
+
+
+def test_sort_orders_tiles_in_bricks():
+    """With plain (depth-1) storage the sorted particles of 8x8x8 tiles follow
+    the brick order of their cells; the key is a bijection onto the tile's
+    512 slots, so the 64 cells of each brick are exactly an 8x2x4 block."""
+    grid = inputs.Grid(n=(16, 16, 24), d=(0.25, 0.5, 0.5), dt=0.25, solver="pd")
+    pl = inputs.uniform_random_plasma(grid, ppc=2, seed=45)
+    T = (8, 8, 8)
+    sim = pic.Simulation(grid.n, grid.d, grid.dt, solver="pd", tile=T, interleave=1, max_particles=pl.count)
+    sim.add_particles(pl)
+    sim.sort(0)
+    got = sim.particles_host(0)
+    assert np.array_equal(np.sort(got["id"]), np.sort(pl.id))
+    tile, key = _brick_key(got["cell"].astype(np.int64), grid.n, T)
+    full = tile * 512 + key
+    assert np.all(np.diff(full) >= 0)
+    cells = np.arange(16 * 16 * 24)
+    t_all, k_all = _brick_key(cells, grid.n, T)
+    assert np.array_equal(np.sort(t_all * 512 + k_all), np.arange(cells.size))
+    brick = (t_all * 512 + k_all) // 64
+    for b in np.unique(brick)[:12]:
+        c = cells[brick == b]
+        ext = [np.ptp(c % 16), np.ptp((c // 16) % 16), np.ptp(c // 256)]
+        assert ext == [7, 1, 3]
+
+
 def test_two_species_keep_their_own_tile_ranges():
     """Two species of very different sizes, sorted every third step: each
     species' fused steps between sorts must use its own tile ranges (fused ==
