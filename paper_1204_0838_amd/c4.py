@@ -27,7 +27,7 @@ no grid-scale (Nyquist) modes.
    that comparison.  Throughput: wall-clock steps per second on the same
    grid (the runs carry 16x different particle counts).
 
-    python -m paper_1204_0838_amd.c4 --out gpurun_out/c4          # full C1 grid, 1000 steps
+    python -m paper_1204_0838_amd.c4 --out c4_out                 # full C1 grid, 1000 steps
     python -m paper_1204_0838_amd.c4 --grid 128,64,64 --steps 200  # small rehearsal
 """
 from __future__ import annotations
