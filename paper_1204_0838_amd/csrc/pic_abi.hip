@@ -634,6 +634,7 @@ void fill_desc(pic_ctx* c, int32_t s, InstDesc& d) {
     d.pd = c->desc.solver == PIC_SOLVER_PD;
     d.depth = c->tl.interleave;
     d.nkeys = c->tl.t.ntiles * c->tl.t.tcells;
+    d.sdiv = make_sortdiv(c->g, c->tl.t);
     d.c = c->pd;
     d.f = fields_of(c);
     float* jt[3];

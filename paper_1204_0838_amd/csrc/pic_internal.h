@@ -20,6 +20,45 @@ struct PlasmaDev {
     int ppc[3];
 };
 
+// Division by a divisor d >= 1 fixed at set-up, for dividends n in [0, 2^31):
+// floor(n / d) = (n m) >> s with s = 31 + ceil(log2 d) and m = ceil(2^s / d)
+// < 2^33 (Granlund and Montgomery, "Division by invariant integers using
+// multiplication", PLDI 1994, Theorem 4.2: m d - 2^s < d <= 2^(s-31)).  A
+// 32x64-bit multiply and a shift, where a general integer division takes some
+// forty instructions.
+struct FastDiv {
+    unsigned long long m;
+    int s;
+};
+
+inline FastDiv make_fastdiv(int d) {
+    if (d < 1) return FastDiv{0ull, 0};   // (invalid sizes are rejected before any launch)
+    int l = 0;
+    while ((1ll << l) < (long long)d) ++l;
+    FastDiv f;
+    f.s = 31 + l;
+    f.m = ((1ull << f.s) + (unsigned long long)d - 1ull) / (unsigned long long)d;
+    return f;
+}
+
+__device__ __forceinline__ int fdiv(int n, const FastDiv& f) {
+    return (int)(((unsigned long long)(unsigned)n * f.m) >> f.s);
+}
+
+// The divisors of the sort's key computation (cell -> coordinates -> tile).
+struct SortDiv {
+    FastDiv nx, nxy, T[3], tcells;
+};
+
+inline SortDiv make_sortdiv(const Geom& g, const TileGeom& t) {
+    SortDiv d;
+    d.nx = make_fastdiv(g.n[0]);
+    d.nxy = make_fastdiv(g.nxy);
+    for (int a = 0; a < 3; ++a) d.T[a] = make_fastdiv(t.T[a]);
+    d.tcells = make_fastdiv(t.tcells);
+    return d;
+}
+
 // One member of a batch of independent simulations for one species and one
 // step, as the batched kernels see it (a device-resident table the host
 // rewrites before each step).  Geometry is the one at the start of the step.
@@ -30,6 +69,7 @@ struct InstDesc {
     int pd;                  // perfect-dispersion smoothing in the B update
     int depth;               // in-tile block transpose of the sort
     int nkeys;               // sort keys (t.ntiles * t.tcells)
+    SortDiv sdiv;            // the sort's divisors for g and t
     PDCoef c;
     FieldPtrs f;
     float* J[3];             // current read by the E update

@@ -32,19 +32,29 @@ __device__ __forceinline__ int local_key(const TileGeom& t, int lx, int ly, int 
     return lx + t.T[0] * (ly + t.T[1] * lz);
 }
 
-__device__ __forceinline__ int tile_key(const TileGeom& t, const int c[3]) {
-    const int tx = c[0] / t.T[0], ty = c[1] / t.T[1], tz = c[2] / t.T[2];
+__device__ __forceinline__ int tile_key(const TileGeom& t, const SortDiv& sd, const int c[3]) {
+    const int tx = fdiv(c[0], sd.T[0]), ty = fdiv(c[1], sd.T[1]), tz = fdiv(c[2], sd.T[2]);
     const int lx = c[0] - tx * t.T[0], ly = c[1] - ty * t.T[1], lz = c[2] - tz * t.T[2];
     const int tile = tx + t.nt[0] * (ty + t.nt[1] * tz);
     return tile * t.tcells + local_key(t, lx, ly, lz);
 }
 
-__device__ __forceinline__ int sort_key(const Geom& g, const TileGeom& t, int cl) {
+// cell -> (x, y, z) for 0 <= cl < ncell, by the precomputed divisors
+__device__ __forceinline__ void cell_coords(const Geom& g, const SortDiv& sd, int cl, int c[3]) {
+    const int cz = fdiv(cl, sd.nxy);
+    const int r = cl - cz * g.nxy;
+    const int cy = fdiv(r, sd.nx);
+    c[0] = r - cy * g.n[0];
+    c[1] = cy;
+    c[2] = cz;
+}
+
+__device__ __forceinline__ int sort_key(const Geom& g, const TileGeom& t, const SortDiv& sd, int cl) {
     if ((unsigned)cl >= (unsigned)g.ncell) return -1;
     int c[3];
-    decompose(g, cl, c);
+    cell_coords(g, sd, cl, c);
     if (window_killed(g, c[0])) return -1;
-    return tile_key(t, c);
+    return tile_key(t, sd, c);
 }
 
 // Histogram and rank of the kCountRows particles p0 + 64 r (r = 0..7): after a
@@ -55,13 +65,14 @@ __device__ __forceinline__ int sort_key(const Geom& g, const TileGeom& t, int cl
 // grouping is correct: a rank is a place among the particles of one key.
 constexpr int kCountRows = 8;
 
-__device__ __forceinline__ void count_column(const Geom& g, const TileGeom& t, const int* __restrict__ cell, int p0,
+__device__ __forceinline__ void count_column(const Geom& g, const TileGeom& t, const SortDiv& sd,
+                                             const int* __restrict__ cell, int p0,
                                              int n, int* __restrict__ hist, int* __restrict__ rank) {
     int key[kCountRows];
 #pragma unroll
     for (int r = 0; r < kCountRows; ++r) {
         const int p = p0 + 64 * r;
-        key[r] = p < n ? sort_key(g, t, cell[p]) : -2;
+        key[r] = p < n ? sort_key(g, t, sd, cell[p]) : -2;
     }
     int rk[kCountRows];
 #pragma unroll
@@ -87,13 +98,13 @@ __device__ __forceinline__ void count_column(const Geom& g, const TileGeom& t, c
 // Thread i counts the column p0 = (i / 64) * 512 + i % 64.
 __device__ __forceinline__ int column_of(int i) { return (i >> 6) * (64 * kCountRows) + (i & 63); }
 
-__global__ void __launch_bounds__(256) k_sort_count(Geom g, TileGeom t, const int* __restrict__ cell,
+__global__ void __launch_bounds__(256) k_sort_count(Geom g, TileGeom t, SortDiv sd, const int* __restrict__ cell,
                                                     const int* __restrict__ d_count, int* __restrict__ hist,
                                                     int* __restrict__ rank) {
     const int p0 = column_of(blockIdx.x * blockDim.x + threadIdx.x);
     const int n = *d_count;
     if (p0 >= n) return;
-    count_column(g, t, cell, p0, n, hist, rank);
+    count_column(g, t, sd, cell, p0, n, hist, rank);
 }
 
 // Exclusive scan, phase 1: per-block totals of 1024-element blocks.
@@ -172,25 +183,34 @@ __global__ void __launch_bounds__(1024) k_scan_apply(const int* in, int n, const
     scan_apply_block(in, n, sums, out, blockIdx.x);
 }
 
-__device__ __forceinline__ void scatter_one(const Geom& g, const TileGeom& t, const SpeciesDev& src,
-                                            const SpeciesDev& dst, int p, const int* __restrict__ rank,
-                                            const int* __restrict__ off, int depth) {
+__device__ __forceinline__ void scatter_one(const Geom& g, const TileGeom& t, const SortDiv& sd,
+                                            const SpeciesDev& src, const SpeciesDev& dst, int p,
+                                            const int* __restrict__ rank, const int* __restrict__ off, int depth) {
     const int r = rank[p];
     if (r < 0) return;
-    const int cl = src.cell[p];
+    const int cl = src.cell[p];   // a ranked particle has a live cell
     int c[3];
-    decompose(g, cl, c);
-    const int key = tile_key(t, c);
+    cell_coords(g, sd, cl, c);
+    const int key = tile_key(t, sd, c);
     int dest = off[key] + r;
     if (depth > 1) {
-        const int tile = key / t.tcells;
+        const int tile = fdiv(key, sd.tcells);
         const int tb = off[tile * t.tcells];
-        const int blk = 64 * depth;
-        const int nfull = (off[(tile + 1) * t.tcells] - tb) / blk * blk;
         const int j = dest - tb;
-        if (j < nfull) {
-            const int b0 = j - j % blk, k = j - b0;
-            dest = tb + b0 + (k % depth) * 64 + k / depth;
+        if ((depth & (depth - 1)) == 0) {   // the usual depths: shifts
+            const int sh = 6 + __ffs(depth) - 1;   // log2 of the block of 64 depth particles
+            const int nfull = ((off[(tile + 1) * t.tcells] - tb) >> sh) << sh;
+            if (j < nfull) {
+                const int b0 = (j >> sh) << sh, k = j - b0;
+                dest = tb + b0 + (k & (depth - 1)) * 64 + (k >> (sh - 6));
+            }
+        } else {
+            const int blk = 64 * depth;
+            const int nfull = (off[(tile + 1) * t.tcells] - tb) / blk * blk;
+            if (j < nfull) {
+                const int b0 = j - j % blk, k = j - b0;
+                dest = tb + b0 + (k % depth) * 64 + k / depth;
+            }
         }
     }
     dst.cell[dest] = p;   // the source index; k_sort_gather replaces it with the particle
@@ -213,12 +233,13 @@ __device__ __forceinline__ void gather_one(const SpeciesDev& src, const SpeciesD
     dst.id[i] = src.id[p];
 }
 
-__global__ void __launch_bounds__(256) k_sort_scatter(Geom g, TileGeom t, SpeciesDev src, SpeciesDev dst,
-                                                      const int* __restrict__ d_count, const int* __restrict__ rank,
-                                                      const int* __restrict__ off, int depth) {
+__global__ void __launch_bounds__(256) k_sort_scatter(Geom g, TileGeom t, SortDiv sd, SpeciesDev src,
+                                                      SpeciesDev dst, const int* __restrict__ d_count,
+                                                      const int* __restrict__ rank, const int* __restrict__ off,
+                                                      int depth) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= *d_count) return;
-    scatter_one(g, t, src, dst, p, rank, off, depth);
+    scatter_one(g, t, sd, src, dst, p, rank, off, depth);
 }
 
 __global__ void __launch_bounds__(256) k_sort_gather(SpeciesDev src, SpeciesDev dst, const int* __restrict__ off,
@@ -258,7 +279,7 @@ __global__ void __launch_bounds__(256) k_batch_sort_count(const InstDesc* __rest
     if (p0 >= n) return;
     const Geom g = d.g;
     const TileGeom t = d.t;
-    count_column(g, t, d.s.cell, p0, n, d.hist, d.rank);
+    count_column(g, t, d.sdiv, d.s.cell, p0, n, d.hist, d.rank);
 }
 
 __global__ void __launch_bounds__(1024) k_batch_scan_reduce(const InstDesc* __restrict__ tab) {
@@ -288,7 +309,7 @@ __global__ void __launch_bounds__(256) k_batch_sort_scatter(const InstDesc* __re
     const Geom g = d.g;
     const TileGeom t = d.t;
     const SpeciesDev src = d.s, dst = d.alt;
-    scatter_one(g, t, src, dst, p, d.rank, d.hist, d.depth);
+    scatter_one(g, t, d.sdiv, src, dst, p, d.rank, d.hist, d.depth);
 }
 
 __global__ void __launch_bounds__(256) k_batch_sort_gather(const InstDesc* __restrict__ tab) {
@@ -335,14 +356,16 @@ hipError_t launch_sort(const Geom& g, const TileGeom& t, const SpeciesDev& src, 
     if (e != hipSuccess) return e;
     const int np = max_count > 0 ? max_count : 1;
     const int ncol = (np + kCountRows - 1) / kCountRows + 64;   // whole 512-particle blocks of columns
-    hipLaunchKernelGGL(k_sort_count, dim3((ncol + 255) / 256), dim3(256), 0, st, g, t, src.cell, d_count, hist, rank);
+    const SortDiv sd = make_sortdiv(g, t);
+    hipLaunchKernelGGL(k_sort_count, dim3((ncol + 255) / 256), dim3(256), 0, st, g, t, sd, src.cell, d_count, hist,
+                       rank);
     const int n = nkeys + 1;
     const int nb = (n + 1023) / 1024;
     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(1024), 0, st, hist, n, sums);
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, sums, nb);
     hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(1024), 0, st, hist, n, sums, hist);
-    hipLaunchKernelGGL(k_sort_scatter, dim3((np + 255) / 256), dim3(256), 0, st, g, t, src, dst, d_count, rank, hist,
-                       depth);
+    hipLaunchKernelGGL(k_sort_scatter, dim3((np + 255) / 256), dim3(256), 0, st, g, t, sd, src, dst, d_count, rank,
+                       hist, depth);
     hipLaunchKernelGGL(k_sort_gather, dim3((np + 255) / 256), dim3(256), 0, st, src, dst, hist, nkeys);
     hipLaunchKernelGGL(k_sort_finish, dim3(1), dim3(1), 0, st, hist, nkeys, d_count, d_sorted);
     hipLaunchKernelGGL(k_tile_offsets, dim3((t.ntiles + 1 + 255) / 256), dim3(256), 0, st, hist, t.tcells, t.ntiles,
