@@ -208,6 +208,45 @@ def test_empty_species_is_vacuum_evolution():
     assert sim.reduce()["n_particles"] == 0
 
 
+def test_light_speed_step_at_the_courant_limit_is_reported():
+    """Perfect dispersion at c dt = dx: a particle with u_x = 1e8 has v_x = 1
+    in FP32 (sqrt(1 + u^2) rounds to u), a move of exactly one cell, which the
+    deposit's support does not cover: PIC_ECFL at the next sync."""
+    pic = _pic()
+    grid = inputs.Grid(n=(16, 8, 8), d=(0.25, 0.5, 0.5), dt=0.25, solver="pd")
+    pl = inputs.uniform_random_plasma(grid, ppc=1, seed=4)
+    pl.u[:] = 0.0
+    pl.u[0, 3] = 1e8
+    sim = _sim(grid, pl.count)
+    sim.add_particles(pl)
+    sim.gather_push(0)
+    with pytest.raises(pic.PicError) as e:
+        sim.sync()
+    assert e.value.status == pic.PIC_ECFL
+
+
+def test_injection_beyond_capacity_is_refused():
+    """Plasma injection that could exceed the species' capacity is refused on
+    the host before any launch (the host keeps an upper bound of the live
+    count, re-read from the device when it gets close): PIC_ENOMEM, and a
+    slab that fits is then injected in full."""
+    pic = _pic()
+    grid = inputs.Grid(n=(16, 8, 8), d=(0.25, 0.5, 0.5), dt=0.25, solver="pd")
+    sim = pic.Simulation(grid.n, grid.d, grid.dt, solver="pd", bc_x=1, max_particles=1024)
+    sim.add_empty_species(1024)
+    sim.set_plasma(0, x_start=0.0, ramp=0.0, n_plateau=1.0, ppc=(2, 2, 2))
+    with pytest.raises(pic.PicError) as e:
+        sim.inject_plasma(0, 4, 7)   # up to 3 x 8 x 8 cells at 8 per cell = 1536 > 1024
+    assert e.value.status == pic.PIC_ENOMEM
+    sim2 = pic.Simulation(grid.n, grid.d, grid.dt, solver="pd", bc_x=1, max_particles=1024)
+    sim2.add_empty_species(1024)
+    sim2.set_plasma(0, x_start=0.0, ramp=0.0, n_plateau=1.0, ppc=(2, 2, 2))
+    sim2.inject_plasma(0, 4, 6)      # 2 x 8 x 8 cells at 8 per cell = 1024: exactly the capacity
+    # (window cells 4 and 5: the first three are the window's removal margin)
+    sim2.sync()
+    assert sim2.reduce()["n_particles"] == 1024
+
+
 def test_non_finite_momentum_is_reported():
     pic = _pic()
     grid = RAGGED
