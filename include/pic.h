@@ -93,8 +93,11 @@ enum { PIC_JPOST_NONE = 0, PIC_JPOST_BINOMIAL = 1, PIC_JPOST_DENOISER = 2 };
  *                handled in LDS (0..3; a negative value selects the
  *                default 1); beyond it the fused step uses global memory
  *                for that particle.  The tile's LDS footprint
- *                24 B x prod(T + 2 guard + 5) + 24 B x prod(T + 2 guard + 4)
- *                must fit in 160 KiB.
+ *                24 B x PJ x (Tz + 2 guard + 5) + 24 B x PF x (Tz + 2 guard + 4)
+ *                must fit in 160 KiB, where the z-plane sizes
+ *                PJ = (Tx + 2 guard + 5)(Ty + 2 guard + 5) and
+ *                PF = (Tx + 2 guard + 4)(Ty + 2 guard + 4) are padded up to
+ *                8 mod 16 and 8 mod 32 words (150,720 B for 8x8x8, guard 1).
  *   threads      threads per tile workgroup (256, 512 or 1024; 0 = 512).
  *   interleave   depth D of the sort's in-tile block transpose: each full
  *                block of 64 D cell-sorted particles is stored D x 64
@@ -236,7 +239,10 @@ pic_status pic_field_step(pic_ctx *ctx);
 pic_status pic_step(pic_ctx *ctx, int32_t nsteps);
 
 /* Counting sort of one species by tile and cell; drops removed particles.
- * The species' data may move to the workspace copy (see pic_species_view).
+ * Tiles of 8 x 2m x 4k cells are stored in 8x2x4-cell bricks (x fastest,
+ * then z, then y inside a brick), other tiles in x-fastest cell order; then
+ * the in-tile block transpose of the tiling's interleave depth.  The
+ * species' data may move to the workspace copy (see pic_species_view).
  * Asynchronous. */
 pic_status pic_sort(pic_ctx *ctx, int32_t species);
 
