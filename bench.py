@@ -64,6 +64,16 @@ KERNEL_SOURCES = ("paper_1204_0838_amd/csrc/pic_tile.hip", "paper_1204_0838_amd/
                   "paper_1204_0838_amd/csrc/pic_device.h")
 
 
+def tile_alg_bytes(npart, ncell, prof):
+    """Algorithmic HBM bytes of one tile launch, averaged over the timed
+    launches: 60 B per particle (cell, off, u, w read; cell, off, u written)
+    and 48 B per cell (E, B staged once; the int64 current added once), plus
+    16 B per particle on the launches right after a sort, which do the sort's
+    gather (the source index and id read, w and id written)."""
+    gather_share = prof["sorts"] / max(1, prof["tile_launches"])
+    return (60.0 + 16.0 * gather_share) * npart + 48.0 * ncell
+
+
 def measured_traffic(path, cfg):
     """HBM bytes per k_pic_tile launch from the committed rocprofv3 counter
     summary, or None when it is missing, for another grid, or the kernel
@@ -124,7 +134,7 @@ def bench_c3(args):
     K = args.steps
     ncell = sum(c["n"][0] * c["n"][1] * c["n"][2] for c in cfgs)
     tile_ms = prof["tile_ms"] / max(1, prof["tile_launches"])
-    alg_bytes = 60.0 * npart + 48.0 * ncell
+    alg_bytes = tile_alg_bytes(npart, ncell, prof)
     achieved = alg_bytes / (tile_ms * 1e-3) / 1e9
     # the same members one after another (per-member launches), a few steps
     seq_steps = 10
@@ -323,7 +333,7 @@ def main():
     ncell = cfg["n"][0] * cfg["n"][1] * cfg["n"][2]
     launches = max(1, prof["tile_launches"])
     tile_ms = prof["tile_ms"] / launches
-    alg_bytes = 60.0 * npart + 48.0 * ncell
+    alg_bytes = tile_alg_bytes(npart, ncell, prof)
     achieved = alg_bytes / (tile_ms * 1e-3) / 1e9
     traffic = measured_traffic(args.traffic_json or os.path.join(ROOT, "profiles", "k_pic_tile_C1_traffic.json"),
                                cfg)

@@ -500,13 +500,15 @@ pic_status end_step(pic_ctx* c) {
     return prof_end(c, PH_WINDOW, t0);
 }
 
-pic_status sort_species(pic_ctx* c, int32_t s) {
+// copy = false: the particle data stay in the pre-sort set (now sp.alt) and
+// the tile step that must follow gathers them (launch_pic_tile with src).
+pic_status sort_species(pic_ctx* c, int32_t s, bool copy) {
     Species& sp = c->sp[s];
     Small* sm = small_of(c);
     int* rank = reinterpret_cast<int*>(c->ws + c->L.sort_rank) + sp.base;
     HIPCHK(c, launch_sort(c->g, c->tl.t, dev_from(c, sp, sp.cur), dev_from(c, sp, sp.alt), &sm->count[s],
                           &sm->sorted[s], (int)sp.bound, hist_of(c), rank, reinterpret_cast<int*>(c->ws + c->L.sums),
-                          c->tl.interleave, toff_of(c, s), c->stream));
+                          c->tl.interleave, toff_of(c, s), copy, c->stream));
     std::swap(sp.cur, sp.alt);
     sp.sorted = true;
     sp.sort_step = c->step;
@@ -985,17 +987,21 @@ pic_status pic_step(pic_ctx* c, int32_t nsteps) {
         for (int32_t s = 0; s < (int32_t)c->sp.size(); ++s) {
             Species& sp = c->sp[s];
             hipEvent_t t0, t1, t2;
+            bool gather = false;
             if (!sp.sorted || c->step - sp.sort_step >= c->tl.sort_interval) {
                 PICCHK(prof_mark(c, &t0));
-                PICCHK(sort_species(c, s));
+                PICCHK(sort_species(c, s, false));
                 PICCHK(prof_end(c, PH_SORT, t0));
                 if (c->prof.on) c->prof.sorts += 1;
+                gather = true;
             }
             Small* sm = small_of(c);
             PICCHK(prof_mark(c, &t1));
             int* rest_idx = reinterpret_cast<int*>(c->ws + c->L.sort_rank) + sp.base;
+            const SpeciesDev pre = dev_from(c, sp, sp.alt);   // the pre-sort set after a sort
             HIPCHK(c, launch_pic_tile(c->g, c->tl.t, c->tl.guard, c->tl.threads, fields_of(c), dev_of(c, sp),
-                                      toff_of(c, s), acc_of(c), &sm->err, &sm->rest_n[s], rest_idx, c->stream));
+                                      gather ? &pre : nullptr, toff_of(c, s), acc_of(c), &sm->err, &sm->rest_n[s],
+                                      rest_idx, c->stream));
             PICCHK(prof_end(c, PH_TILE, t1));
             if (c->prof.on) c->prof.tiles += 1;
             PICCHK(prof_mark(c, &t2));
@@ -1011,7 +1017,7 @@ pic_status pic_step(pic_ctx* c, int32_t nsteps) {
 
 pic_status pic_sort(pic_ctx* c, int32_t s) {
     PICCHK(check_species(c, s));
-    return sort_species(c, s);
+    return sort_species(c, s, true);
 }
 
 pic_status pic_species_view(pic_ctx* c, int32_t s, pic_species_bufs* out, int64_t* n_live) {

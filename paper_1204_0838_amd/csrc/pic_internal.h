@@ -75,7 +75,7 @@ struct InstDesc {
     float* J[3];             // current read by the E update
     float* Jt[3];            // workspace current (binomial filter source)
     int jpost;               // 0: none, 1: binomial filter
-    int sorting;             // 1: sort s -> alt first; the step then runs on alt
+    int sorting;             // 1: sort s -> alt first (no copy pass: the tile step gathers from s); the step runs on alt
     SpeciesDev s;            // particle arrays at the start of the step
     SpeciesDev alt;          // the other array set
     int* hist;               // sort histogram, then its exclusive scan (member scratch)
@@ -166,18 +166,22 @@ hipError_t launch_jfinal(const Geom& g, unsigned long long* acc, float* const J[
 
 // sort (pic_sort.hip): src -> dst, new count into d_count and d_sorted, tile
 // ranges into toff (t.ntiles + 1 entries); hist, rank, sums are scratch.
-// depth: in-tile block-transpose depth (1 = plain cell order)
+// depth: in-tile block-transpose depth (1 = plain cell order).  copy = false
+// leaves only each destination's source index in dst.cell: the next tile
+// step (launch_pic_tile with src) then gathers the particles itself.
 hipError_t launch_sort(const Geom& g, const TileGeom& t, const SpeciesDev& src, const SpeciesDev& dst,
                        int* d_count, int* d_sorted, int max_count, int* hist, int* rank, int* sums, int depth,
-                       int* toff, hipStream_t st);
+                       int* toff, bool copy, hipStream_t st);
 
 // fused tile kernel (pic_tile.hip)
 size_t tile_lds_bytes(const TileGeom& t, int guard);
 // toff: tile ranges of the species' last sort
 // rest_n / rest_idx: the species' rest list (counter zeroed here, indices appended by the kernel)
+// src: null, or the pre-sort arrays when the sort ran without its copy pass
+// (s.cell then holds source indices; the step writes every array of s)
 hipError_t launch_pic_tile(const Geom& g, const TileGeom& t, int guard, int threads, const FieldPtrs& f,
-                           const SpeciesDev& s, const int* toff, unsigned long long* acc, int* d_err, int* rest_n,
-                           int* rest_idx, hipStream_t st);
+                           const SpeciesDev& s, const SpeciesDev* src, const int* toff, unsigned long long* acc,
+                           int* d_err, int* rest_n, int* rest_idx, hipStream_t st);
 // rest pass after the tile kernel: the particles on its rest list (beyond
 // their tile's guard, marked cell -2 - c) and those appended after the last
 // sort (index >= sorted)

@@ -6,7 +6,10 @@
 // within its cell), an exclusive scan of the histogram, a scatter of each
 // particle's index to its destination and a gather of the particle data by
 // destination place every tile's particles contiguously.  Removed particles
-// (cell < 0, or outside a moving window) are dropped.
+// (cell < 0, or outside a moving window) are dropped.  Inside the production
+// step the gather is left to the tile kernel that runs next (it reads each
+// particle through the source index and writes all its arrays), which saves
+// the copy pass's read and write of every particle.
 //
 // Inside a tile the cell-sorted sequence is stored block-transposed: each full
 // block of 64*D particles (D = the interleave depth) is written as a D x 64
@@ -213,7 +216,7 @@ __device__ __forceinline__ void scatter_one(const Geom& g, const TileGeom& t, co
             }
         }
     }
-    dst.cell[dest] = p;   // the source index; k_sort_gather replaces it with the particle
+    dst.cell[dest] = p;   // the source index; the gather replaces it with the particle
 }
 
 // Second pass of the permutation, over destinations: dst.cell[i] holds the
@@ -312,14 +315,6 @@ __global__ void __launch_bounds__(256) k_batch_sort_scatter(const InstDesc* __re
     scatter_one(g, t, d.sdiv, src, dst, p, d.rank, d.hist, d.depth);
 }
 
-__global__ void __launch_bounds__(256) k_batch_sort_gather(const InstDesc* __restrict__ tab) {
-    const InstDesc& d = tab[blockIdx.y];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (!d.sorting || i >= d.hist[d.nkeys]) return;
-    const SpeciesDev src = d.s, dst = d.alt;
-    gather_one(src, dst, i);
-}
-
 __global__ void __launch_bounds__(256) k_batch_sort_finish(const InstDesc* __restrict__ tab) {
     const InstDesc& d = tab[blockIdx.y];
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -343,14 +338,14 @@ hipError_t launch_batch_sort(const InstDesc* d, int n, int max_particles, int ma
     hipLaunchKernelGGL(k_batch_scan_sums, dim3(1, n), dim3(1024), 0, st, d);
     hipLaunchKernelGGL(k_batch_scan_apply, dim3(nb, n), dim3(1024), 0, st, d);
     hipLaunchKernelGGL(k_batch_sort_scatter, dim3((np + 255) / 256, n), dim3(256), 0, st, d);
-    hipLaunchKernelGGL(k_batch_sort_gather, dim3((np + 255) / 256, n), dim3(256), 0, st, d);
+    // (no copy pass: each sorting member's tile step gathers its particles)
     hipLaunchKernelGGL(k_batch_sort_finish, dim3((max_tiles1 + 255) / 256, n), dim3(256), 0, st, d);
     return hipGetLastError();
 }
 
 hipError_t launch_sort(const Geom& g, const TileGeom& t, const SpeciesDev& src, const SpeciesDev& dst,
                        int* d_count, int* d_sorted, int max_count, int* hist, int* rank, int* sums, int depth,
-                       int* toff, hipStream_t st) {
+                       int* toff, bool copy, hipStream_t st) {
     const int nkeys = t.ntiles * t.tcells;
     hipError_t e = hipMemsetAsync(hist, 0, ((size_t)nkeys + 1) * sizeof(int), st);
     if (e != hipSuccess) return e;
@@ -366,7 +361,7 @@ hipError_t launch_sort(const Geom& g, const TileGeom& t, const SpeciesDev& src, 
     hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(1024), 0, st, hist, n, sums, hist);
     hipLaunchKernelGGL(k_sort_scatter, dim3((np + 255) / 256), dim3(256), 0, st, g, t, sd, src, dst, d_count, rank,
                        hist, depth);
-    hipLaunchKernelGGL(k_sort_gather, dim3((np + 255) / 256), dim3(256), 0, st, src, dst, hist, nkeys);
+    if (copy) hipLaunchKernelGGL(k_sort_gather, dim3((np + 255) / 256), dim3(256), 0, st, src, dst, hist, nkeys);
     hipLaunchKernelGGL(k_sort_finish, dim3(1), dim3(1), 0, st, hist, nkeys, d_count, d_sorted);
     hipLaunchKernelGGL(k_tile_offsets, dim3((t.ntiles + 1 + 255) / 256), dim3(256), 0, st, hist, t.tcells, t.ntiles,
                        toff);

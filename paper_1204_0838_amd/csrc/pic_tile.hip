@@ -13,7 +13,10 @@
 //     arithmetic).  Keeping that path out of the tile kernel keeps its loop
 //     free of calls, so the kernel arguments stay in scalar registers.
 // Finally the non-zero LDS current is added to the global fixed-point
-// accumulator in one atomic pass.  Every value goes through the same device
+// accumulator in one atomic pass.  The step right after a sort also does the
+// sort's gather: the sort leaves each destination's source index in the
+// cell array, and this kernel reads every particle through it from the
+// pre-sort arrays and writes all of its arrays at the destination.  Every value goes through the same device
 // functions as the split kernels, so the fused and split paths agree bit for
 // bit (integer sums are order-independent).
 //
@@ -124,14 +127,57 @@ __host__ __device__ constexpr int pad_plane(int p, int m) { return p + ((8 - p %
 __host__ __device__ constexpr int field_plane(int fx, int fy) { return pad_plane(fx * fy, 32); }
 __host__ __device__ constexpr int cur_plane(int jx, int jy) { return pad_plane(jx * jy, 16); }
 
+// Load particle pn of the tile's range.  With GATHER the step runs right
+// after a sort that left only each destination's source index in s.cell:
+// the particle is read from src at that index, and w and id, which the step
+// does not change, are written to the destination at once (the step writes
+// the other arrays), so the sort needs no copy pass of its own.
+template <bool GATHER>
+__device__ __forceinline__ void load_particle(const SpeciesDev& s, const SpeciesDev& src, int pn, int& cell,
+                                              float o[3], float u[3], float& w) {
+    if (GATHER) {
+        const int ps = s.cell[pn];
+        cell = src.cell[ps];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            o[d] = src.off[d][ps];
+            u[d] = src.u[d][ps];
+        }
+        w = src.w[ps];
+        s.w[pn] = w;
+        s.id[pn] = src.id[ps];
+    } else {
+        cell = s.cell[pn];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            o[d] = s.off[d][pn];
+            u[d] = s.u[d][pn];
+        }
+        w = s.w[pn];
+    }
+}
+
+// Offsets and momenta of particle p written unchanged (a gathering step's
+// particles that it does not push here still need them at their new place).
+template <bool GATHER>
+__device__ __forceinline__ void keep_particle(const SpeciesDev& s, int p, const float o[3], const float u[3]) {
+    if (GATHER) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            s.off[d][p] = o[d];
+            s.u[d][p] = u[d];
+        }
+    }
+}
+
 // Body of the fused step for one tile (the whole workgroup cooperates).
 // TX, TY, TZ > 0 and GD >= 0 fix the tile shape and guard at compile time:
 // every LDS stride is then a constant and each particle's current atomics
 // and field reads address LDS as one base register plus immediate offsets.
 // 0 (-1 for GD) takes them from t and guard_rt.
-template <int NT, int TX = 0, int TY = 0, int TZ = 0, int GD = -1>
+template <int NT, int TX = 0, int TY = 0, int TZ = 0, int GD = -1, bool GATHER = false>
 __device__ __forceinline__ void tile_body(const Geom& g, const TileGeom& t, int guard_rt, const FieldPtrs& f,
-                                          const SpeciesDev& s, const int* __restrict__ toff,
+                                          const SpeciesDev& s, const SpeciesDev& src, const int* __restrict__ toff,
                                           unsigned long long* __restrict__ acc, int* __restrict__ d_err,
                                           int* __restrict__ rest_n, int* __restrict__ rest_idx,
                                           unsigned long long* lds_u64, int tile) {
@@ -187,40 +233,34 @@ __device__ __forceinline__ void tile_body(const Geom& g, const TileGeom& t, int 
     // software pipeline: the next particle's SoA loads are issued before the
     // current particle is processed
     int pn = pb + (int)threadIdx.x, celln = -1;
-    float oxn = 0.f, oyn = 0.f, ozn = 0.f, uxn = 0.f, uyn = 0.f, uzn = 0.f, wn = 0.f;
-    if (NT < 1024 && (int)threadIdx.x < n) {
-        celln = s.cell[pn];
-        oxn = s.off[0][pn], oyn = s.off[1][pn], ozn = s.off[2][pn];
-        uxn = s.u[0][pn], uyn = s.u[1][pn], uzn = s.u[2][pn];
-        wn = s.w[pn];
-    }
+    float on[3] = {0.f, 0.f, 0.f}, un[3] = {0.f, 0.f, 0.f}, wn = 0.f;
+    if (NT < 1024 && (int)threadIdx.x < n) load_particle<GATHER>(s, src, pn, celln, on, un, wn);
     for (int q = threadIdx.x; q < n; q += NT) {
         if (NT >= 1024) {
             pn = pb + q;
-            celln = s.cell[pn];
-            oxn = s.off[0][pn], oyn = s.off[1][pn], ozn = s.off[2][pn];
-            uxn = s.u[0][pn], uyn = s.u[1][pn], uzn = s.u[2][pn];
-            wn = s.w[pn];
+            load_particle<GATHER>(s, src, pn, celln, on, un, wn);
         }
         const int p = pn;
         const int cell = celln;
-        float o[3] = {oxn, oyn, ozn};
-        float u[3] = {uxn, uyn, uzn};
+        float o[3] = {on[0], on[1], on[2]};
+        float u[3] = {un[0], un[1], un[2]};
         const float wq = s.mq * wn;
         // (1024-thread workgroups keep four waves per SIMD; there the hardware
         // hides the load latency and the prefetch registers would spill)
         if (NT < 1024 && q + NT < n) {
             pn = p + NT;
-            celln = s.cell[pn];
-            oxn = s.off[0][pn], oyn = s.off[1][pn], ozn = s.off[2][pn];
-            uxn = s.u[0][pn], uyn = s.u[1][pn], uzn = s.u[2][pn];
-            wn = s.w[pn];
+            load_particle<GATHER>(s, src, pn, celln, on, un, wn);
         }
-        if ((unsigned)cell >= (unsigned)g.ncell) continue;
+        if ((unsigned)cell >= (unsigned)g.ncell) {   // (a sort drops these)
+            if (GATHER) s.cell[p] = cell;
+            keep_particle<GATHER>(s, p, o, u);
+            continue;
+        }
         int c[3];
         decompose(g, cell, c);
         if (window_killed(g, c[0])) {
             s.cell[p] = -1;
+            keep_particle<GATHER>(s, p, o, u);
             continue;
         }
         int lc[3];
@@ -235,6 +275,7 @@ __device__ __forceinline__ void tile_body(const Geom& g, const TileGeom& t, int 
         }
         if (!inside) {   // beyond the guard: the rest pass takes it
             s.cell[p] = -2 - cell;
+            keep_particle<GATHER>(s, p, o, u);
             const unsigned long long m = __ballot(1);   // the lanes in this branch
             const int lane = __lane_id(), leader = __ffsll((long long)m) - 1;
             int base = 0;
@@ -302,15 +343,16 @@ __device__ __forceinline__ void tile_body(const Geom& g, const TileGeom& t, int 
     }
 }
 
-template <int NT, int TX = 0, int TY = 0, int TZ = 0, int GD = -1>
+template <int NT, int TX = 0, int TY = 0, int TZ = 0, int GD = -1, bool GATHER = false>
 __global__ void __launch_bounds__(NT) k_pic_tile(Geom g, TileGeom t, int guard, FieldPtrs f, SpeciesDev s,
-                                                 const int* __restrict__ toff, unsigned long long* __restrict__ acc,
-                                                 int* __restrict__ d_err, int* __restrict__ rest_n,
-                                                 int* __restrict__ rest_idx) {
+                                                 SpeciesDev src, const int* __restrict__ toff,
+                                                 unsigned long long* __restrict__ acc, int* __restrict__ d_err,
+                                                 int* __restrict__ rest_n, int* __restrict__ rest_idx) {
     extern __shared__ unsigned long long lds_u64[];
     const int tile = xcd_tile(blockIdx.x, t.ntiles, t.nt[0]);
     if (tile >= t.ntiles) return;
-    tile_body<NT, TX, TY, TZ, GD>(g, t, guard, f, s, toff, acc, d_err, rest_n, rest_idx, lds_u64, tile);
+    tile_body<NT, TX, TY, TZ, GD, GATHER>(g, t, guard, f, s, src, toff, acc, d_err, rest_n, rest_idx, lds_u64,
+                                          tile);
 }
 
 // Batched form: the work list is the concatenation of every member's tiles
@@ -332,7 +374,12 @@ __global__ void __launch_bounds__(NT) k_batch_tile(const InstDesc* __restrict__ 
     const TileGeom t = d.t;
     const FieldPtrs f = d.f;
     const SpeciesDev s = step_arrays(d);
-    tile_body<NT>(g, t, d.guard, f, s, d.toff, d.acc, d.err, d.rest_n, d.rank, lds_u64, ft - tile_begin[lo]);
+    // a member that sorted this step gathers its particles from the pre-sort set
+    if (d.sorting)
+        tile_body<NT, 0, 0, 0, -1, true>(g, t, d.guard, f, s, d.s, d.toff, d.acc, d.err, d.rest_n, d.rank, lds_u64,
+                                         ft - tile_begin[lo]);
+    else
+        tile_body<NT>(g, t, d.guard, f, s, s, d.toff, d.acc, d.err, d.rest_n, d.rank, lds_u64, ft - tile_begin[lo]);
 }
 
 // The rest pass, after the tile kernel: the particles on the species' rest
@@ -403,43 +450,54 @@ size_t tile_lds_bytes(const TileGeom& t, int guard) {
     return 3 * jr * 8 + 6 * fr * 4;
 }
 
-template <int NT, int TX = 0, int TY = 0, int TZ = 0, int GD = -1>
-static hipError_t launch_tile_nt(const Geom& g, const TileGeom& t, int guard, const FieldPtrs& f,
-                                 const SpeciesDev& s, const int* toff, unsigned long long* acc,
-                                 int* d_err, int* rest_n, int* rest_idx, hipStream_t st) {
+template <int NT, int TX, int TY, int TZ, int GD, bool GATHER>
+static hipError_t launch_tile_k(const Geom& g, const TileGeom& t, int guard, const FieldPtrs& f,
+                                const SpeciesDev& s, const SpeciesDev& src, const int* toff, unsigned long long* acc,
+                                int* d_err, int* rest_n, int* rest_idx, hipStream_t st) {
     const size_t lds = tile_lds_bytes(t, guard);
     const int nb = xcd_blocks(t.ntiles, t.nt[0]);
-    hipError_t e = hipFuncSetAttribute((const void*)k_pic_tile<NT, TX, TY, TZ, GD>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_pic_tile<NT, TX, TY, TZ, GD, GATHER>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_zero_rest, dim3(1), dim3(1), 0, st, rest_n);
-    hipLaunchKernelGGL((k_pic_tile<NT, TX, TY, TZ, GD>), dim3(nb), dim3(NT), lds, st, g, t, guard, f, s, toff, acc,
-                       d_err, rest_n, rest_idx);
+    hipLaunchKernelGGL((k_pic_tile<NT, TX, TY, TZ, GD, GATHER>), dim3(nb), dim3(NT), lds, st, g, t, guard, f, s, src,
+                       toff, acc, d_err, rest_n, rest_idx);
     return hipGetLastError();
+}
+
+template <int NT, int TX = 0, int TY = 0, int TZ = 0, int GD = -1>
+static hipError_t launch_tile_nt(const Geom& g, const TileGeom& t, int guard, const FieldPtrs& f,
+                                 const SpeciesDev& s, const SpeciesDev* src, const int* toff, unsigned long long* acc,
+                                 int* d_err, int* rest_n, int* rest_idx, hipStream_t st) {
+    if (src)
+        return launch_tile_k<NT, TX, TY, TZ, GD, true>(g, t, guard, f, s, *src, toff, acc, d_err, rest_n, rest_idx, st);
+    return launch_tile_k<NT, TX, TY, TZ, GD, false>(g, t, guard, f, s, s, toff, acc, d_err, rest_n, rest_idx, st);
 }
 
 // Tile shapes with a compile-time specialisation (the library default and
 // the autotuner's usual picks); every other shape runs the general body.
 template <int NT>
 static hipError_t launch_tile_shape(const Geom& g, const TileGeom& t, int guard, const FieldPtrs& f,
-                                    const SpeciesDev& s, const int* toff, unsigned long long* acc, int* d_err,
-                                    int* rest_n, int* rest_idx, hipStream_t st) {
+                                    const SpeciesDev& s, const SpeciesDev* src, const int* toff,
+                                    unsigned long long* acc, int* d_err, int* rest_n, int* rest_idx, hipStream_t st) {
     if (t.T[0] == 8 && t.T[1] == 8 && t.T[2] == 8) {
-        if (guard == 1) return launch_tile_nt<NT, 8, 8, 8, 1>(g, t, guard, f, s, toff, acc, d_err, rest_n, rest_idx, st);
-        if (guard == 0) return launch_tile_nt<NT, 8, 8, 8, 0>(g, t, guard, f, s, toff, acc, d_err, rest_n, rest_idx, st);
+        if (guard == 1)
+            return launch_tile_nt<NT, 8, 8, 8, 1>(g, t, guard, f, s, src, toff, acc, d_err, rest_n, rest_idx, st);
+        if (guard == 0)
+            return launch_tile_nt<NT, 8, 8, 8, 0>(g, t, guard, f, s, src, toff, acc, d_err, rest_n, rest_idx, st);
     }
     if (t.T[0] == 8 && t.T[1] == 8 && t.T[2] == 4 && guard == 1)
-        return launch_tile_nt<NT, 8, 8, 4, 1>(g, t, guard, f, s, toff, acc, d_err, rest_n, rest_idx, st);
-    return launch_tile_nt<NT>(g, t, guard, f, s, toff, acc, d_err, rest_n, rest_idx, st);
+        return launch_tile_nt<NT, 8, 8, 4, 1>(g, t, guard, f, s, src, toff, acc, d_err, rest_n, rest_idx, st);
+    return launch_tile_nt<NT>(g, t, guard, f, s, src, toff, acc, d_err, rest_n, rest_idx, st);
 }
 
 hipError_t launch_pic_tile(const Geom& g, const TileGeom& t, int guard, int threads, const FieldPtrs& f,
-                           const SpeciesDev& s, const int* toff, unsigned long long* acc,
+                           const SpeciesDev& s, const SpeciesDev* src, const int* toff, unsigned long long* acc,
                            int* d_err, int* rest_n, int* rest_idx, hipStream_t st) {
     switch (threads) {
-        case 256: return launch_tile_shape<256>(g, t, guard, f, s, toff, acc, d_err, rest_n, rest_idx, st);
-        case 1024: return launch_tile_shape<1024>(g, t, guard, f, s, toff, acc, d_err, rest_n, rest_idx, st);
-        default: return launch_tile_shape<512>(g, t, guard, f, s, toff, acc, d_err, rest_n, rest_idx, st);
+        case 256: return launch_tile_shape<256>(g, t, guard, f, s, src, toff, acc, d_err, rest_n, rest_idx, st);
+        case 1024: return launch_tile_shape<1024>(g, t, guard, f, s, src, toff, acc, d_err, rest_n, rest_idx, st);
+        default: return launch_tile_shape<512>(g, t, guard, f, s, src, toff, acc, d_err, rest_n, rest_idx, st);
     }
 }
 
