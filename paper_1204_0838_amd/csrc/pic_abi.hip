@@ -736,7 +736,7 @@ pic_status batch_one_step(pic_batch* b) {
         int total = 0;
         PICCHK(upload_tables(b, s, &dtab, &dbegin, &total));
         int max_sort = 0, max_keys1 = 0, max_tiles1 = 0;
-        bool any_sort = false;
+        bool any_sort = false, all_888g1 = true;
         size_t lds = 0;
         for (int i = 0; i < n; ++i) {
             pic_ctx* c = b->m[i];
@@ -753,6 +753,7 @@ pic_status batch_one_step(pic_batch* b) {
             }
             sp.prev_valid = false;
             lds = std::max(lds, tile_lds_bytes(c->tl.t, c->tl.guard));
+            all_888g1 = all_888g1 && c->tl.t.T[0] == 8 && c->tl.t.T[1] == 8 && c->tl.t.T[2] == 8 && c->tl.guard == 1;
         }
         hipEvent_t t0, t1, t2;
         if (any_sort) {
@@ -762,7 +763,7 @@ pic_status batch_one_step(pic_batch* b) {
             if (b->prof.on) b->prof.sorts += 1;
         }
         PICCHK(bmark(b, &t1));
-        BHIPCHK(b, launch_batch_tile(dtab, dbegin, n, total, b->m[0]->tl.threads, lds, b->stream));
+        BHIPCHK(b, launch_batch_tile(dtab, dbegin, n, total, b->m[0]->tl.threads, lds, all_888g1, b->stream));
         PICCHK(bend(b, PH_TILE, t1));
         if (b->prof.on) b->prof.tiles += 1;
         PICCHK(bmark(b, &t2));

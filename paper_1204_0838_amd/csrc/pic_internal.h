@@ -111,8 +111,9 @@ __host__ __device__ inline const SpeciesDev& step_arrays(const InstDesc& d) { re
 // except the tile step, whose work list is the concatenation of all tiles)
 hipError_t launch_batch_sort(const InstDesc* d, int n, int max_particles, int max_keys1, int max_tiles1,
                              hipStream_t st);
+// all_888g1: every member tiles 8x8x8 with guard 1 (the compile-time tile body)
 hipError_t launch_batch_tile(const InstDesc* d, const int* tile_begin, int n, int total_tiles, int threads,
-                             size_t lds_bytes, hipStream_t st);
+                             size_t lds_bytes, bool all_888g1, hipStream_t st);
 hipError_t launch_batch_rest(const InstDesc* d, int n, hipStream_t st);
 hipError_t launch_batch_jfinal(const InstDesc* d, int n, int max_cells, hipStream_t st);
 hipError_t launch_batch_binomial(const InstDesc* d, int n, int max_cells, hipStream_t st);

@@ -357,8 +357,9 @@ __global__ void __launch_bounds__(NT) k_pic_tile(Geom g, TileGeom t, int guard, 
 
 // Batched form: the work list is the concatenation of every member's tiles
 // (member m owns flat tiles [tile_begin[m], tile_begin[m+1])), mapped XCD by
-// XCD like the single-instance launch.
-template <int NT>
+// XCD like the single-instance launch.  TX..GD > 0 (>= 0): every member has
+// that tile shape and guard (the compile-time body of the single launch).
+template <int NT, int TX = 0, int TY = 0, int TZ = 0, int GD = -1>
 __global__ void __launch_bounds__(NT) k_batch_tile(const InstDesc* __restrict__ tab,
                                                    const int* __restrict__ tile_begin, int n, int total) {
     extern __shared__ unsigned long long lds_u64[];
@@ -376,10 +377,11 @@ __global__ void __launch_bounds__(NT) k_batch_tile(const InstDesc* __restrict__ 
     const SpeciesDev s = step_arrays(d);
     // a member that sorted this step gathers its particles from the pre-sort set
     if (d.sorting)
-        tile_body<NT, 0, 0, 0, -1, true>(g, t, d.guard, f, s, d.s, d.toff, d.acc, d.err, d.rest_n, d.rank, lds_u64,
-                                         ft - tile_begin[lo]);
+        tile_body<NT, TX, TY, TZ, GD, true>(g, t, d.guard, f, s, d.s, d.toff, d.acc, d.err, d.rest_n, d.rank, lds_u64,
+                                            ft - tile_begin[lo]);
     else
-        tile_body<NT>(g, t, d.guard, f, s, s, d.toff, d.acc, d.err, d.rest_n, d.rank, lds_u64, ft - tile_begin[lo]);
+        tile_body<NT, TX, TY, TZ, GD>(g, t, d.guard, f, s, s, d.toff, d.acc, d.err, d.rest_n, d.rank, lds_u64,
+                                      ft - tile_begin[lo]);
 }
 
 // The rest pass, after the tile kernel: the particles on the species' rest
@@ -501,25 +503,32 @@ hipError_t launch_pic_tile(const Geom& g, const TileGeom& t, int guard, int thre
     }
 }
 
-template <int NT>
-static hipError_t launch_batch_tile_nt(const InstDesc* d, const int* tile_begin, int n, int total, size_t lds,
-                                       hipStream_t st) {
+template <int NT, int TX = 0, int TY = 0, int TZ = 0, int GD = -1>
+static hipError_t launch_batch_tile_k(const InstDesc* d, const int* tile_begin, int n, int total, size_t lds,
+                                      hipStream_t st) {
     const int nb = xcd_blocks(total, kBatchChunk);
-    hipError_t e = hipFuncSetAttribute((const void*)k_batch_tile<NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
+    hipError_t e = hipFuncSetAttribute((const void*)k_batch_tile<NT, TX, TY, TZ, GD>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_batch_zero_rest, dim3((n + 63) / 64), dim3(64), 0, st, d, n);
-    hipLaunchKernelGGL(k_batch_tile<NT>, dim3(nb), dim3(NT), lds, st, d, tile_begin, n, total);
+    hipLaunchKernelGGL((k_batch_tile<NT, TX, TY, TZ, GD>), dim3(nb), dim3(NT), lds, st, d, tile_begin, n, total);
     return hipGetLastError();
 }
 
+template <int NT>
+static hipError_t launch_batch_tile_nt(const InstDesc* d, const int* tile_begin, int n, int total, size_t lds,
+                                       bool all_888g1, hipStream_t st) {
+    if (all_888g1) return launch_batch_tile_k<NT, 8, 8, 8, 1>(d, tile_begin, n, total, lds, st);
+    return launch_batch_tile_k<NT>(d, tile_begin, n, total, lds, st);
+}
+
 hipError_t launch_batch_tile(const InstDesc* d, const int* tile_begin, int n, int total_tiles, int threads,
-                             size_t lds_bytes, hipStream_t st) {
+                             size_t lds_bytes, bool all_888g1, hipStream_t st) {
     if (n <= 0 || total_tiles <= 0) return hipSuccess;
     switch (threads) {
-        case 256: return launch_batch_tile_nt<256>(d, tile_begin, n, total_tiles, lds_bytes, st);
-        case 1024: return launch_batch_tile_nt<1024>(d, tile_begin, n, total_tiles, lds_bytes, st);
-        default: return launch_batch_tile_nt<512>(d, tile_begin, n, total_tiles, lds_bytes, st);
+        case 256: return launch_batch_tile_nt<256>(d, tile_begin, n, total_tiles, lds_bytes, all_888g1, st);
+        case 1024: return launch_batch_tile_nt<1024>(d, tile_begin, n, total_tiles, lds_bytes, all_888g1, st);
+        default: return launch_batch_tile_nt<512>(d, tile_begin, n, total_tiles, lds_bytes, all_888g1, st);
     }
 }
 

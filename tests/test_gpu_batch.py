@@ -32,6 +32,14 @@ MEMBERS = [
     dict(n=(32, 16, 24), a0=4.5, dens=0.7, tiling=dict(tile=(4, 4, 4), guard=0, sort_interval=1), jpost="none"),
     dict(n=(24, 16, 16), yee=True, tiling=dict(tile=(8, 8, 8), interleave=1), jpost="none"),
 ]
+# every member on 8x8x8 tiles with guard 1 (the batch then runs the compiled
+# tile body of that shape), ragged grids and different sort schedules
+MEMBERS_888 = [
+    dict(n=(44, 20, 16), a0=2.5, dens=1.2, tiling=dict(tile=(8, 8, 8), guard=1, sort_interval=2), jpost="none"),
+    dict(n=(40, 16, 12), a0=4.0, dens=0.8, tiling=dict(tile=(8, 8, 8), guard=1, sort_interval=3, interleave=4),
+         jpost="binomial"),
+    dict(n=(20, 12, 16), yee=True, tiling=dict(tile=(8, 8, 8), guard=1, sort_interval=1), jpost="none"),
+]
 
 
 def _make(spec):
@@ -72,14 +80,15 @@ def _state(sim):
     return out
 
 
-def test_batch_members_match_single_runs():
+@pytest.mark.parametrize("members", [MEMBERS, MEMBERS_888], ids=["mixed_tilings", "all_8x8x8_guard1"])
+def test_batch_members_match_single_runs(members):
     singles = []
-    for spec in MEMBERS:
+    for spec in members:
         sim = _make(spec)
         sim.step(sum(STEPS))
         singles.append(_state(sim))
         sim.close()
-    sims = [_make(spec) for spec in MEMBERS]
+    sims = [_make(spec) for spec in members]
     batch = pic.Batch(sims)
     batch.profile_enable(True)
     for k in STEPS:
@@ -90,7 +99,7 @@ def test_batch_members_match_single_runs():
     for i, (sim, ref) in enumerate(zip(sims, singles)):
         got = _state(sim)
         assert got["window"] == ref["window"], i
-        if not MEMBERS[i].get("yee"):
+        if not members[i].get("yee"):
             assert got["window"][0] == sum(STEPS) - 24 + 1          # the window moved
             assert np.abs(ref["E"][1]).max() > 0.1                   # the laser is in
         for f in ("E", "B", "J"):
