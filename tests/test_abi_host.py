@@ -58,6 +58,20 @@ def test_validation_rejects_bad_descriptors(kw, fragment):
     assert fragment in msg
 
 
+def test_autotuner_lds_model_matches_the_library():
+    """The autotuner's LDS footprint (padded tile planes) decides feasibility
+    exactly as the library's own check does, for every tile shape and guard."""
+    from paper_1204_0838_amd import autotune
+    for tx in range(3, 17):
+        for ty in (3, 4, 6, 8, 12, 16):
+            for tz in (3, 4, 8, 16):
+                for guard in range(4):
+                    st, msg = pic.validate(_desc(n=(64, 64, 64), tile=(tx, ty, tz), guard=guard))
+                    lib_ok = st == pic.PIC_OK
+                    assert lib_ok or "LDS" in msg, msg
+                    assert lib_ok == autotune.feasible(dict(tile=(tx, ty, tz), guard=guard)), (tx, ty, tz, guard)
+
+
 def test_workspace_size_grows_with_particles_and_rejects_invalid():
     d = _desc()
     a = pic.workspace_bytes(d, 1000)
