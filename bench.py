@@ -3,19 +3,26 @@
 One step = the whole production step of the library (periodic cell sort,
 fused cubic gather + Boris push + Esirkepov deposit, current read-out,
 perfect-dispersion field update, laser source, window motion and plasma
-injection).  The job is the 1000-step C1 run: W warm-up steps, then K timed
-steps (defaults 5 + 995).  Prints one JSON line:
+injection).  The job is the 1000-step C1 run.  Its cost changes over the run
+(early on the laser has not reached the plasma and the cold particles do
+not move, so they deposit nothing; later the wake makes most of them move),
+so the K timed steps are spread evenly over the run: after W untimed
+warm-up steps, step W + floor((j + 1/2)(1000 - W)/K) is timed for j < K and
+the steps between are advanced untimed.  K = 1000 - W times every step.
+Each timed step is bracketed by device synchronisations and HIP events on
+the library's stream.  Prints one JSON line:
 
-  value      particle-steps/s over the timed steps (particles live in HBM
-             before timing starts; the count per step is the mean of the
-             counts before and after the timed region)
+  value      particle-steps/s over the timed steps (particles live in HBM;
+             the count of each timed step is the live count before it)
   roofline   the fused tile kernel (dominant): algorithmic bytes per launch
              (60 B per particle read+written, 24 B per cell of E/B read,
              24 B per cell of int64 current accumulated) over its mean
              launch time from HIP events on the library's stream, against
-             8 TB/s HBM3E
+             8 TB/s HBM3E; the sort's gather, which the launch after a sort
+             also does, is reported apart
   cpu_baseline  the FP64 oracle (single thread) on a crop of the same
-             workload, gather + push + deposit only
+             workload, gather + push + deposit only, and on the 16-step C0
+             parity workload
 """
 from __future__ import annotations
 
@@ -32,11 +39,47 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 
 
+def _host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"cpu_model": model, "nproc": avail}
+
+
+def _oracle_gpd(O, g, x, u, w, E, B, steps, field_steps=False):
+    """Time `steps` oracle gather+push+deposit passes (the field update, when
+    run, is untimed); returns (seconds, particle-steps)."""
+    t = 0.0
+    ps = 0
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        x0 = x.copy()
+        x, u, x1 = O.push(g, x, u, E, B)
+        J = O.deposit(g, x0, x1, w)
+        t += time.perf_counter() - t0
+        ps += x.shape[1]
+        if field_steps:
+            E, B = O.field_step(g, E, B, J)
+    return t, ps
+
+
 def cpu_baseline(cfg, crop=(64, 32, 32), steps=12):
-    """Oracle gather+push+deposit rate on a crop of the workload (one thread)."""
+    """Oracle gather+push+deposit rate on a crop of the workload (one thread),
+    and on the 16-step C0 parity workload."""
     import numpy as np
 
     from oracle import oracle as O
+    from paper_1204_0838_amd import inputs
 
     g = O.make_grid(crop, cfg["d"], cfg["dt"], solver=cfg["solver"], xbc=1)
     p = cfg["plasma"]
@@ -46,38 +89,49 @@ def cpu_baseline(cfg, crop=(64, 32, 32), steps=12):
     E = O.zeros_field(g)
     B = O.zeros_field(g)
     rng = np.random.default_rng(0)
-    E += 0.05 * rng.standard_normal(E.shape)   # a perturbed state so particles move
-    t = 0.0
-    for _ in range(steps):
-        t0 = time.perf_counter()
-        x0 = x.copy()
-        x, u, x1 = O.push(g, x, u, E, B)
-        O.deposit(g, x0, x1, w)
-        t += time.perf_counter() - t0
+    E += 0.05 * rng.standard_normal(E.shape)   # a perturbed state so particles move and deposit
+    t, ps = _oracle_gpd(O, g, x, u, w, E, B, steps)
     npart = x.shape[1]
-    return {"value": npart * steps / t, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"C1 geometry crop {crop[0]}x{crop[1]}x{crop[2]} cells ({npart} particles, ramp region), "
-                      f"{steps} FP64 oracle steps of gather+push+deposit, single thread"}
+    # C0: 64x32x32 periodic Yee grid, 524,288 electrons, 16 full steps (field update untimed)
+    c0g = inputs.c0_grid()
+    pl = inputs.c0_particles(seed=1)
+    og = O.from_grid(c0g)
+    t0, ps0 = _oracle_gpd(O, og, pl.positions(c0g), pl.u.astype(np.float64), pl.w.astype(np.float64),
+                          O.zeros_field(og), O.zeros_field(og), 16, field_steps=True)
+    return {"value": ps / t, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"C1 geometry crop {crop[0]}x{crop[1]}x{crop[2]} cells ({npart} particles, ramp region, "
+                      f"perturbed E so that particles move), {steps} FP64 oracle steps of gather+push+deposit, "
+                      f"single thread",
+            "host": _host_cpu(),
+            "c0_16_steps": {"value": ps0 / t0, "unit": "particle-steps/s", "cores": 1,
+                            "sample": "C0 64x32x32 periodic Yee grid, 524,288 electrons, 16 FP64 oracle steps, "
+                                      "gather+push+deposit timed (field update untimed), single thread"}}
 
 
 KERNEL_SOURCES = ("paper_1204_0838_amd/csrc/pic_tile.hip", "paper_1204_0838_amd/csrc/pic_particle_ops.h",
                   "paper_1204_0838_amd/csrc/pic_device.h")
 
 
-def tile_alg_bytes(npart, ncell, prof):
-    """Algorithmic HBM bytes of one tile launch, averaged over the timed
-    launches: 60 B per particle (cell, off, u, w read; cell, off, u written)
-    and 48 B per cell (E, B staged once; the int64 current added once), plus
-    16 B per particle on the launches right after a sort, which do the sort's
-    gather (the source index and id read, w and id written)."""
-    gather_share = prof["sorts"] / max(1, prof["tile_launches"])
-    return (60.0 + 16.0 * gather_share) * npart + 48.0 * ncell
+def tile_alg_bytes(npart, ncell):
+    """Algorithmic HBM bytes of one tile launch: 60 B per particle (cell, off,
+    u, w read; cell, off, u written) and 48 B per cell (E, B staged once; the
+    int64 current added once)."""
+    return 60.0 * npart + 48.0 * ncell
 
 
-def measured_traffic(path, cfg):
+def sort_gather_bytes(npart, prof):
+    """Per tile launch, averaged over the timed launches: the sort's gather
+    that the launch right after a sort does (source index and id read, w and
+    id written: 16 B per particle) -- sort traffic, not gather+push+deposit."""
+    return 16.0 * npart * prof["sorts"] / max(1, prof["tile_launches"])
+
+
+def measured_traffic(path, cfg, idx):
     """HBM bytes per k_pic_tile launch from the committed rocprofv3 counter
-    summary, or None when it is missing, for another grid, or the kernel
-    sources changed since it was measured."""
+    summary, averaged over the timed steps `idx` (the summary holds the bytes
+    of each launch of the run: one launch per step), or None when it is
+    missing, for another grid, or the kernel sources changed since it was
+    measured."""
     import hashlib
 
     if cfg["n"] != (512, 256, 256) or not os.path.exists(path):
@@ -88,7 +142,10 @@ def measured_traffic(path, cfg):
     for rel in KERNEL_SOURCES:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
-    return rec.get("bytes_per_launch") if rec.get("source_sha256") == h.hexdigest() else None
+    per_step = rec.get("mb_per_launch_by_step")
+    if rec.get("source_sha256") != h.hexdigest() or not per_step or max(idx) >= len(per_step):
+        return None
+    return 1e6 * sum(per_step[i] for i in idx) / len(idx)
 
 
 def bench_c3(args):
@@ -134,7 +191,7 @@ def bench_c3(args):
     K = args.steps
     ncell = sum(c["n"][0] * c["n"][1] * c["n"][2] for c in cfgs)
     tile_ms = prof["tile_ms"] / max(1, prof["tile_launches"])
-    alg_bytes = tile_alg_bytes(npart, ncell, prof)
+    alg_bytes = tile_alg_bytes(npart, ncell)
     achieved = alg_bytes / (tile_ms * 1e-3) / 1e9
     # the same members one after another (per-member launches), a few steps
     seq_steps = 10
@@ -163,14 +220,16 @@ def bench_c3(args):
                                "per phase for all members",
                    "members": len(sims), "particles": int(npart), "cells": ncell,
                    "tiling_by_class": {k: v for k, v in zip([workloads.size_class(c) for c in cfgs], tilings)}},
-        "gather_push_deposit_particle_steps_per_s": npart * prof["tile_launches"] / (prof["tile_ms"] * 1e-3),
+        "gather_push_deposit_particle_steps_per_s": npart * prof["steps"] / ((prof["tile_ms"] + prof["loose_ms"])
+                                                                             * 1e-3),
         "phase_ms_per_step": {k[:-3]: prof[k] / max(1, prof["steps"]) for k in
                               ("sort_ms", "tile_ms", "loose_ms", "jpost_ms", "field_ms", "window_ms")},
         "sequential_ms_per_step": seq_ms,
         "batched_speedup_vs_sequential": seq_ms / (ms / K),
         "roofline": {"bound": "hbm", "kernel": "k_batch_tile", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "alg_bytes_per_launch": alg_bytes, "mean_launch_ms": tile_ms},
+                     "alg_bytes_per_launch": alg_bytes, "sort_gather_bytes_per_launch": sort_gather_bytes(npart, prof),
+                     "mean_launch_ms": tile_ms},
         "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
@@ -241,7 +300,7 @@ def bench_c4(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=995)
+    ap.add_argument("--steps", type=int, default=0, help="timed steps (default: every step after the warm-up)")
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--grid", type=str, default="", help="override nx,ny,nz (default: the C1 grid)")
     ap.add_argument("--tile", type=str, default="")
@@ -273,21 +332,36 @@ def main():
         return
 
     if args.workload == "c3":
-        if args.steps == 995:
-            args.steps = 195
+        args.steps = args.steps or 195
         bench_c3(args)
         return
     if args.workload == "c4":
-        if args.steps == 995:
-            args.steps = 200
+        args.steps = args.steps or 200
         bench_c4(args)
         return
+    args.steps = args.steps or 1000 - args.warmup
+
+    bench_c1(args)
+
+
+def timed_indices(total, warmup, k):
+    """K step indices spread evenly over [warmup, total) (all of them when k = total - warmup)."""
+    span = total - warmup
+    return [warmup + int((j + 0.5) * span / k) for j in range(k)]
+
+
+def bench_c1(args):
+    import torch
 
     from paper_1204_0838_amd import workloads
 
     cfg = workloads.C1
     if args.grid:
         cfg = workloads.scaled(cfg, [int(v) for v in args.grid.split(",")])
+    total = cfg["steps"]
+    if args.warmup + args.steps > total:
+        print(f"warmup + steps must not exceed the {total}-step run", file=sys.stderr)
+        sys.exit(2)
     tiling = {}
     if args.tile:
         tiling["tile"] = tuple(int(v) for v in args.tile.split(","))
@@ -300,43 +374,54 @@ def main():
     t_setup = time.perf_counter()
     sim = workloads.build(cfg, **tiling)
     sim.sync()
+    idx = timed_indices(total, args.warmup, args.steps)
     print(f"# setup {time.perf_counter() - t_setup:.1f}s, window starts at step "
-          f"{workloads.window_start_step(cfg)}", file=sys.stderr, flush=True)
-    done = 0
-    while done < args.warmup:
-        k = min(100, args.warmup - done)
-        sim.step(k)
-        done += k
-    sim.sync()
-    n0 = sim.reduce()["n_particles"]
-    sim.profile_enable(True)
+          f"{workloads.window_start_step(cfg)}, {len(idx)} timed steps from {idx[0]} to {idx[-1]}",
+          file=sys.stderr, flush=True)
     st = sim.stream
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(st)
-    left = args.steps
-    while left > 0:
-        k = min(100, left)
-        sim.step(k)
-        left -= k
-        if args.steps >= 200 and left % 200 == 0:
-            print(f"# {args.steps - left}/{args.steps} steps", file=sys.stderr, flush=True)
-    e1.record(st)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    prof = sim.profile_read()
-    n1 = sim.reduce()["n_particles"]
-    npart = 0.5 * (n0 + n1)
-    K = args.steps
-    value = npart * K / (ms * 1e-3)
+    keys = ("sort_ms", "tile_ms", "loose_ms", "jpost_ms", "field_ms", "window_ms", "steps", "sorts", "tile_launches")
+    prof = {k: 0 for k in keys}
+    ms = 0.0
+    part_steps = 0.0
+    part_launches = 0.0
+    done = 0
+    last_note = time.perf_counter()
+    for j, i in enumerate(idx):
+        while done < i:                       # untimed advance to the next timed step
+            k = min(100, i - done)
+            sim.step(k)
+            done += k
+        sim.sync()
+        n_live = sim.reduce()["n_particles"]
+        sim.profile_enable(True)
+        torch.cuda.synchronize()
+        e0.record(st)
+        sim.step(1)
+        e1.record(st)
+        torch.cuda.synchronize()
+        done += 1
+        ms += e0.elapsed_time(e1)
+        p = sim.profile_read()
+        sim.profile_enable(False)
+        for k in keys:
+            prof[k] += p[k]
+        part_steps += n_live
+        part_launches += n_live * p["tile_launches"]
+        if time.perf_counter() - last_note > 20 or j + 1 == len(idx):
+            print(f"# {j + 1}/{len(idx)} timed steps (step {i})", file=sys.stderr, flush=True)
+            last_note = time.perf_counter()
+    K = len(idx)
+    value = part_steps / (ms * 1e-3)
+    npart = part_steps / K                    # mean live particles over the timed steps
     ncell = cfg["n"][0] * cfg["n"][1] * cfg["n"][2]
     launches = max(1, prof["tile_launches"])
     tile_ms = prof["tile_ms"] / launches
-    alg_bytes = tile_alg_bytes(npart, ncell, prof)
+    alg_bytes = tile_alg_bytes(part_launches / launches, ncell)
     achieved = alg_bytes / (tile_ms * 1e-3) / 1e9
     traffic = measured_traffic(args.traffic_json or os.path.join(ROOT, "profiles", "k_pic_tile_C1_traffic.json"),
-                               cfg)
+                               cfg, idx)
     out = {
         "metric": "particle-steps/s (gather+push+deposit), % HBM peak; plain vs denoised at eps",
         "value": value,
@@ -353,7 +438,12 @@ def main():
         "config": {
             "workload": "C1 3D LWFA moving-window slab {}x{}x{}, dx=0.25 dy=dz=0.5 c/wp, perfect-dispersion "
                         "solver c dt = dx, 8 ppc cold lattice plasma behind a 50-cell ramp, a0=4 w0=5 "
-                        "FWHM 2.5 laser from the x boundary, window at c, 1000-step run".format(*cfg["n"]),
+                        "FWHM 2.5 laser from the x boundary, window at c from step {}, {}-step run; timed steps "
+                        "{}: {} spread evenly over steps {}-{} (untimed advance between them)".format(
+                            *cfg["n"], workloads.window_start_step(cfg), total, K,
+                            "every step" if K == total - args.warmup else "one in ~{}".format(
+                                round((total - args.warmup) / K)), idx[0], idx[-1]),
+            "timed_step_indices": idx if K <= 50 else "{}..{}".format(idx[0], idx[-1]),
             "particles": int(npart),
             "cells": ncell,
             "tiling": {"tile": [sim.desc.tile[a] or 8 for a in range(3)],
@@ -362,9 +452,8 @@ def main():
                        "sort_interval": sim.desc.sort_interval or 2,
                        "source": "explicit" if tiling else "autotune cache or library default"},
         },
-        "gather_push_deposit_particle_steps_per_s": npart * launches / (prof["tile_ms"] * 1e-3),
-        "phase_ms_per_step": {k[:-3]: prof[k] / max(1, prof["steps"]) for k in
-                              ("sort_ms", "tile_ms", "loose_ms", "jpost_ms", "field_ms", "window_ms")},
+        "gather_push_deposit_particle_steps_per_s": part_steps / ((prof["tile_ms"] + prof["loose_ms"]) * 1e-3),
+        "phase_ms_per_step": {k[:-3]: prof[k] / max(1, prof["steps"]) for k in keys[:6]},
         "roofline": {
             "bound": "hbm",
             "kernel": "k_pic_tile",
@@ -374,10 +463,12 @@ def main():
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
             "alg_bytes_per_launch": alg_bytes,
+            "sort_gather_bytes_per_launch": sort_gather_bytes(npart, prof),
             "mean_launch_ms": tile_ms,
         },
         "cpu_baseline": None,
     }
+    sim.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(out), flush=True)

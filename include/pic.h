@@ -216,14 +216,25 @@ pic_status pic_init_species(pic_ctx *ctx, const pic_species_bufs *bufs, int64_t 
                             int32_t *species_out);
 
 /* Field gather + Boris push + move for one species: x^n, u^{n-1/2} ->
- * x^{n+1}, u^{n+1/2}, using E^n, B^n.  Keeps x^n in the workspace for
- * pic_deposit.  Asynchronous. */
+ * x^{n+1}, u^{n+1/2}, using E^n, B^n.  This is the particle half of the PIC
+ * cycle of Section 1 (particles in continuous phase space driven by the
+ * grid fields); the paper's advance of the macroparticles is the cost it
+ * names as dominant (Section 1).  The interpolation is the third-order
+ * (cubic) B-spline of the macroparticle shapes (Sections 1 and 3.1) taken
+ * at each field component's own staggered position.  The paper does not
+ * name its pusher: this library uses the relativistic Boris rotation.
+ * Keeps x^n in the workspace for pic_deposit.  Asynchronous. */
 pic_status pic_gather_push(pic_ctx *ctx, int32_t species);
 
-/* Charge-conserving cubic deposit of the species' motion x^n -> x^{n+1}
- * (the last pic_gather_push) into the exact fixed-point current accumulator;
- * then J (FP32) is set to the accumulated current of all species deposited
- * since the last field step.  Asynchronous. */
+/* The current J of eq. 2.1, "deposited from particle motion" (Section 2),
+ * for the species' motion x^n -> x^{n+1} of the last pic_gather_push, with
+ * the cubic shapes of Sections 1 and 3.1.  The paper does not name the
+ * deposition scheme: this library uses Esirkepov's charge-conserving
+ * decomposition, so the discrete continuity equation holds exactly for the
+ * charge the same shapes deposit.  Contributions are summed in an exact
+ * int64 fixed-point accumulator (2^-40 units; independent of order), then J
+ * (FP32) is set to the accumulated current of all species deposited since
+ * the last field step.  Asynchronous. */
 pic_status pic_deposit(pic_ctx *ctx, int32_t species);
 
 /* J post-processing (desc.jpost), then B^{n+1/2} = B^n - dt/2 curl'E^n,
@@ -232,13 +243,19 @@ pic_status pic_deposit(pic_ctx *ctx, int32_t species);
  * filter, J holds the filtered current.  Asynchronous. */
 pic_status pic_field_step(pic_ctx *ctx);
 
-/* nsteps full production steps: periodic cell sort, fused tiled
- * gather+push+deposit of every species, J post-processing, field update and
- * window motion.  Equal to pic_gather_push + pic_deposit (all species) +
- * pic_field_step per step, bit for bit.  Asynchronous. */
+/* nsteps full production steps of the PIC cycle of Section 1 (fields on
+ * the grid advanced by eq. 2.1 of Section 2, particles advanced in
+ * continuous phase space) with the moving window of Section 1: periodic
+ * cell sort, fused tiled gather+push+deposit of every species, J
+ * post-processing, field update and window motion.  Equal to
+ * pic_gather_push + pic_deposit (all species) + pic_field_step per step,
+ * bit for bit.  Asynchronous. */
 pic_status pic_step(pic_ctx *ctx, int32_t nsteps);
 
 /* Counting sort of one species by tile and cell; drops removed particles.
+ * Not part of the paper's method: a data layout of this library (particles
+ * of one tile are contiguous so the fused step can stage the tile's fields
+ * and current in on-chip memory); it changes no result.
  * Tiles of 8 x 2m x 4k cells are stored in 8x2x4-cell bricks (x fastest,
  * then z, then y inside a brick), other tiles in x-fastest cell order; then
  * the in-tile block transpose of the tiling's interleave depth.  The
@@ -250,13 +267,18 @@ pic_status pic_sort(pic_ctx *ctx, int32_t species);
  * Synchronises the stream and reports device-side errors. */
 pic_status pic_species_view(pic_ctx *ctx, int32_t species, pic_species_bufs *out, int64_t *n_live);
 
-/* Continuity check of the last gather_push/deposit pair, FP64 on the device:
+/* Continuity check of the last gather_push/deposit pair (the charge
+ * conservation that the current of eq. 2.1 must obey), FP64 on the device:
  * max over nodes of |(rho^{n+1} - rho^n) dx/dt + sum_d (dx/d_d)(J_d - J_d[-e_d])|
  * with rho deposited in FP64 from the stored FP32 positions and J the FP32
  * current.  *resid and *max_abs_j are host outputs.  Synchronises. */
 pic_status pic_continuity(pic_ctx *ctx, int32_t species, double *resid, double *max_abs_j);
 
-/* FP64 diagnostics (host output).  Synchronises; reports device errors. */
+/* FP64 diagnostics (host output): total charge, field energy, kinetic
+ * energy, max |J| and the live particle count (pic_diag).  Section 3 names
+ * grid heating among the numerical artefacts a predictive code must not
+ * introduce; the field and kinetic energy sums are what watching for it
+ * takes.  Synchronises; reports device errors. */
 pic_status pic_reduce(pic_ctx *ctx, pic_diag *host_out);
 
 /* Wait for queued work; report device-side errors. */
@@ -290,6 +312,40 @@ pic_status pic_set_window(pic_ctx *ctx, int64_t start_step);
 /* Cells the window has moved and the storage x index of window cell 0
  * (host outputs). */
 pic_status pic_window_state(pic_ctx *ctx, int64_t *shift, int32_t *origin);
+
+/* ---- Checkpoint / resume ---------------------------------------------------
+ *
+ * A long laser-wakefield run (the paper's runs take 10^5 CPU-hours,
+ * Section 3.1) is resumed from a host copy of its state.  The blob holds the
+ * fields E, B, J, every species' particles (cell, off, u, w, id of the live
+ * and not yet dropped entries), the step counter, the window's shift and
+ * origin (which fix where the next plasma slab is loaded and whether the
+ * laser source is active).  Configuration is not in the blob: a resumed run
+ * is a context made with the same descriptor, the same species (capacities
+ * at least the stored counts) and the same pic_set_laser / pic_set_plasma /
+ * pic_set_window / pic_denoiser_set calls.  A resumed run reaches the same
+ * fields and particles (by id) bit for bit as the uninterrupted one: the
+ * current is summed in an order-independent fixed-point accumulator and
+ * the cell sort changes no result.
+ * Layout (host byte order): a header, then E[3], B[3], J[3] as
+ * n[0]*n[1]*n[2] floats each, then for each species its count entries of
+ * cell, off[0..2], u[0..2], w, id (4 bytes per value, array by array). */
+
+/* Bytes pic_copy_out needs for the current state (host output).
+ * Synchronises the stream and reports device errors. */
+pic_status pic_checkpoint_bytes(pic_ctx *ctx, size_t *bytes);
+
+/* Copy the state into host_blob (host memory of `bytes` bytes; PIC_ENOMEM
+ * if too small).  PIC_ESTATE inside a split-path step (pic_gather_push
+ * without the closing pic_field_step).  Synchronises. */
+pic_status pic_copy_out(pic_ctx *ctx, void *host_blob, size_t bytes);
+
+/* Restore a state written by pic_copy_out into a context with the same grid
+ * (n, d, dt, solver, x boundary) and species count (PIC_EINVAL otherwise;
+ * PIC_ENOMEM when a species' capacity is below its stored count).  The
+ * caller's species arrays receive the particles; every species is re-sorted
+ * at its next pic_step.  Synchronises. */
+pic_status pic_copy_in(pic_ctx *ctx, const void *host_blob, size_t bytes);
 
 /* Change the fused step's tiling on a live context (same meaning and
  * defaults as the pic_grid_desc fields; the LDS footprint must fit).  Every

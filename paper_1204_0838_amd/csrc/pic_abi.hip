@@ -256,6 +256,8 @@ struct pic_ctx {
     DenoiseWeights dn{};
     // phase timing (pic_profile_*)
     Prof prof;
+    // a split-path step is in progress (pic_gather_push since the last pic_field_step)
+    bool mid_step = false;
 };
 
 namespace {
@@ -572,6 +574,55 @@ pic_status finish_step(pic_ctx* c) {
     PICCHK(field_update(c, Juse));
     PICCHK(prof_end(c, PH_FIELD, t1));
     return end_step(c);
+}
+
+
+// ---- checkpoint blob ---------------------------------------------------------
+// header, then E[3], B[3], J[3] (ncell floats each), then per species its
+// `count` particles as cell, off[3], u[3], w, id arrays (4 bytes per value).
+constexpr uint64_t kCkptMagic = 0x4b43353533434950ull;   // "PIC355CK" little-endian
+constexpr uint32_t kCkptVersion = 1;
+
+struct CkptHeader {
+    uint64_t magic;
+    uint32_t version;
+    uint32_t nspecies;
+    int32_t n[3];
+    int32_t origin;
+    int32_t solver, bc_x;
+    double d[3];
+    double dt;
+    int64_t step;
+    int64_t shift;
+    int64_t count[kMaxSpecies];
+};
+
+constexpr int kCkptArrays = 9;   // cell, off[3], u[3], w, id
+
+size_t ckpt_bytes(const pic_ctx* c, const int64_t* count) {
+    size_t b = sizeof(CkptHeader) + 9 * (size_t)c->g.ncell * 4;
+    for (size_t s = 0; s < c->sp.size(); ++s) b += (size_t)count[s] * 4 * kCkptArrays;
+    return b;
+}
+
+// The nine per-particle arrays of a buffer set, in blob order.
+void ckpt_arrays(const pic_species_bufs& b, void* out[kCkptArrays]) {
+    out[0] = b.cell;
+    for (int a = 0; a < 3; ++a) {
+        out[1 + a] = b.off[a];
+        out[4 + a] = b.u[a];
+    }
+    out[7] = b.w;
+    out[8] = b.id;
+}
+
+// Exact particle counts of every species (synchronises).
+pic_status exact_counts(pic_ctx* c, int64_t* count) {
+    int cnt[kMaxSpecies] = {};
+    HIPCHK(c, hipMemcpyAsync(cnt, small_of(c)->count, sizeof cnt, hipMemcpyDeviceToHost, c->stream));
+    PICCHK(device_errors(c));
+    for (size_t s = 0; s < c->sp.size(); ++s) count[s] = cnt[s];
+    return PIC_OK;
 }
 
 }  // namespace
@@ -958,6 +1009,7 @@ pic_status pic_gather_push(pic_ctx* c, int32_t s) {
     HIPCHK(c, launch_gather_push(c->g, fields_of(c), dev_of(c, sp), prev_of(c, sp), &small_of(c)->count[s],
                                  (int)sp.bound, &small_of(c)->err, c->stream));
     sp.prev_valid = true;
+    c->mid_step = true;
     return PIC_OK;
 }
 
@@ -979,6 +1031,7 @@ pic_status pic_field_step(pic_ctx* c) {
     PICCHK(filter_in_place(c));
     PICCHK(field_update(c, Juse));
     HIPCHK(c, launch_zero_u64(acc_of(c), 3 * (int64_t)c->g.ncell, c->stream));
+    c->mid_step = false;
     return end_step(c);
 }
 
@@ -1160,6 +1213,117 @@ pic_status pic_window_state(pic_ctx* c, int64_t* shift, int32_t* origin) {
     if (!c) return PIC_EINVAL;
     if (shift) *shift = c->shift;
     if (origin) *origin = c->g.origin;
+    return PIC_OK;
+}
+
+pic_status pic_checkpoint_bytes(pic_ctx* c, size_t* bytes) {
+    if (!c || !bytes) return PIC_EINVAL;
+    int64_t count[kMaxSpecies] = {};
+    PICCHK(exact_counts(c, count));
+    *bytes = ckpt_bytes(c, count);
+    return PIC_OK;
+}
+
+pic_status pic_copy_out(pic_ctx* c, void* host_blob, size_t bytes) {
+    if (!c || !host_blob) return PIC_EINVAL;
+    if (c->mid_step) return fail(c, PIC_ESTATE, "checkpoint inside a split-path step (gather_push without field_step)");
+    int64_t count[kMaxSpecies] = {};
+    PICCHK(exact_counts(c, count));
+    const size_t need = ckpt_bytes(c, count);
+    if (bytes < need) return fail(c, PIC_ENOMEM, "checkpoint needs %zu bytes, blob has %zu", need, bytes);
+    CkptHeader h;
+    memset(&h, 0, sizeof h);
+    h.magic = kCkptMagic;
+    h.version = kCkptVersion;
+    h.nspecies = (uint32_t)c->sp.size();
+    for (int a = 0; a < 3; ++a) {
+        h.n[a] = c->desc.n[a];
+        h.d[a] = c->desc.d[a];
+    }
+    h.origin = c->g.origin;
+    h.solver = c->desc.solver;
+    h.bc_x = c->desc.bc_x;
+    h.dt = c->desc.dt;
+    h.step = c->step;
+    h.shift = c->shift;
+    for (size_t s = 0; s < c->sp.size(); ++s) h.count[s] = count[s];
+    char* p = reinterpret_cast<char*>(host_blob);
+    memcpy(p, &h, sizeof h);
+    p += sizeof h;
+    const size_t fbytes = (size_t)c->g.ncell * 4;
+    float* const* F[3] = {c->f.E, c->f.B, c->f.J};
+    for (int k = 0; k < 3; ++k)
+        for (int a = 0; a < 3; ++a) {
+            HIPCHK(c, hipMemcpyAsync(p, F[k][a], fbytes, hipMemcpyDeviceToHost, c->stream));
+            p += fbytes;
+        }
+    for (size_t s = 0; s < c->sp.size(); ++s) {
+        void* arr[kCkptArrays];
+        ckpt_arrays(c->sp[s].cur, arr);
+        const size_t pb = (size_t)count[s] * 4;
+        for (int k = 0; k < kCkptArrays; ++k) {
+            if (pb) HIPCHK(c, hipMemcpyAsync(p, arr[k], pb, hipMemcpyDeviceToHost, c->stream));
+            p += pb;
+        }
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PIC_OK;
+}
+
+pic_status pic_copy_in(pic_ctx* c, const void* host_blob, size_t bytes) {
+    if (!c || !host_blob) return PIC_EINVAL;
+    if (bytes < sizeof(CkptHeader)) return fail(c, PIC_EINVAL, "checkpoint blob shorter than its header");
+    CkptHeader h;
+    memcpy(&h, host_blob, sizeof h);
+    if (h.magic != kCkptMagic || h.version != kCkptVersion) return fail(c, PIC_EINVAL, "not a checkpoint of this library");
+    for (int a = 0; a < 3; ++a)
+        if (h.n[a] != c->desc.n[a] || h.d[a] != c->desc.d[a])
+            return fail(c, PIC_EINVAL, "checkpoint grid differs from the context's");
+    if (h.dt != c->desc.dt || h.solver != c->desc.solver || h.bc_x != c->desc.bc_x)
+        return fail(c, PIC_EINVAL, "checkpoint time step, solver or x boundary differs from the context's");
+    if (h.nspecies != c->sp.size()) return fail(c, PIC_EINVAL, "checkpoint has %u species, context %zu", h.nspecies,
+                                                c->sp.size());
+    if (h.origin < 0 || h.origin >= c->g.n[0] || h.step < 0 || h.shift < 0 || (!c->g.window && (h.shift || h.origin)))
+        return fail(c, PIC_EINVAL, "invalid step or window state in the checkpoint");
+    for (size_t s = 0; s < c->sp.size(); ++s)
+        if (h.count[s] < 0 || h.count[s] > c->sp[s].user.capacity)
+            return fail(c, PIC_ENOMEM, "species %zu: %lld particles exceed capacity %lld", s, (long long)h.count[s],
+                        (long long)c->sp[s].user.capacity);
+    if (bytes < ckpt_bytes(c, h.count)) return fail(c, PIC_EINVAL, "checkpoint blob truncated");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const char* p = reinterpret_cast<const char*>(host_blob) + sizeof h;
+    const size_t fbytes = (size_t)c->g.ncell * 4;
+    float* const* F[3] = {c->f.E, c->f.B, c->f.J};
+    for (int k = 0; k < 3; ++k)
+        for (int a = 0; a < 3; ++a) {
+            HIPCHK(c, hipMemcpyAsync(F[k][a], p, fbytes, hipMemcpyHostToDevice, c->stream));
+            p += fbytes;
+        }
+    Small* sm = small_of(c);
+    for (size_t s = 0; s < c->sp.size(); ++s) {
+        Species& sp = c->sp[s];
+        // the caller's arrays hold the data again; the workspace set is the spare
+        if (sp.cur.cell != sp.user.cell) std::swap(sp.cur, sp.alt);
+        void* arr[kCkptArrays];
+        ckpt_arrays(sp.cur, arr);
+        const size_t pb = (size_t)h.count[s] * 4;
+        for (int k = 0; k < kCkptArrays; ++k) {
+            if (pb) HIPCHK(c, hipMemcpyAsync(arr[k], p, pb, hipMemcpyHostToDevice, c->stream));
+            p += pb;
+        }
+        int cnt[2] = {(int)h.count[s], 0};
+        HIPCHK(c, hipMemcpyAsync(&sm->count[s], &cnt[0], sizeof(int), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(&sm->sorted[s], &cnt[1], sizeof(int), hipMemcpyHostToDevice, c->stream));
+        sp.bound = h.count[s];
+        sp.sorted = false;
+        sp.prev_valid = false;
+    }
+    HIPCHK(c, launch_zero_u64(acc_of(c), 3 * (int64_t)c->g.ncell, c->stream));
+    c->step = h.step;
+    c->shift = h.shift;
+    c->g.origin = h.origin;
+    c->mid_step = false;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     return PIC_OK;
 }
 

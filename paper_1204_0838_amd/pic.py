@@ -81,6 +81,9 @@ class Tiling(ctypes.Structure):
 # every symbol the header declares, with its ctypes signature
 _SIGS = {
     "pic_set_tiling": (ctypes.c_int, [_vp, ctypes.POINTER(Tiling)]),
+    "pic_checkpoint_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+    "pic_copy_out": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
+    "pic_copy_in": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
     "pic_profile_enable": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "pic_profile_read": (ctypes.c_int, [_vp, ctypes.POINTER(Profile)]),
     "pic_set_laser": (ctypes.c_int, [_vp, ctypes.POINTER(LaserDesc)]),
@@ -375,6 +378,20 @@ class Simulation:
         d = Diag()
         self._check(lib().pic_reduce(self.handle, ctypes.byref(d)))
         return {k: getattr(d, k) for k, _ in Diag._fields_}
+
+    # ------------------------------------------------------------ checkpoint
+    def copy_out(self) -> bytes:
+        """Host checkpoint blob of the current state (synchronises)."""
+        nb = ctypes.c_size_t()
+        self._check(lib().pic_checkpoint_bytes(self.handle, ctypes.byref(nb)))
+        buf = ctypes.create_string_buffer(nb.value)
+        self._check(lib().pic_copy_out(self.handle, ctypes.cast(buf, _vp), nb.value))
+        return buf.raw
+
+    def copy_in(self, blob: bytes):
+        """Restore a checkpoint blob written by copy_out (synchronises)."""
+        buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+        self._check(lib().pic_copy_in(self.handle, ctypes.cast(buf, _vp), len(blob)))
 
     # ------------------------------------------------------------ views
     def _tensor_at(self, ptr, n, dtype, s):

@@ -121,3 +121,55 @@ def test_batched_step_and_eval_agree_with_single_crop_losses():
     b0 = tr.get_params()[1].copy()
     tr.step_batch([a for a, _ in pairs], [b for _, b in pairs], 1e-3)
     assert np.array_equal(tr.get_params()[1], b0)
+
+
+def test_trainer_gradients_on_a_crop_of_more_than_512_tiles():
+    """A 100x42x60 crop has 7 x 11 x 8 = 616 output tiles of 16x4x8 cells, so
+    the weight-gradient kernel (at most 512 workgroups) sums several tiles per
+    workgroup: tile t and tile t + 512 in one.  The data sit in two boxes, one
+    in tile 40 and one across tiles 551 and 552 (ragged tiles on the x and z
+    faces), with zeros elsewhere; with zero biases nothing outside a box's
+    7-cell neighbourhood is touched, so the crop's gradient is the sum of
+    the gradients of two small crops around the boxes (each box plus an
+    8-cell margin, cut at the crop's faces, where both see zero padding),
+    weighted by their cell counts: the oracle computes those small crops."""
+    crop = (100, 42, 60)
+    nx, ny, nz = crop
+    print(f"trainer gradients on a {crop} crop (616 tiles)", flush=True)
+    rng = np.random.default_rng(61)
+    J = np.zeros((3, nz, ny, nx))
+    T = np.zeros_like(J)
+    boxes = [((82, 90), (20, 24), (2, 6)), ((92, 100), (4, 8), (56, 60))]
+    for (x0, x1), (y0, y1), (z0, z1) in boxes:
+        shp = (3, z1 - z0, y1 - y0, x1 - x0)
+        Jb = rng.standard_normal(shp) * SCALE[:, None, None, None]
+        J[:, z0:z1, y0:y1, x0:x1] = Jb
+        T[:, z0:z1, y0:y1, x0:x1] = Jb + 0.5 * rng.standard_normal(shp) * SCALE[:, None, None, None]
+    J = J.astype(np.float32)
+    T = T.astype(np.float32)
+    P = _params(62)
+    for k in (1, 3, 5):
+        P[k] = np.zeros_like(P[k])
+    d = (0.25, 0.5, 0.4)
+    tr = pic.DenoiserTrainer(crop, cell=d)
+    tr.set_params(P, SCALE)
+    loss, G = tr.grad(torch.as_tensor(J).cuda().contiguous(), torch.as_tensor(T).cuda().contiguous())
+    s = SCALE[:, None, None, None]
+    n_big = nx * ny * nz
+    ref_loss = 0.0
+    ref_G = [np.zeros_like(p) for p in P]
+    for (x0, x1), (y0, y1), (z0, z1) in boxes:
+        sx = slice(max(0, x0 - 8), min(nx, x1 + 8))
+        sy = slice(max(0, y0 - 8), min(ny, y1 + 8))
+        sz = slice(max(0, z0 - 8), min(nz, z1 + 8))
+        Js = np.ascontiguousarray(J[:, sz, sy, sx]).astype(np.float64)
+        Ts = np.ascontiguousarray(T[:, sz, sy, sx]).astype(np.float64)
+        n_small = Js.shape[1] * Js.shape[2] * Js.shape[3]
+        ls, Gs = O.denoise_grad(Js, _bf16_array(Js / s), Ts, SCALE, P, d=d, bc=("zero", "zero", "zero"))
+        ref_loss += ls * n_small / n_big
+        for acc, g in zip(ref_G, Gs):
+            acc += g * (n_small / n_big)
+    assert abs(loss - ref_loss) <= 1e-2 * ref_loss
+    for name, g, gr in zip(("W1", "b1", "W2", "b2", "W3", "b3"), G, ref_G):
+        assert np.all(np.isfinite(g)), name
+        assert rel_l2(g, gr) <= 3e-2, (name, rel_l2(g, gr))
