@@ -274,6 +274,18 @@ pic_status pic_species_view(pic_ctx *ctx, int32_t species, pic_species_bufs *out
  * current.  *resid and *max_abs_j are host outputs.  Synchronises. */
 pic_status pic_continuity(pic_ctx *ctx, int32_t species, double *resid, double *max_abs_j);
 
+/* pic_continuity without the workspace: for callers that cannot allocate
+ * device memory themselves (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, results and
+ * synchronisation as pic_continuity, but its scratch (the FP64 charge
+ * density and the reduction words) is a fixed device array of the library,
+ * 16 MiB + 256 B per GPU, held until the process ends; it allocates
+ * nothing and writes nothing to the workspace's density buffer.  Grids of
+ * more than 2^21 cells are refused (PIC_EINVAL).  Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (other threads or
+ * streams) race.  The array is cleared by a kernel at each call. */
+pic_status pic_continuity_noalloc(pic_ctx *ctx, int32_t species, double *resid, double *max_abs_j);
+
 /* FP64 diagnostics (host output): total charge, field energy, kinetic
  * energy, max |J| and the live particle count (pic_diag).  Section 3 names
  * grid heating among the numerical artefacts a predictive code must not

@@ -953,7 +953,9 @@ pic_status pic_init_grid(pic_ctx** out, const pic_grid_desc* desc, const pic_fie
     g.kill_hi = kKillMargin;
     g.dt = (float)desc->dt;
     pd_coefficients(desc, &c->pd);
-    hipError_t e = hipMemsetAsync(c->ws + L.acc, 0, 3 * (size_t)ncell * 8, c->stream);
+    void* scratch_ptr = nullptr;   // this GPU's allocation-free scratch, looked up once per device
+    hipError_t e = noalloc_scratch(&scratch_ptr);
+    if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.acc, 0, 3 * (size_t)ncell * 8, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.small, 0, sizeof(Small), c->stream);
     if (e != hipSuccess) {
         delete c;
@@ -1106,6 +1108,43 @@ pic_status pic_continuity(pic_ctx* c, int32_t s, double* resid, double* max_abs_
     unsigned int jm = 0;
     HIPCHK(c, hipMemcpyAsync(&cm, &sm->contmax, 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(&jm, &sm->jmax, 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double r;
+    memcpy(&r, &cm, 8);
+    float j;
+    memcpy(&j, &jm, 4);
+    if (resid) *resid = r;
+    if (max_abs_j) *max_abs_j = j;
+    return device_errors(c);
+}
+
+pic_status pic_continuity_noalloc(pic_ctx* c, int32_t s, double* resid, double* max_abs_j) {
+    PICCHK(check_species(c, s));
+    if (c->g.ncell > kNoAllocMaxCells)
+        return fail(c, PIC_EINVAL, "grid of %d cells exceeds the %d cells of the allocation-free continuity check",
+                    c->g.ncell, kNoAllocMaxCells);
+    Species& sp = c->sp[s];
+    if (!sp.prev_valid) return fail(c, PIC_ESTATE, "continuity needs a preceding gather_push and deposit");
+    void* base = nullptr;
+    HIPCHK(c, noalloc_scratch(&base));
+    NoAllocHead* head = reinterpret_cast<NoAllocHead*>(base);
+    double* rho = reinterpret_cast<double*>(reinterpret_cast<char*>(base) + kNoAllocRhoOffset);
+    // clear the head and this grid's density with a fill kernel (no memset node)
+    HIPCHK(c, launch_zero_u64(reinterpret_cast<unsigned long long*>(base),
+                              (int64_t)(kNoAllocRhoOffset / 8) + c->g.ncell, c->stream));
+    SpeciesDev d = dev_of(c, sp);
+    PrevDev pv = prev_of(c, sp);
+    Small* sm = small_of(c);
+    HIPCHK(c, launch_rho(c->g, d.cell, d.off, d.w, sp.user.q, 1.0, &sm->count[s], (int)sp.bound, rho, c->stream));
+    HIPCHK(c, launch_rho(c->g, pv.cell, pv.off, d.w, sp.user.q, -1.0, &sm->count[s], (int)sp.bound, rho, c->stream));
+    HIPCHK(c, launch_continuity(c->g, rho, c->f.J, c->desc.d[0] / c->desc.dt, c->desc.d[0] / c->desc.d[1],
+                                c->desc.d[0] / c->desc.d[2], &head->contmax, c->stream));
+    FieldPtrs f = fields_of(c);
+    HIPCHK(c, launch_diag_fields(c->g, f.E, f.B, c->f.J, 1.0, head->red, &head->jmax, c->stream));
+    unsigned long long cm = 0;
+    unsigned int jm = 0;
+    HIPCHK(c, hipMemcpyAsync(&cm, &head->contmax, 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(&jm, &head->jmax, 4, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     double r;
     memcpy(&r, &cm, 8);

@@ -208,6 +208,20 @@ hipError_t launch_diag_fields(const Geom& g, float* const E[3], float* const B[3
 // rho += sign * q w S S S (FP64 atomics) for positions (cell, off)
 hipError_t launch_rho(const Geom& g, const int* cell, float* const off[3], const float* w, double q, double sign,
                       const int* d_count, int max_count, double* rho, hipStream_t st);
+// Scratch of the allocation-free continuity check (pic_reduce.hip): the
+// device address of this GPU's fixed scratch array (looked up once per
+// device, with that device current).  Layout: NoAllocHead at offset 0, the
+// FP64 charge density (at most kNoAllocMaxCells cells) at kNoAllocRhoOffset.
+constexpr int kNoAllocMaxCells = 1 << 21;
+constexpr size_t kNoAllocRhoOffset = 256;
+struct NoAllocHead {
+    double red[4];
+    unsigned long long contmax;
+    unsigned int jmax;
+    unsigned int pad;
+};
+hipError_t noalloc_scratch(void** out);
+
 // max over nodes of |rho dx/dt + sum_d (dx/d_d)(J_d - J_d[-e_d])| as double bits
 // ry = dx/dy, rz = dx/dz
 hipError_t launch_continuity(const Geom& g, const double* rho, float* const J[3], double dx_dt, double ry,

@@ -1,6 +1,8 @@
 // FP64 global reductions: charge, kinetic and field energy, max |J|, and the
 // continuity residual of the last deposit (rho re-deposited in FP64 from the
 // stored FP32 positions).
+#include <mutex>
+
 #include "pic_internal.h"
 #include "pic_particle_ops.h"
 
@@ -168,6 +170,36 @@ hipError_t launch_continuity(const Geom& g, const double* rho, float* const J[3]
     hipLaunchKernelGGL(k_continuity, dim3(grid_for(g.ncell)), dim3(256), 0, st, g, rho, J[0], J[1], J[2], dx_dt, ry,
                        rz, maxbits);
     return hipGetLastError();
+}
+
+// ---- allocation-free continuity check --------------------------------------
+// The scratch of pic_continuity_noalloc: a fixed device array (one per GPU,
+// held until the process ends) instead of the caller's workspace.  Words
+// 0..31 hold the reduction results (see NoAllocHead), the FP64 charge
+// density follows at kNoAllocRhoOffset.
+static __device__ __align__(256) unsigned char scratch[kNoAllocRhoOffset + (size_t)kNoAllocMaxCells * 8];
+
+namespace {
+constexpr int kMaxDevices = 64;
+void* g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+}  // namespace
+
+hipError_t noalloc_scratch(void** out) {
+    *out = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 }  // namespace pic

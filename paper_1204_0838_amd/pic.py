@@ -106,6 +106,8 @@ _SIGS = {
                                         ctypes.POINTER(ctypes.c_int64)]),
     "pic_continuity": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_double)]),
+    "pic_continuity_noalloc": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                              ctypes.POINTER(ctypes.c_double)]),
     "pic_reduce": (ctypes.c_int, [_vp, ctypes.POINTER(Diag)]),
     "pic_sync": (ctypes.c_int, [_vp]),
     "pic_last_error": (ctypes.c_char_p, [_vp]),
@@ -372,6 +374,12 @@ class Simulation:
     def continuity(self, s=0):
         r, j = ctypes.c_double(), ctypes.c_double()
         self._check(lib().pic_continuity(self.handle, s, ctypes.byref(r), ctypes.byref(j)))
+        return r.value, j.value
+
+    def continuity_noalloc(self, s=0):
+        """pic_continuity through the library's fixed scratch (no workspace density buffer)."""
+        r, j = ctypes.c_double(), ctypes.c_double()
+        self._check(lib().pic_continuity_noalloc(self.handle, s, ctypes.byref(r), ctypes.byref(j)))
         return r.value, j.value
 
     def reduce(self):
