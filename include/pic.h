@@ -325,6 +325,73 @@ pic_status pic_set_window(pic_ctx *ctx, int64_t start_step);
  * (host outputs). */
 pic_status pic_window_state(pic_ctx *ctx, int64_t *shift, int32_t *origin);
 
+/* ---- Run diagnostics -----------------------------------------------------
+ *
+ * The quantities Section 3.2 reports for its runs, computed on the device in
+ * FP64 from the live state (synchronising calls; host outputs).  Positions
+ * are window coordinates (x from the window's trailing face); particles in
+ * the window's removal margins count as gone, as in pic_reduce.
+ */
+
+/* A field component (comp 0..5 = E_x, E_y, E_z, B_x, B_y, B_z) along x at
+ * the transverse point (yc, zc): host_line[i], i < n[0], is the value at
+ * window cell i of the component's staggered grid, bilinear in y and z
+ * between the four nearest nodes (periodic y, z).  With comp 0 on the laser
+ * axis this is the on-axis longitudinal field of Section 3.2, Fig. 1(a). */
+pic_status pic_axis_line(pic_ctx *ctx, int32_t comp, double yc, double zc, double *host_line);
+
+/* Length of the accelerating phase on the axis (yc, zc): the region inside
+ * the bubble where E_x < 0 (Section 3.2, Fig. 1(a)).  Going backward from
+ * the last E_x sample at or behind x_from (window coordinates, typically
+ * the laser centroid), samples with E_x >= 0 (the front of the bubble) are
+ * skipped; the accelerating phase is the run of negative samples that
+ * follows, its ends at the zero crossings interpolated linearly between
+ * samples (a run reaching past x_from ends there).  0 if there is none. */
+pic_status pic_accelerating_length(pic_ctx *ctx, double yc, double zc, double x_from, double *length);
+
+/* Charge spectrum of a species: the charge |q| w dV of its live particles
+ * binned by kinetic energy gamma - 1 (quantity 0, in m_e c^2) or by the
+ * longitudinal momentum u_x (quantity 1, in m_e c) over [lo, hi) in nbins
+ * equal bins (1..2048); particles outside the range are not counted
+ * (Section 3.2, Figs. 3-4; Section 3.3, momentum spectra).  host_charge:
+ * nbins doubles; host_count (may be NULL): nbins particle counts. */
+pic_status pic_spectrum(pic_ctx *ctx, int32_t species, int32_t quantity, double lo, double hi, int32_t nbins,
+                        double *host_charge, int64_t *host_count);
+
+/* Beam of the particles with u_x > ux_min: its charge, count, mean u_x and
+ * normalised transverse emittances in y and z (Section 3.2, Table 1):
+ * eps_N,i = [(<p_i^2> - <p_i>^2)(<r_i^2> - <r_i>^2) - (<p_i r_i> - <r_i><p_i>)^2]^(1/2)
+ * with p in m_e c and r in c/w_pe (so eps in c/w_pe), averages weighted by
+ * charge; also the centroid and spreads of r and p. */
+typedef struct {
+    double charge;
+    int64_t count;
+    double mean_ux;
+    double eps_ny, eps_nz;
+    double mean_r[2];   /* <y>, <z> */
+    double rms_r[2];    /* spread of y, z */
+    double rms_p[2];    /* spread of u_y, u_z */
+} pic_beam_diag;
+
+pic_status pic_beam_moments(pic_ctx *ctx, int32_t species, double ux_min, pic_beam_diag *out);
+
+/* The particles with u_x > ux_min, for the collection phase space of
+ * Section 3.2, Fig. 1(b), (c): their tags (from which the plasma loading
+ * gives the initial position), window x and u_x, in no particular order.
+ * Up to cap of them are written to host_id, host_x, host_ux; *n_selected
+ * receives how many qualify.  Uses the species' spare particle arrays as
+ * staging (free between steps). */
+pic_status pic_select_particles(pic_ctx *ctx, int32_t species, double ux_min, int64_t cap, int32_t *host_id,
+                                double *host_x, float *host_ux, int64_t *n_selected);
+
+/* Moments of the electromagnetic energy density e = (E^2 + B^2)/2 along x:
+ * host_out[0] = sum e dV, [1] = sum e x dV, [2] = sum e x^2 dV, each
+ * component at its own staggered x position in window coordinates.
+ * transverse_only != 0 uses E_y, E_z, B_y, B_z only (a pulse travelling
+ * along x).  [1]/[0] is the laser centroid, whose motion gives the pulse's
+ * group velocity (Section 3.3). */
+pic_status pic_field_moments(pic_ctx *ctx, int32_t transverse_only, double *host_out);
+
 /* ---- Checkpoint / resume ---------------------------------------------------
  *
  * A long laser-wakefield run (the paper's runs take 10^5 CPU-hours,

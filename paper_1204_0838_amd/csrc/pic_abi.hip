@@ -21,6 +21,9 @@ constexpr int kMaxSpecies = 8;
 constexpr size_t kAlign = 256;
 constexpr int kKillMargin = 3;   // window cells behind which particles are removed
 constexpr size_t kMaxLds = 160 * 1024;
+constexpr int kDiagBins = 2048;                                   // most spectrum bins
+constexpr size_t kDiagWords = 64;                                 // reduction words of the diagnostics
+constexpr size_t kDiagBytesFixed = (2 * kDiagBins + kDiagWords) * 8;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -51,7 +54,7 @@ Tiling tiling_of(const pic_grid_desc* d) {
 // species take consecutive sub-ranges of them.
 struct Layout {
     size_t acc, jtmp, rho, small, prev_cell, prev_off, alt_cell, alt_off, alt_u, alt_w, alt_id, sort_rank, hist,
-        sums, toff, toff_stride, dn_w, dn_h1, dn_h2, total;
+        sums, toff, toff_stride, dn_w, dn_h1, dn_h2, diag, total;
 };
 
 // small block: err flags, per-species counts, reduction results
@@ -141,6 +144,8 @@ Layout layout(const pic_grid_desc* d, int64_t maxp) {
     L.dn_w = take(dn ? (kDnW1 + kDnW2 + kDnW3) * 2 + kDnBias * 4 : 0);
     L.dn_h1 = take(dn ? (size_t)ncell * 64 : 0);
     L.dn_h2 = take(dn ? (size_t)ncell * 64 : 0);
+    // run diagnostics: spectrum bins (charge, count), reduction words, axis line
+    L.diag = take(kDiagBytesFixed + (size_t)d->n[0] * 8);
     L.total = o;
     return L;
 }
@@ -901,6 +906,32 @@ pic_status batch_one_step(pic_batch* b) {
 
 }  // namespace
 
+// helpers of the run diagnostics
+namespace {
+
+double* diag_words(pic_ctx* c) {
+    return reinterpret_cast<double*>(c->ws + c->L.diag) + 2 * kDiagBins;
+}
+
+// Bilinear weights of the transverse point (yc, zc) on component comp's grid.
+void axis_weights(const pic_ctx* c, int comp, double yc, double zc, int* j0, int* k0, double* ty, double* tz) {
+    static const double sy[6] = {0.0, 0.5, 0.0, 0.5, 0.0, 0.5};
+    static const double sz[6] = {0.0, 0.0, 0.5, 0.5, 0.5, 0.0};
+    const double gy = yc / c->desc.d[1] - sy[comp];
+    const double gz = zc / c->desc.d[2] - sz[comp];
+    const double fy = floor(gy), fz = floor(gz);
+    *ty = gy - fy;
+    *tz = gz - fz;
+    // periodic y, z: bring the base node into [0, n)
+    const long long jy = (long long)fy, kz = (long long)fz;
+    *j0 = (int)(((jy % c->g.n[1]) + c->g.n[1]) % c->g.n[1]);
+    *k0 = (int)(((kz % c->g.n[2]) + c->g.n[2]) % c->g.n[2]);
+}
+
+float* field_comp(pic_ctx* c, int comp) { return comp < 3 ? c->f.E[comp] : c->f.B[comp - 3]; }
+
+}  // namespace
+
 extern "C" {
 
 size_t pic_workspace_bytes(const pic_grid_desc* desc, int64_t max_particles) {
@@ -1042,6 +1073,10 @@ pic_status pic_step(pic_ctx* c, int32_t nsteps) {
     for (int32_t it = 0; it < nsteps; ++it) {
         for (int32_t s = 0; s < (int32_t)c->sp.size(); ++s) {
             Species& sp = c->sp[s];
+            if (sp.bound == 0) {            // no particle can exist: nothing to sort, push or deposit
+                sp.prev_valid = false;
+                continue;
+            }
             hipEvent_t t0, t1, t2;
             bool gather = false;
             if (!sp.sorted || c->step - sp.sort_step >= c->tl.sort_interval) {
@@ -1362,6 +1397,153 @@ pic_status pic_copy_in(pic_ctx* c, const void* host_blob, size_t bytes) {
     c->shift = h.shift;
     c->g.origin = h.origin;
     c->mid_step = false;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PIC_OK;
+}
+
+// ---- run diagnostics ---------------------------------------------------------
+
+
+pic_status pic_axis_line(pic_ctx* c, int32_t comp, double yc, double zc, double* host_line) {
+    if (!c || !host_line) return PIC_EINVAL;
+    if (comp < 0 || comp > 5) return fail(c, PIC_EINVAL, "field component %d outside 0..5", comp);
+    if (!isfinite(yc) || !isfinite(zc)) return fail(c, PIC_EINVAL, "non-finite axis position");
+    int j0, k0;
+    double ty, tz;
+    axis_weights(c, comp, yc, zc, &j0, &k0, &ty, &tz);
+    double* line = diag_words(c) + kDiagWords;
+    HIPCHK(c, launch_axis_line(c->g, field_comp(c, comp), j0, k0, ty, tz, line, c->stream));
+    HIPCHK(c, hipMemcpyAsync(host_line, line, (size_t)c->g.n[0] * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PIC_OK;
+}
+
+pic_status pic_accelerating_length(pic_ctx* c, double yc, double zc, double x_from, double* length) {
+    if (!c || !length) return PIC_EINVAL;
+    const int nx = c->g.n[0];
+    std::vector<double> line((size_t)nx);
+    PICCHK(pic_axis_line(c, 0, yc, zc, line.data()));
+    // E_x samples sit at (i + 1/2) dx in window coordinates
+    const double dx = c->desc.d[0];
+    auto xs = [&](int i) { return (i + 0.5) * dx; };
+    int i = (int)floor(x_from / dx - 0.5);
+    if (i >= nx) i = nx - 1;
+    *length = 0.0;
+    if (i < 0) return PIC_OK;
+    const int start = i;
+    while (i >= 0 && line[i] >= 0.0) --i;
+    if (i < 0) return PIC_OK;
+    const int hi = i;
+    while (i >= 0 && line[i] < 0.0) --i;
+    const int lo = i + 1;
+    auto crossing = [&](int a, int b) { return xs(a) + (xs(b) - xs(a)) * line[a] / (line[a] - line[b]); };
+    double front;
+    if (hi < start)
+        front = crossing(hi + 1, hi);
+    else
+        front = (hi + 1 >= nx || line[hi + 1] < 0.0) ? x_from : crossing(hi + 1, hi);
+    const double rear = lo >= 1 ? crossing(lo - 1, lo) : xs(lo);
+    *length = front - rear;
+    return PIC_OK;
+}
+
+pic_status pic_spectrum(pic_ctx* c, int32_t s, int32_t quantity, double lo, double hi, int32_t nbins,
+                        double* host_charge, int64_t* host_count) {
+    PICCHK(check_species(c, s));
+    if (!host_charge) return PIC_EINVAL;
+    if (quantity != 0 && quantity != 1) return fail(c, PIC_EINVAL, "spectrum quantity must be 0 (gamma-1) or 1 (u_x)");
+    if (nbins < 1 || nbins > kDiagBins) return fail(c, PIC_EINVAL, "spectrum bins outside 1..%d", kDiagBins);
+    if (!(hi > lo) || !isfinite(lo) || !isfinite(hi)) return fail(c, PIC_EINVAL, "spectrum range must have hi > lo");
+    double* charge = reinterpret_cast<double*>(c->ws + c->L.diag);
+    unsigned long long* count = reinterpret_cast<unsigned long long*>(charge + kDiagBins);
+    HIPCHK(c, launch_zero_u64(reinterpret_cast<unsigned long long*>(charge), 2 * kDiagBins, c->stream));
+    Species& sp = c->sp[s];
+    const double dv = c->desc.d[0] * c->desc.d[1] * c->desc.d[2];
+    HIPCHK(c, launch_spectrum(c->g, dev_of(c, sp), &small_of(c)->count[s], (int)sp.bound, quantity, lo, hi, nbins,
+                              fabs(sp.user.q) * dv, charge, count, c->stream));
+    HIPCHK(c, hipMemcpyAsync(host_charge, charge, (size_t)nbins * 8, hipMemcpyDeviceToHost, c->stream));
+    if (host_count) HIPCHK(c, hipMemcpyAsync(host_count, count, (size_t)nbins * 8, hipMemcpyDeviceToHost, c->stream));
+    return device_errors(c);
+}
+
+pic_status pic_beam_moments(pic_ctx* c, int32_t s, double ux_min, pic_beam_diag* out) {
+    PICCHK(check_species(c, s));
+    if (!out) return PIC_EINVAL;
+    double* sums = diag_words(c);
+    HIPCHK(c, launch_zero_u64(reinterpret_cast<unsigned long long*>(sums), 13, c->stream));
+    Species& sp = c->sp[s];
+    HIPCHK(c, launch_beam_moments(c->g, dev_of(c, sp), &small_of(c)->count[s], (int)sp.bound, ux_min, c->desc.d[1],
+                                  c->desc.d[2], sums, c->stream));
+    double h[13];
+    HIPCHK(c, hipMemcpyAsync(h, sums, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    PICCHK(device_errors(c));
+    const double dv = c->desc.d[0] * c->desc.d[1] * c->desc.d[2];
+    memset(out, 0, sizeof *out);
+    out->count = (int64_t)h[12];
+    out->charge = fabs(sp.user.q) * dv * h[0];
+    if (h[0] > 0.0) {
+        const double W = h[0];
+        out->mean_ux = h[1] / W;
+        double eps[2];
+        for (int a = 0; a < 2; ++a) {
+            const double* m = h + 2 + 5 * a;
+            const double mr = m[0] / W, mr2 = m[1] / W, mp = m[2] / W, mp2 = m[3] / W, mpr = m[4] / W;
+            const double var_p = mp2 - mp * mp, var_r = mr2 - mr * mr, cov = mpr - mr * mp;
+            const double v = var_p * var_r - cov * cov;
+            eps[a] = v > 0.0 ? sqrt(v) : 0.0;
+            out->mean_r[a] = mr;
+            out->rms_r[a] = var_r > 0.0 ? sqrt(var_r) : 0.0;
+            out->rms_p[a] = var_p > 0.0 ? sqrt(var_p) : 0.0;
+        }
+        out->eps_ny = eps[0];
+        out->eps_nz = eps[1];
+    }
+    return PIC_OK;
+}
+
+pic_status pic_select_particles(pic_ctx* c, int32_t s, double ux_min, int64_t cap, int32_t* host_id, double* host_x,
+                                float* host_ux, int64_t* n_selected) {
+    PICCHK(check_species(c, s));
+    if (cap < 0 || (cap > 0 && (!host_id || !host_x || !host_ux))) return PIC_EINVAL;
+    Species& sp = c->sp[s];
+    int* counter = reinterpret_cast<int*>(diag_words(c) + 16);
+    HIPCHK(c, launch_zero_u64(reinterpret_cast<unsigned long long*>(counter), 1, c->stream));
+    // staging: the species' spare particle arrays (free between steps)
+    const pic_species_bufs& o = sp.alt;
+    HIPCHK(c, launch_select(c->g, dev_of(c, sp), &small_of(c)->count[s], (int)sp.bound, ux_min, o.cell, o.off[0],
+                            o.u[0], o.id, counter, c->stream));
+    int nsel = 0;
+    HIPCHK(c, hipMemcpyAsync(&nsel, counter, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    PICCHK(device_errors(c));
+    if (n_selected) *n_selected = nsel;
+    const int64_t k = nsel < cap ? nsel : cap;
+    if (k > 0) {
+        std::vector<int32_t> cell((size_t)k);
+        std::vector<float> off((size_t)k);
+        HIPCHK(c, hipMemcpyAsync(cell.data(), o.cell, (size_t)k * 4, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(off.data(), o.off[0], (size_t)k * 4, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(host_ux, o.u[0], (size_t)k * 4, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(host_id, o.id, (size_t)k * 4, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        const int nx = c->g.n[0];
+        for (int64_t q = 0; q < k; ++q) {
+            int xw = cell[q] % nx;
+            if (c->g.window) xw = (xw - c->g.origin + nx) % nx;
+            host_x[q] = ((double)xw + (double)off[q]) * c->desc.d[0];
+        }
+    }
+    return PIC_OK;
+}
+
+pic_status pic_field_moments(pic_ctx* c, int32_t transverse_only, double* host_out) {
+    if (!c || !host_out) return PIC_EINVAL;
+    double* sums = diag_words(c) + 24;
+    HIPCHK(c, launch_zero_u64(reinterpret_cast<unsigned long long*>(sums), 3, c->stream));
+    const int mask = transverse_only ? 0x36 : 0x3f;   // E_y, E_z, B_y, B_z or all six
+    FieldPtrs f = fields_of(c);
+    HIPCHK(c, launch_field_moments(c->g, f.E, f.B, mask, c->desc.d[0], c->desc.d[0] * c->desc.d[1] * c->desc.d[2],
+                                   sums, c->stream));
+    HIPCHK(c, hipMemcpyAsync(host_out, sums, 3 * 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return PIC_OK;
 }

@@ -208,6 +208,20 @@ hipError_t launch_diag_fields(const Geom& g, float* const E[3], float* const B[3
 // rho += sign * q w S S S (FP64 atomics) for positions (cell, off)
 hipError_t launch_rho(const Geom& g, const int* cell, float* const off[3], const float* w, double q, double sign,
                       const int* d_count, int max_count, double* rho, hipStream_t st);
+// run diagnostics (pic_diag.hip)
+int diag_max_bins();
+hipError_t launch_axis_line(const Geom& g, const float* F, int j0, int k0, double ty, double tz, double* out,
+                            hipStream_t st);
+hipError_t launch_spectrum(const Geom& g, const SpeciesDev& s, const int* d_count, int max_count, int quantity,
+                           double lo, double hi, int nbins, double qdv, double* charge, unsigned long long* count,
+                           hipStream_t st);
+hipError_t launch_beam_moments(const Geom& g, const SpeciesDev& s, const int* d_count, int max_count, double ux_min,
+                               double dy, double dz, double* sums, hipStream_t st);
+hipError_t launch_select(const Geom& g, const SpeciesDev& s, const int* d_count, int max_count, double ux_min,
+                         int* ocell, float* ooff, float* oux, int* oid, int* counter, hipStream_t st);
+hipError_t launch_field_moments(const Geom& g, float* const E[3], float* const B[3], int mask, double dx, double dv,
+                                double* sums, hipStream_t st);
+
 // Scratch of the allocation-free continuity check (pic_reduce.hip): the
 // device address of this GPU's fixed scratch array (looked up once per
 // device, with that device current).  Layout: NoAllocHead at offset 0, the

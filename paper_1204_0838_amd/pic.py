@@ -73,6 +73,12 @@ class Profile(ctypes.Structure):
                 ("steps", ctypes.c_int64), ("sorts", ctypes.c_int64), ("tile_launches", ctypes.c_int64)]
 
 
+class BeamDiag(ctypes.Structure):
+    _fields_ = [("charge", ctypes.c_double), ("count", ctypes.c_int64), ("mean_ux", ctypes.c_double),
+                ("eps_ny", ctypes.c_double), ("eps_nz", ctypes.c_double), ("mean_r", ctypes.c_double * 2),
+                ("rms_r", ctypes.c_double * 2), ("rms_p", ctypes.c_double * 2)]
+
+
 class Tiling(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32 * 3), ("guard", ctypes.c_int32), ("threads", ctypes.c_int32),
                 ("interleave", ctypes.c_int32), ("sort_interval", ctypes.c_int32)]
@@ -81,6 +87,15 @@ class Tiling(ctypes.Structure):
 # every symbol the header declares, with its ctypes signature
 _SIGS = {
     "pic_set_tiling": (ctypes.c_int, [_vp, ctypes.POINTER(Tiling)]),
+    "pic_axis_line": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
+    "pic_accelerating_length": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
+    "pic_spectrum": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
+    "pic_beam_moments": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(BeamDiag)]),
+    "pic_select_particles": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int64,
+                                            ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
+                                            ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_int64)]),
+    "pic_field_moments": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
     "pic_checkpoint_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
     "pic_copy_out": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
     "pic_copy_in": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
@@ -386,6 +401,57 @@ class Simulation:
         d = Diag()
         self._check(lib().pic_reduce(self.handle, ctypes.byref(d)))
         return {k: getattr(d, k) for k, _ in Diag._fields_}
+
+    # ------------------------------------------------------------ run diagnostics
+    def axis_line(self, comp=0, yc=None, zc=None):
+        """Field component comp (0..5 = E_x..B_z) along x at (yc, zc) (default: the box's axis)."""
+        yc = self.n[1] * self.desc.d[1] / 2 if yc is None else yc
+        zc = self.n[2] * self.desc.d[2] / 2 if zc is None else zc
+        out = np.zeros(self.n[0])
+        self._check(lib().pic_axis_line(self.handle, int(comp), float(yc), float(zc),
+                                        out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def accelerating_length(self, x_from, yc=None, zc=None):
+        yc = self.n[1] * self.desc.d[1] / 2 if yc is None else yc
+        zc = self.n[2] * self.desc.d[2] / 2 if zc is None else zc
+        v = ctypes.c_double()
+        self._check(lib().pic_accelerating_length(self.handle, float(yc), float(zc), float(x_from), ctypes.byref(v)))
+        return v.value
+
+    def spectrum(self, s=0, quantity=0, lo=0.0, hi=1.0, nbins=64):
+        """(charge per bin, count per bin) over [lo, hi); quantity 0: gamma - 1, 1: u_x."""
+        charge = np.zeros(int(nbins))
+        count = np.zeros(int(nbins), dtype=np.int64)
+        self._check(lib().pic_spectrum(self.handle, s, int(quantity), float(lo), float(hi), int(nbins),
+                                       charge.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                       count.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        return charge, count
+
+    def beam_moments(self, s=0, ux_min=0.0):
+        d = BeamDiag()
+        self._check(lib().pic_beam_moments(self.handle, s, float(ux_min), ctypes.byref(d)))
+        return {"charge": d.charge, "count": d.count, "mean_ux": d.mean_ux, "eps_ny": d.eps_ny, "eps_nz": d.eps_nz,
+                "mean_r": tuple(d.mean_r), "rms_r": tuple(d.rms_r), "rms_p": tuple(d.rms_p)}
+
+    def select_particles(self, s=0, ux_min=0.0, cap=1 << 20):
+        """(ids, window x, u_x) of the particles with u_x > ux_min (at most cap), and how many qualify."""
+        ids = np.zeros(int(cap), dtype=np.int32)
+        x = np.zeros(int(cap))
+        ux = np.zeros(int(cap), dtype=np.float32)
+        n = ctypes.c_int64()
+        self._check(lib().pic_select_particles(self.handle, s, float(ux_min), int(cap),
+                                               ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                               x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                               ux.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(n)))
+        k = min(n.value, int(cap))
+        return ids[:k], x[:k], ux[:k], n.value
+
+    def field_moments(self, transverse_only=False):
+        out = np.zeros(3)
+        self._check(lib().pic_field_moments(self.handle, 1 if transverse_only else 0,
+                                            out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return tuple(out)
 
     # ------------------------------------------------------------ checkpoint
     def copy_out(self) -> bytes:
