@@ -16,7 +16,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
-_SRCS = (_SRC, os.path.join(_HERE, "denoise.c"))
+_SRCS = (_SRC, os.path.join(_HERE, "denoise.c"), os.path.join(_HERE, "circ.c"))
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 _dp = ctypes.POINTER(ctypes.c_double)
