@@ -158,6 +158,52 @@ _SIGS = {
     "pic_batch_destroy": (None, [_vp]),
 }
 
+class CircDesc(ctypes.Structure):
+    _fields_ = [("nz", ctypes.c_int32), ("nr", ctypes.c_int32), ("dz", ctypes.c_double), ("dr", ctypes.c_double),
+                ("dt", ctypes.c_double), ("window_period", ctypes.c_int32), ("sort_interval", ctypes.c_int32)]
+
+
+class CircFieldBufs(ctypes.Structure):
+    _fields_ = [("E", _vp * 9), ("B", _vp * 9), ("J", _vp * 9)]
+
+
+class CircLaser(ctypes.Structure):
+    _fields_ = [("a0", ctypes.c_double), ("omega0", ctypes.c_double), ("waist", ctypes.c_double),
+                ("fwhm", ctypes.c_double), ("t_peak", ctypes.c_double), ("t_end", ctypes.c_double),
+                ("src_z", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+
+
+class CircPlasma(ctypes.Structure):
+    _fields_ = [("z_start", ctypes.c_double), ("ramp", ctypes.c_double), ("n_plateau", ctypes.c_double),
+                ("ppc", ctypes.c_int32), ("r_cells", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+_SIGS.update({
+    "pic_circ_validate": (ctypes.c_int, [ctypes.POINTER(CircDesc), ctypes.c_char_p, ctypes.c_size_t]),
+    "pic_circ_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(CircDesc), ctypes.c_int64]),
+    "pic_circ_init": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(CircDesc), ctypes.POINTER(CircFieldBufs), _vp,
+                                     ctypes.c_size_t, ctypes.c_int64, _vp]),
+    "pic_circ_init_species": (ctypes.c_int, [_vp, ctypes.POINTER(SpeciesBufs), ctypes.c_int64,
+                                             ctypes.POINTER(ctypes.c_int32)]),
+    "pic_circ_gather_push": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "pic_circ_deposit": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "pic_circ_field_step": (ctypes.c_int, [_vp]),
+    "pic_circ_step": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "pic_circ_set_laser": (ctypes.c_int, [_vp, ctypes.POINTER(CircLaser)]),
+    "pic_circ_set_plasma": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(CircPlasma)]),
+    "pic_circ_inject_plasma": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "pic_circ_set_window": (ctypes.c_int, [_vp, ctypes.c_int64]),
+    "pic_circ_window_state": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]),
+    "pic_circ_species_view": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(SpeciesBufs),
+                                             ctypes.POINTER(ctypes.c_int64)]),
+    "pic_circ_reduce": (ctypes.c_int, [_vp, ctypes.POINTER(Diag)]),
+    "pic_circ_sync": (ctypes.c_int, [_vp]),
+    "pic_circ_profile_enable": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "pic_circ_profile_read": (ctypes.c_int, [_vp, ctypes.POINTER(Profile)]),
+    "pic_circ_last_error": (ctypes.c_char_p, [_vp]),
+    "pic_circ_destroy": (None, [_vp]),
+})
+
 _lib = None
 
 
