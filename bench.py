@@ -297,6 +297,120 @@ def bench_c4(args):
     print(json.dumps(out), flush=True)
 
 
+CIRC_CELL_BYTES = 18 * 4 + 9 * 8     # mode-field planes staged once, int64 current channels added once
+
+
+def cpu_baseline_c2(cfg, crop=(256, 64), steps=20):
+    """Cylindrical oracle gather+push+deposit on a crop of the C2 grid (one
+    thread): the C2 plasma over a 256x64 (z, r) crop, perturbed fields."""
+    import numpy as np
+
+    from oracle import circ as OC
+    from paper_1204_0838_amd import inputs
+
+    nz, nr = crop
+    g = OC.make_grid(nz, nr, cfg["dz"], cfg["dr"], cfg["dt"])
+    p = dict(cfg["plasma"])
+    P = OC.load(g, {k: p[k] for k in ("z_start", "ramp", "n_plateau", "ppc")}, 0, 0, nz - 2,
+                lambda c: inputs.uniform53(p["seed"], c), nr - 4)
+    x, w = P["x"], P["w"].astype(np.float64)
+    u = np.zeros_like(x)
+    rng = np.random.default_rng(0)
+    E = OC.zeros_field(g) + 0.05 * rng.standard_normal((2, 3, nr, nz))
+    B = OC.zeros_field(g)
+    t = 0.0
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        u, x1 = OC.push(g, x, u, E, B)
+        OC.deposit(g, x, x1, u, w)
+        t += time.perf_counter() - t0
+        x = x1
+    return {"value": x.shape[1] * steps / t, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"C2 geometry crop {nz}x{nr} (z, r) cells ({x.shape[1]} particles, 32 per cell, ramp region), "
+                      f"{steps} FP64 oracle steps of gather+push+deposit, single thread", "host": _host_cpu()}
+
+
+def bench_c2(args):
+    """C2: the quasi-cylindrical two-mode run, K timed steps spread over its
+    2000 steps (as for C1).  Roofline of the fused tile kernel: 60 B per
+    particle plus 144 B per (z, r) cell (18 mode-field planes read, 9 int64
+    current channels accumulated)."""
+    import torch
+
+    from paper_1204_0838_amd import workloads
+
+    cfg = workloads.C2
+    total = cfg["steps"]
+    args.steps = args.steps or total - args.warmup
+    t_setup = time.perf_counter()
+    sim = workloads.build_c2(cfg, sort_interval=args.sort_interval)
+    sim.sync()
+    idx = timed_indices(total, args.warmup, args.steps)
+    print(f"# setup {time.perf_counter() - t_setup:.1f}s, window from step {workloads.c2_window_start(cfg)}, "
+          f"{len(idx)} timed steps from {idx[0]} to {idx[-1]}", file=sys.stderr, flush=True)
+    st = sim.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    keys = ("sort_ms", "tile_ms", "loose_ms", "jpost_ms", "field_ms", "window_ms", "steps", "sorts", "tile_launches")
+    prof = {k: 0 for k in keys}
+    ms = part = 0.0
+    done = 0
+    last = time.perf_counter()
+    for j, i in enumerate(idx):
+        while done < i:
+            k = min(200, i - done)
+            sim.step(k)
+            done += k
+        sim.sync()
+        n_live = sim.reduce()["n_particles"]
+        sim.profile_enable(True)
+        torch.cuda.synchronize()
+        e0.record(st)
+        sim.step(1)
+        e1.record(st)
+        torch.cuda.synchronize()
+        done += 1
+        ms += e0.elapsed_time(e1)
+        p = sim.profile_read()
+        sim.profile_enable(False)
+        for k in keys:
+            prof[k] += p[k]
+        part += n_live
+        if time.perf_counter() - last > 20 or j + 1 == len(idx):
+            print(f"# {j + 1}/{len(idx)} timed steps (step {i})", file=sys.stderr, flush=True)
+            last = time.perf_counter()
+    K = len(idx)
+    npart = part / K
+    ncell = cfg["nz"] * cfg["nr"]
+    launches = max(1, prof["tile_launches"])
+    tile_ms = prof["tile_ms"] / launches
+    alg = 60.0 * npart + CIRC_CELL_BYTES * ncell
+    achieved = alg / (tile_ms * 1e-3) / 1e9
+    out = {
+        "metric": "particle-steps/s (gather+push+deposit), quasi-cylindrical m=0,1",
+        "value": part / (ms * 1e-3), "unit": "particle-steps/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": ms / K, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "C2 quasi-cylindrical two-mode run Nz=4096 Nr=256 dz=0.05 dr=0.2 c/wp, 32 ppc per "
+                               "(z,r) cell at random azimuth, C1 laser on mode 1 and C1 density profile, c dt = dz/2, "
+                               "window from step {}, {}-step run; {} timed steps spread over steps {}-{}".format(
+                                   workloads.c2_window_start(cfg), total, K, idx[0], idx[-1]),
+                   "timed_step_indices": idx if K <= 50 else "{}..{}".format(idx[0], idx[-1]),
+                   "particles": int(npart), "cells": ncell, "tile": [32, 8], "guard": 1,
+                   "sort_interval": sim.desc.sort_interval or 2},
+        "gather_push_deposit_particle_steps_per_s": part / ((prof["tile_ms"] + prof["loose_ms"]) * 1e-3),
+        "phase_ms_per_step": {k[:-3]: prof[k] / max(1, prof["steps"]) for k in keys[:6]},
+        "roofline": {"bound": "hbm", "kernel": "k_circ_tile", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None, "alg_bytes_per_launch": alg,
+                     "mean_launch_ms": tile_ms},
+        "cpu_baseline": None,
+    }
+    sim.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_c2(cfg)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -309,9 +423,9 @@ def main():
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-json", type=str, default="", help="per-launch HBM bytes from rocprofv3 counters")
-    ap.add_argument("--workload", type=str, default="c1", choices=["c1", "c3", "c4"],
-                    help="c1 (default): the LWFA slab; c3: the batched 64-member parameter scan; "
-                         "c4: the 2-ppc run with the learned denoiser")
+    ap.add_argument("--workload", type=str, default="c1", choices=["c1", "c2", "c3", "c4"],
+                    help="c1 (default): the LWFA slab; c2: the quasi-cylindrical two-mode run; c3: the batched "
+                         "64-member parameter scan; c4: the 2-ppc run with the learned denoiser")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 5 device copies of 1 GiB (reference for the FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
@@ -338,6 +452,9 @@ def main():
     if args.workload == "c4":
         args.steps = args.steps or 200
         bench_c4(args)
+        return
+    if args.workload == "c2":
+        bench_c2(args)
         return
     args.steps = args.steps or 1000 - args.warmup
 

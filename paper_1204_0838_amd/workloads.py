@@ -12,6 +12,12 @@ The paper resolves lambda0 with dx = 0.06 lambda0 (Section 3.1); keeping that
 resolution gives lambda0 = 4.17 c/w_p, i.e. omega0 = 1.508 w_p.  The window
 starts to move at c when the pulse peak reaches 64 cells from the front.
 
+C2 is the quasi-cylindrical counterpart (two azimuthal modes): Nz = 4096,
+Nr = 256, dz = 0.05, dr = 0.2 c/w_p, 32 particles per (z, r) cell at
+uniform random azimuth over the radial cells below 252, the C1 laser on
+mode 1 and the C1 density profile, c dt = dz / 2 (the window moves one cell
+every second step once the pulse has entered), 2000 steps.
+
 C3 is a parameter scan of 64 such setups of uneven size, advanced together
 by the batched launcher: instance i draws from seeded stream 3 + i its grid
 (nx uniform in 64..256, ny and nz in 32..64, each rounded to a multiple of
@@ -37,6 +43,45 @@ C1 = {
               "t_end": 20.0, "src_x": 2},
     "front_margin": 64,
 }
+
+
+C2 = {
+    "name": "C2",
+    "nz": 4096,
+    "nr": 256,
+    "dz": 0.05,
+    "dr": 0.2,
+    "dt": 0.025,
+    "window_period": 2,
+    "steps": 2000,
+    "plasma": {"z_start": 2.0, "ramp": 12.5, "n_plateau": 1.0, "ppc": 32, "r_cells": 252, "seed": 5},
+    "laser": {"a0": 4.0, "omega0": 2 * math.pi / (0.25 / 0.06), "waist": 5.0, "fwhm": 2.5, "t_peak": 10.0,
+              "t_end": 20.0, "src_z": 2},
+}
+
+
+def c2_window_start(cfg: dict) -> int:
+    """First step after which the C2 window moves: once the source is off."""
+    return int(math.ceil(cfg["laser"]["t_end"] / cfg["dt"] - 1e-9))
+
+
+def build_c2(cfg: dict = C2, capacity_factor: float = 1.05, device="cuda:0", sort_interval: int = 0):
+    """A CircSimulation holding the C2 workload at t = 0 (plasma loaded, laser and window set)."""
+    from .circ import CircSimulation
+
+    p = cfg["plasma"]
+    nz, nr = cfg["nz"], cfg["nr"]
+    shifts = (cfg["steps"] - c2_window_start(cfg)) // cfg["window_period"] + 1
+    cap = int(((nz - 2) * p["r_cells"] * p["ppc"]) * capacity_factor) + shifts * p["r_cells"] * p["ppc"]
+    sim = CircSimulation(nz, nr, cfg["dz"], cfg["dr"], cfg["dt"], window_period=cfg["window_period"],
+                         sort_interval=sort_interval, max_particles=cap, device=device)
+    sim.add_empty_species(cap)
+    sim.set_plasma(0, p["z_start"], p["ramp"], p["n_plateau"], p["ppc"], p["r_cells"], p["seed"])
+    sim.inject_plasma(0, 0, nz - 2)
+    L = cfg["laser"]
+    sim.set_laser(L["a0"], L["omega0"], L["waist"], L["fwhm"], L["t_peak"], L["t_end"], L["src_z"])
+    sim.set_window(c2_window_start(cfg))
+    return sim
 
 
 def scaled(cfg: dict, n) -> dict:

@@ -294,3 +294,29 @@ def _base_sigs():
             "ora_field_step_laser": (None, [G, dp, dp, dp, LP, ctypes.c_double]),
             "ora_pd_coeffs": (ctypes.c_int, [dp, ctypes.c_int, dp, dp, dp]),
             "ora_boris": (None, [dp, dp, dp, ctypes.c_double, ctypes.c_double])}
+
+
+def _energy_growth(nz, nr, dz, dr, dt, steps, seed=0):
+    g = C.make_grid(nz, nr, dz, dr, dt)
+    rng = np.random.default_rng(seed)
+    E = rng.standard_normal((2, 3, nr, nz)) + 1j * rng.standard_normal((2, 3, nr, nz))
+    B = rng.standard_normal((2, 3, nr, nz)) + 1j * rng.standard_normal((2, 3, nr, nz))
+    E[0], B[0] = E[0].real, B[0].real
+    E, B = np.ascontiguousarray(E), np.ascontiguousarray(B)
+    e0 = C.field_energy(g, E, B)
+    for _ in range(steps):
+        E, B = C.field_step(g, E, B)
+    return C.field_energy(g, E, B) / e0
+
+
+@pytest.mark.parametrize("dz,dr", [(0.05, 0.2), (0.2, 0.2), (0.2, 0.1)])
+def test_time_step_bound_keeps_random_fields_bounded(dz, dr):
+    """The descriptor's bound dt <= 0.95 / sqrt(1/dz^2 + 4/dr^2): random
+    fields of both modes stay bounded for 3000 steps at the bound, and the
+    same test does see a growth above the scheme's limit."""
+    bound = 0.95 / math.sqrt(1 / dz ** 2 + 4 / dr ** 2)
+    assert _energy_growth(16, 8, dz, dr, bound, 3000) < 1.5
+    if dz < dr:
+        over = 1.5 / math.sqrt(1 / dz ** 2 + 1 / dr ** 2)
+        ratio = _energy_growth(16, 8, dz, dr, over, 400)
+        assert not ratio < 100.0
