@@ -42,7 +42,7 @@ typedef struct {
     double d[3];      /* cell sizes */
     double dt;        /* time step */
     int32_t xbc;      /* 0: periodic in x; 1: zero ghost beyond both x edges */
-    int32_t pad_;
+    int32_t yzbc;     /* bit 0: zero beyond the y edges, bit 1: beyond the z edges (else periodic) */
     double alpha[3];  /* centre weights of S_x, S_y, S_z */
     double beta[3];   /* beta_x, beta_y, beta_z */
     double gam[3];    /* gamma_yz, gamma_zx, gamma_xy */
@@ -68,6 +68,8 @@ static double fld(const ora_grid *g, const double *F, int64_t i, int64_t j, int6
     } else {
         i = wrap(i, g->n[0]);
     }
+    if ((g->yzbc & 1) && (j < 0 || j >= g->n[1])) return 0.0;
+    if ((g->yzbc & 2) && (k < 0 || k >= g->n[2])) return 0.0;
     j = wrap(j, g->n[1]);
     k = wrap(k, g->n[2]);
     return F[i + g->n[0] * (j + g->n[1] * k)];
@@ -80,6 +82,8 @@ static int64_t node(const ora_grid *g, int64_t i, int64_t j, int64_t k) {
     } else {
         i = wrap(i, g->n[0]);
     }
+    if ((g->yzbc & 1) && (j < 0 || j >= g->n[1])) return -1;
+    if ((g->yzbc & 2) && (k < 0 || k >= g->n[2])) return -1;
     j = wrap(j, g->n[1]);
     k = wrap(k, g->n[2]);
     return i + g->n[0] * (j + g->n[1] * k);
@@ -509,6 +513,122 @@ int ora_step(const ora_grid *g, int64_t np, double *x, double *u, const double *
 }
 
 /* ------------------------------------------------------------------ */
+/* transverse perfectly matched layer                                  */
+
+/* Section 3.1 surrounds its Cartesian domain transversely with a 16-layer
+ * perfectly matched layer.  The paper gives no formulation; this is the
+ * convolutional form (stretched coordinates d/dy -> d/dy / s_y with
+ * s_y = 1 + sigma_y / (i omega), kappa = 1, no frequency shift): every
+ * transverse derivative term D_d F of a curl carries an auxiliary psi that
+ * follows psi <- b psi + (b - 1) D_d F with b = exp(-sigma_d h) for an
+ * update of time increment h, and the curl uses D_d F + psi.
+ *
+ * Grading: at position p (in cells, integer for nodes, half-integer for
+ * face centres) along an axis of n cells with a layer of L cells,
+ * depth = max((L - 1 - p) / L, (p - (n - L)) / L), clipped to [0, 1] (the
+ * profile is symmetric under p -> n - 1 - p, zero on nodes L-1 .. n-L), and
+ * sigma = sigma_max depth^grade.  Zero fields lie beyond the outer faces
+ * (grid yzbc bits).  In normalised units (c = eps0 = 1, impedance 1)
+ * sigma_max = 0.8 (grade + 1) / d is the usual choice; grade 3. */
+typedef struct {
+    int64_t layers;
+    double sigma_max[3];   /* per axis; index 0 unused (no layer along x) */
+    double grade;          /* exponent of the profile (0: constant sigma_max over the layer) */
+} ora_pml;
+
+/* sigma at position p (in cells) along axis a of n cells */
+static double pml_sigma(const ora_pml *P, int a, int64_t n, double p) {
+    double L = (double)P->layers;
+    double lo = (L - 1.0 - p) / L, hi = (p - ((double)n - L)) / L;
+    double depth = lo > hi ? lo : hi;
+    if (!(depth > 0.0)) return 0.0;
+    if (depth > 1.0) depth = 1.0;
+    return P->sigma_max[a] * pow(depth, P->grade);
+}
+
+/* psi update and stretched derivative: returns D + psi' with psi' = b psi + (b - 1) D */
+static double stretch(double *psi, double D, double sigma, double h) {
+    double b = exp(-sigma * h);
+    *psi = b * (*psi) + (b - 1.0) * D;
+    return D + *psi;
+}
+
+/* Stretched derivative D + psi' with psi' = b psi + (b - 1) D, b = exp(-sigma dt);
+ * psi' is written back when `store` is set. */
+static double stretch_b(double *psi, double D, double sigma, double dt, int store) {
+    double b = exp(-sigma * dt);
+    double p = b * (*psi) + (b - 1.0) * D;
+    if (store) *psi = p;
+    return D + p;
+}
+
+/* B -= (dt/2) curl' E with the layer's stretched transverse derivatives.
+ * The two half steps of B together are the leapfrog step B^{n-1/2} ->
+ * B^{n+1/2} = B^{n-1/2} - dt curl' E^n, so the auxiliary arrays of B follow
+ * the leapfrog recursion at the half-integer times: the first half step of a
+ * step advances them with E^n (store = 1) and the second uses, without
+ * storing, the value that the next step's first half step will store (the
+ * same E^{n+1}).  psi[0..3]: B_x by y, B_x by z, B_y by z, B_z by y (each
+ * ncell); the derivatives sit at the half-integer position of their axis. */
+static void b_half_pml(const ora_grid *g, const ora_pml *P, const double *E, double *B, double *psi, int store) {
+    int64_t nc = ncell(g);
+    double h = 0.5 * g->dt;
+    double *tmp = (double *)malloc(sizeof(double) * 3 * nc);
+    const double *Ex = E, *Ey = E + nc, *Ez = E + 2 * nc;
+    for (int64_t k = 0; k < g->n[2]; ++k)
+        for (int64_t j = 0; j < g->n[1]; ++j)
+            for (int64_t i = 0; i < g->n[0]; ++i) {
+                int64_t f = i + g->n[0] * (j + g->n[1] * k);
+                double sy = pml_sigma(P, 1, g->n[1], (double)j + 0.5), sz = pml_sigma(P, 2, g->n[2], (double)k + 0.5);
+                double dyEz = stretch_b(psi + f, dsmooth(g, Ez, 1, i, j, k), sy, g->dt, store);
+                double dzEy = stretch_b(psi + nc + f, dsmooth(g, Ey, 2, i, j, k), sz, g->dt, store);
+                double dzEx = stretch_b(psi + 2 * nc + f, dsmooth(g, Ex, 2, i, j, k), sz, g->dt, store);
+                double dyEx = stretch_b(psi + 3 * nc + f, dsmooth(g, Ex, 1, i, j, k), sy, g->dt, store);
+                tmp[f] = dyEz - dzEy;
+                tmp[nc + f] = dzEx - dsmooth(g, Ez, 0, i, j, k);
+                tmp[2 * nc + f] = dsmooth(g, Ey, 0, i, j, k) - dyEx;
+            }
+    for (int64_t f = 0; f < 3 * nc; ++f) B[f] -= h * tmp[f];
+    free(tmp);
+}
+
+/* E += dt (curl B - J) with the layer's stretched transverse derivatives.
+ * psi[0..3]: E_x by y, E_x by z, E_y by z, E_z by y; the derivatives of E's
+ * update sit on the integer position of their axis. */
+static void e_full_pml(const ora_grid *g, const ora_pml *P, double *E, const double *B, const double *J, double *psi) {
+    int64_t nc = ncell(g);
+    double *tmp = (double *)malloc(sizeof(double) * 3 * nc);
+    const double *Bx = B, *By = B + nc, *Bz = B + 2 * nc;
+    for (int64_t k = 0; k < g->n[2]; ++k)
+        for (int64_t j = 0; j < g->n[1]; ++j)
+            for (int64_t i = 0; i < g->n[0]; ++i) {
+                int64_t f = i + g->n[0] * (j + g->n[1] * k);
+                double sy = pml_sigma(P, 1, g->n[1], (double)j), sz = pml_sigma(P, 2, g->n[2], (double)k);
+                double dyBz = stretch(psi + f, dback(g, Bz, 1, i, j, k), sy, g->dt);
+                double dzBy = stretch(psi + nc + f, dback(g, By, 2, i, j, k), sz, g->dt);
+                double dzBx = stretch(psi + 2 * nc + f, dback(g, Bx, 2, i, j, k), sz, g->dt);
+                double dyBx = stretch(psi + 3 * nc + f, dback(g, Bx, 1, i, j, k), sy, g->dt);
+                tmp[f] = dyBz - dzBy;
+                tmp[nc + f] = dzBx - dback(g, Bz, 0, i, j, k);
+                tmp[2 * nc + f] = dback(g, By, 0, i, j, k) - dyBx;
+            }
+    for (int64_t f = 0; f < 3 * nc; ++f) E[f] += g->dt * (tmp[f] - (J ? J[f] : 0.0));
+    free(tmp);
+}
+
+/* One field step with the transverse layer: psi holds 8 ncell arrays, the
+ * four of the B updates then the four of the E update, carried from step
+ * to step (zero at the start). */
+void ora_pml_field_step(const ora_grid *g, const ora_pml *P, double *E, double *B, const double *J, double *psi) {
+    int64_t nc = ncell(g);
+    b_half_pml(g, P, E, B, psi, 1);
+    e_full_pml(g, P, E, B, J, psi + 4 * nc);
+    b_half_pml(g, P, E, B, psi, 0);
+}
+
+double ora_pml_sigma(const ora_pml *P, int a, int64_t n, double p) { return pml_sigma(P, a, n, p); }
+
+/* ------------------------------------------------------------------ */
 /* laser-wakefield boundaries: laser source, moving window, plasma     */
 
 /* Linearly polarised (E along y) Gaussian pulse entering through the plane
@@ -576,6 +696,35 @@ void ora_field_step_laser(const ora_grid *g, double *E, double *B, const double 
     if (L) ora_laser_e_correction(g, L, E, t + 0.5 * g->dt);
     b_half(g, E, B, 0.5 * g->dt);
     if (L) ora_laser_b_correction(g, L, B, 0.5 * g->dt, t + g->dt);
+}
+
+/* The same with the transverse layer (P, psi as ora_pml_field_step). */
+void ora_field_step_laser_pml(const ora_grid *g, double *E, double *B, const double *J, const ora_laser *L,
+                              double t, const ora_pml *P, double *psi) {
+    int64_t nc = ncell(g);
+    b_half_pml(g, P, E, B, psi, 1);
+    if (L) ora_laser_b_correction(g, L, B, 0.5 * g->dt, t);
+    e_full_pml(g, P, E, B, J, psi + 4 * nc);
+    if (L) ora_laser_e_correction(g, L, E, t + 0.5 * g->dt);
+    b_half_pml(g, P, E, B, psi, 0);
+    if (L) ora_laser_b_correction(g, L, B, 0.5 * g->dt, t + g->dt);
+}
+
+/* One array of ncell values moves one cell toward -x; the new leading plane is zero. */
+static void shift_down_x(const ora_grid *g, double *F) {
+    int64_t nx = g->n[0];
+    for (int64_t k = 0; k < g->n[2]; ++k)
+        for (int64_t j = 0; j < g->n[1]; ++j) {
+            double *row = F + nx * (j + g->n[1] * k);
+            for (int64_t i = 0; i + 1 < nx; ++i) row[i] = row[i + 1];
+            row[nx - 1] = 0.0;
+        }
+}
+
+/* The layer's eight auxiliary arrays move with the window like the fields. */
+void ora_pml_window_shift(const ora_grid *g, double *psi) {
+    int64_t nc = ncell(g);
+    for (int a = 0; a < 8; ++a) shift_down_x(g, psi + a * nc);
 }
 
 /* Moving window, one cell: every field moves one cell toward -x (the plane

@@ -26,7 +26,7 @@ _i32p = ctypes.POINTER(ctypes.c_int32)
 
 class OraGrid(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64 * 3), ("d", ctypes.c_double * 3), ("dt", ctypes.c_double),
-                ("xbc", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("xbc", ctypes.c_int32), ("yzbc", ctypes.c_int32),
                 ("alpha", ctypes.c_double * 3), ("beta", ctypes.c_double * 3), ("gam", ctypes.c_double * 3)]
 
 
@@ -101,8 +101,9 @@ def pd_coeffs(d, variant: int = 0):
     return a, b, g
 
 
-def make_grid(n, d, dt, solver: str = "yee", xbc: int = 0, variant: int = 0, coeffs=None) -> OraGrid:
+def make_grid(n, d, dt, solver: str = "yee", xbc: int = 0, variant: int = 0, coeffs=None, yzbc: int = 0) -> OraGrid:
     g = OraGrid()
+    g.yzbc = int(yzbc)
     for a in range(3):
         g.n[a] = int(n[a])
         g.d[a] = float(d[a])
@@ -300,7 +301,7 @@ def inject(g: OraGrid, P: OraPlasma, shift: int, xb: int, xe: int):
 
 
 def run_lwfa(g: OraGrid, P: OraPlasma, L: OraLaser, nsteps: int, window_start: int, kill_lo: int = 3,
-             inject_hi: int = 3, jpost: int = 0, q=-1.0, m=1.0):
+             inject_hi: int = 3, jpost: int = 0, q=-1.0, m=1.0, pml=None):
     """Moving-window laser-wakefield run in window coordinates (c = 1, c dt = dx).
 
     Start: vacuum fields, plasma loaded over window cells [0, nx - inject_hi).
@@ -310,15 +311,35 @@ def run_lwfa(g: OraGrid, P: OraPlasma, L: OraLaser, nsteps: int, window_start: i
     plane is cleared and the plasma of the newly covered lab cell is loaded
     at window cell nx - 1 - inject_hi).  After every step particles outside
     window cells [kill_lo, nx - 1 - inject_hi] are removed (their shapes
-    would reach past the window's ends).  Returns dict(x, u, w, id, E, B, J, shift).
+    would reach past the window's ends).
+
+    pml (an OraPml, grid with both yzbc bits): the transverse layer in the
+    field update, its auxiliary arrays moving with the window, and particles
+    whose transverse cell lies in the layer are removed with the others
+    (also right after loading, i.e. before they ever move).
+    Returns dict(x, u, w, id, E, B, J, shift).
     """
     nx = int(g.n[0])
     x, w, ids = inject(g, P, 0, 0, nx - inject_hi)
     u = np.zeros_like(x)
     E = zeros_field(g)
     B = zeros_field(g)
+    psi = zeros_psi(g) if pml is not None else None
     shift = 0
     J = zeros_field(g)
+
+    def kept(x):
+        k = (x[0] >= kill_lo * g.d[0]) & (x[0] < (nx - inject_hi) * g.d[0])
+        if pml is not None:
+            lay = int(pml.layers)
+            for a in (1, 2):
+                c = np.floor(x[a] / g.d[a])
+                k &= (c >= lay) & (c < int(g.n[a]) - lay)
+        return k
+
+    if pml is not None:
+        keep = kept(x)
+        x, u, w, ids = x[:, keep], u[:, keep], w[keep], ids[keep]
     for n in range(nsteps):
         t = n * g.dt
         x0 = x.copy()
@@ -326,10 +347,16 @@ def run_lwfa(g: OraGrid, P: OraPlasma, L: OraLaser, nsteps: int, window_start: i
         J = deposit(g, x0, x1, w, q)
         if jpost == 1:
             J = binomial(g, J)
-        E, B = field_step_laser(g, E, B, J, L if (shift == 0 and t <= L.t_end) else None, t)
+        Ln = L if (shift == 0 and t <= L.t_end) else None
+        if pml is not None:
+            E, B, psi = field_step_laser_pml(g, E, B, J, Ln, t, pml, psi)
+        else:
+            E, B = field_step_laser(g, E, B, J, Ln, t)
         x = xw
         if n + 1 >= window_start:
             E, B = window_shift(g, E, B)
+            if pml is not None:
+                psi = pml_window_shift(g, psi)
             shift += 1
             x[0] -= g.d[0]
             xn, wn, idn = inject(g, P, shift, nx - 1 - inject_hi, nx - inject_hi)
@@ -337,9 +364,68 @@ def run_lwfa(g: OraGrid, P: OraPlasma, L: OraLaser, nsteps: int, window_start: i
             u = np.concatenate([u, np.zeros_like(xn)], axis=1)
             w = np.concatenate([w, wn])
             ids = np.concatenate([ids, idn])
-        keep = (x[0] >= kill_lo * g.d[0]) & (x[0] < (nx - inject_hi) * g.d[0])
+        keep = kept(x)
         x, u, w, ids = x[:, keep], u[:, keep], w[keep], ids[keep]
-    return {"x": x, "u": u, "w": w, "id": ids, "E": E, "B": B, "J": J, "shift": shift}
+    return {"x": x, "u": u, "w": w, "id": ids, "E": E, "B": B, "J": J, "shift": shift, "psi": psi}
+
+
+class OraPml(ctypes.Structure):
+    _fields_ = [("layers", ctypes.c_int64), ("sigma_max", ctypes.c_double * 3), ("grade", ctypes.c_double)]
+
+
+def make_pml(g: OraGrid, layers: int = 16, sigma_max=None, grade: float = 3.0, axes=(1, 2)) -> OraPml:
+    """Transverse layer of `layers` cells on the given axes; sigma_max per
+    axis (default 0.8 (grade + 1) / d), profile sigma_max depth^grade."""
+    P = OraPml()
+    P.layers = int(layers)
+    P.grade = float(grade)
+    for a in axes:
+        P.sigma_max[a] = float(sigma_max if sigma_max is not None else 0.8 * (grade + 1.0) / g.d[a])
+    return P
+
+
+def _pml_sigs():
+    L = lib()
+    G, PP, LP = ctypes.POINTER(OraGrid), ctypes.POINTER(OraPml), ctypes.POINTER(OraLaser)
+    for name, (res, args) in {"ora_pml_field_step": (None, [G, PP, _dp, _dp, _dp, _dp]),
+                              "ora_pml_sigma": (ctypes.c_double, [PP, ctypes.c_int, ctypes.c_int64, ctypes.c_double]),
+                              "ora_field_step_laser_pml": (None, [G, _dp, _dp, _dp, LP, ctypes.c_double, PP, _dp]),
+                              "ora_pml_window_shift": (None, [G, _dp]),
+                              }.items():
+        f = getattr(L, name)
+        f.restype, f.argtypes = res, args
+    return L
+
+
+def zeros_psi(g: OraGrid) -> np.ndarray:
+    return np.zeros((8,) + _fshape(g)[1:])
+
+
+def pml_field_step(g: OraGrid, P: OraPml, E, B, psi, J=None):
+    """One field step with the transverse layer; returns (E, B, psi) (copies)."""
+    E, B, psi = f64(E).copy(), f64(B).copy(), f64(psi).copy()
+    Jp = _p(f64(J)) if J is not None else None
+    _pml_sigs().ora_pml_field_step(ctypes.byref(g), ctypes.byref(P), _p(E), _p(B), Jp, _p(psi))
+    return E, B, psi
+
+
+def pml_sigma(P: OraPml, axis: int, n: int, p: float) -> float:
+    return _pml_sigs().ora_pml_sigma(ctypes.byref(P), int(axis), int(n), float(p))
+
+
+def field_step_laser_pml(g: OraGrid, E, B, J, L, t: float, P: OraPml, psi):
+    """field_step_laser with the transverse layer; returns (E, B, psi) (copies)."""
+    E, B, psi = f64(E).copy(), f64(B).copy(), f64(psi).copy()
+    Jp = _p(f64(J)) if J is not None else None
+    Lp = ctypes.byref(L) if L is not None else None
+    _pml_sigs().ora_field_step_laser_pml(ctypes.byref(g), _p(E), _p(B), Jp, Lp, float(t), ctypes.byref(P), _p(psi))
+    return E, B, psi
+
+
+def pml_window_shift(g: OraGrid, psi):
+    psi = f64(psi).copy()
+    _pml_sigs().ora_pml_window_shift(ctypes.byref(g), _p(psi))
+    return psi
 
 
 def step(g: OraGrid, x, u, w, E, B, q=-1.0, m=1.0, jpost: int = 0):

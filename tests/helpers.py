@@ -1,4 +1,9 @@
-"""Shared helpers of the parity tests (layout conversions and error norms only)."""
+"""Shared helpers of the tests: layout conversions, error norms, and copies
+of the oracle with one planted mistake (for checking that a pin catches it)."""
+import importlib.util
+import os
+import shutil
+
 import numpy as np
 
 
@@ -26,3 +31,26 @@ def periodic_delta(x1, x0, L):
 def by_id(ids, *arrays):
     order = np.argsort(ids, kind="stable")
     return [a[..., order] for a in arrays]
+
+
+def oracle_mutant(tmp_path, name, c_edit=None, py_edit=None):
+    """A copy of the oracle package with one edit (old, new) in oracle.c
+    and/or oracle.py, built and imported as a separate module."""
+    from oracle import oracle as O
+
+    src_dir = os.path.dirname(O.__file__)
+    d = tmp_path / name
+    d.mkdir()
+    for f in ("oracle.c", "denoise.c", "circ.c", "oracle.py"):
+        shutil.copy(os.path.join(src_dir, f), d / f)
+    for fname, edit in (("oracle.c", c_edit), ("oracle.py", py_edit)):
+        if edit:
+            src = (d / fname).read_text()
+            old, new = edit
+            assert src.count(old) == 1, (fname, old)
+            (d / fname).write_text(src.replace(old, new))
+    spec = importlib.util.spec_from_file_location(f"oracle_mutant_{name}", d / "oracle.py")
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    mod.build(force=True)
+    return mod

@@ -14,17 +14,13 @@ dropped cell volume, gamma in place of gamma - 1, the plasma injected one
 cell off, ...), built on the CPU from edited sources; every planted
 mistake must make the pin fail.
 """
-import importlib.util
 import math
-import os
-import shutil
 
 import numpy as np
 import pytest
 
 from oracle import oracle as O
-
-ORACLE_DIR = os.path.dirname(O.__file__)
+from tests.helpers import oracle_mutant
 
 
 # ---------------------------------------------------------------- ora_diag
@@ -137,22 +133,7 @@ def test_run_lwfa_window_keeps_a_vacuum_pulse_in_place():
 
 # ---------------------------------------------------------------- planted mistakes
 def _mutant(tmp_path, name, c_edit=None, py_edit=None):
-    """A copy of the oracle package with one edit, as a separate module."""
-    d = tmp_path / name
-    d.mkdir()
-    for f in ("oracle.c", "denoise.c", "oracle.py"):
-        shutil.copy(os.path.join(ORACLE_DIR, f), d / f)
-    for fname, edit in (("oracle.c", c_edit), ("oracle.py", py_edit)):
-        if edit:
-            src = (d / fname).read_text()
-            old, new = edit
-            assert src.count(old) == 1, (fname, old)
-            (d / fname).write_text(src.replace(old, new))
-    spec = importlib.util.spec_from_file_location(f"oracle_mutant_{name}", d / "oracle.py")
-    mod = importlib.util.module_from_spec(spec)
-    spec.loader.exec_module(mod)
-    mod.build(force=True)
-    return mod
+    return oracle_mutant(tmp_path, name, c_edit, py_edit)
 
 
 MUTANTS = [
@@ -168,7 +149,7 @@ MUTANTS = [
     ("window_inject_one_cell_ahead", pin_window_cold_plasma, None,
      ("inject(g, P, shift, nx - 1 - inject_hi, nx - inject_hi)", "inject(g, P, shift, nx - inject_hi, nx + 1 - inject_hi)")),
     ("window_kill_margin_short", pin_window_cold_plasma, None,
-     ("keep = (x[0] >= kill_lo * g.d[0])", "keep = (x[0] >= (kill_lo - 1) * g.d[0])")),
+     ("k = (x[0] >= kill_lo * g.d[0])", "k = (x[0] >= (kill_lo - 1) * g.d[0])")),
     ("window_particles_not_shifted", pin_window_cold_plasma, None, ("            x[0] -= g.d[0]\n", "")),
     ("window_inject_lab_cell_off", pin_window_cold_plasma, None,
      ("inject(g, P, shift, nx - 1 - inject_hi, nx - inject_hi)",
