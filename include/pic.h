@@ -325,6 +325,41 @@ pic_status pic_set_window(pic_ctx *ctx, int64_t start_step);
  * (host outputs). */
 pic_status pic_window_state(pic_ctx *ctx, int64_t *shift, int32_t *origin);
 
+/* ---- Transverse absorbing layer --------------------------------------------
+ *
+ * Section 3.1 surrounds its Cartesian box transversely with a 16-layer
+ * perfectly matched layer.  With a layer set, y and z are no longer
+ * periodic: the `layers` outermost cells at each y and z edge form the
+ * layer, fields beyond the outer faces are zero, and every transverse
+ * derivative D of the curls inside the layer is stretched in the
+ * convolutional form (D -> D + psi, psi <- b psi + (b - 1) D,
+ * b = exp(-sigma dt), no frequency shift, unit kappa).  Grading: at
+ * position p in cells (integer for nodes, half-integer for face centres)
+ * along an axis of n cells, depth = max((L - 1 - p) / L, (p - (n - L)) / L)
+ * clipped to [0, 1] and sigma = sigma_max depth^grade (zero on nodes
+ * L - 1 .. n - L).  The B arrays advance once per step, at the first B half
+ * step, as the leapfrog recursion of B between half-integer times.
+ * Particles whose transverse cell lies in the layer are removed at the
+ * start of the next step (like the window's kill zones; pic_reduce and the
+ * diagnostics no longer count them).  The auxiliary arrays move with the
+ * window and are part of the checkpoint blob. */
+typedef struct {
+    int32_t layers;         /* L: cells per edge, 8 <= L, 2 L + 1 <= n[1], n[2]; 0 removes the layer */
+    int32_t pad_;
+    double sigma_max[2];    /* y, z in w_pe (<= 0: 0.8 (grade + 1) / d, the usual optimum) */
+    double grade;           /* profile exponent (<= 0: 3) */
+} pic_pml_desc;
+
+/* Device bytes the layer's arrays need (pure host; 0 for an invalid descriptor). */
+size_t pic_pml_bytes(const pic_grid_desc *desc, const pic_pml_desc *pml);
+
+/* Set (or with layers = 0 remove) the layer.  buffer: caller-owned device
+ * memory of at least pic_pml_bytes, 256-byte aligned, kept until the
+ * context is destroyed or the layer removed; zeroed here (the layer starts
+ * empty).  Not with the batched launcher (pic_batch_create rejects such a
+ * context).  Synchronises. */
+pic_status pic_set_pml(pic_ctx *ctx, const pic_pml_desc *pml, void *buffer, size_t bytes);
+
 /* ---- Run diagnostics -----------------------------------------------------
  *
  * The quantities Section 3.2 reports for its runs, computed on the device in
@@ -407,8 +442,10 @@ pic_status pic_field_moments(pic_ctx *ctx, int32_t transverse_only, double *host
  * current is summed in an order-independent fixed-point accumulator and
  * the cell sort changes no result.
  * Layout (host byte order): a header, then E[3], B[3], J[3] as
- * n[0]*n[1]*n[2] floats each, then for each species its count entries of
- * cell, off[0..2], u[0..2], w, id (4 bytes per value, array by array). */
+ * n[0]*n[1]*n[2] floats each, with a transverse absorbing layer its
+ * auxiliary arrays (pic_pml_bytes minus the coefficient table), then for
+ * each species its count entries of cell, off[0..2], u[0..2], w, id (4
+ * bytes per value, array by array). */
 
 /* Bytes pic_copy_out needs for the current state (host output).
  * Synchronises the stream and reports device errors. */
@@ -420,7 +457,7 @@ pic_status pic_checkpoint_bytes(pic_ctx *ctx, size_t *bytes);
 pic_status pic_copy_out(pic_ctx *ctx, void *host_blob, size_t bytes);
 
 /* Restore a state written by pic_copy_out into a context with the same grid
- * (n, d, dt, solver, x boundary) and species count (PIC_EINVAL otherwise;
+ * (n, d, dt, solver, x boundary, absorbing layer thickness) and species count (PIC_EINVAL otherwise;
  * PIC_ENOMEM when a species' capacity is below its stored count).  The
  * caller's species arrays receive the particles; every species is re-sorted
  * at its next pic_step.  Synchronises. */

@@ -263,6 +263,11 @@ struct pic_ctx {
     Prof prof;
     // a split-path step is in progress (pic_gather_push since the last pic_field_step)
     bool mid_step = false;
+    // transverse absorbing layer (pic_set_pml); g.pml holds its thickness
+    pic_pml_desc pml_desc{};
+    PmlDev pml{};
+    char* pml_buf = nullptr;
+    size_t pml_state_bytes = 0;   // the auxiliary arrays (checkpointed), after the coefficient table
 };
 
 namespace {
@@ -446,11 +451,12 @@ pic_status field_update(pic_ctx* c, float* const Juse[3]) {
     const int pd = c->desc.solver == PIC_SOLVER_PD;
     const double dt = c->desc.dt, t = c->step * dt;
     const bool laser = c->has_laser && c->shift == 0 && t <= c->laser.t_end;
-    HIPCHK(c, launch_bhalf(c->g, pd, c->pd, f.E, f.B, (float)(0.5 * dt), c->stream));
+    const PmlDev* pml = c->g.pml ? &c->pml : nullptr;
+    HIPCHK(c, launch_bhalf(c->g, pd, c->pd, f.E, f.B, (float)(0.5 * dt), pml, 1, c->stream));
     if (laser) PICCHK(laser_plane(c, false, 0.5 * dt, t));
-    HIPCHK(c, launch_efull(c->g, f.E, f.B, Juse, c->stream));
+    HIPCHK(c, launch_efull(c->g, f.E, f.B, Juse, pml, c->stream));
     if (laser) PICCHK(laser_plane(c, true, dt, t + 0.5 * dt));
-    HIPCHK(c, launch_bhalf(c->g, pd, c->pd, f.E, f.B, (float)(0.5 * dt), c->stream));
+    HIPCHK(c, launch_bhalf(c->g, pd, c->pd, f.E, f.B, (float)(0.5 * dt), pml, 0, c->stream));
     if (laser) PICCHK(laser_plane(c, false, 0.5 * dt, t + dt));
     return PIC_OK;
 }
@@ -499,6 +505,7 @@ pic_status end_step(pic_ctx* c) {
     hipEvent_t t0;
     PICCHK(prof_mark(c, &t0));
     HIPCHK(c, launch_clear_plane(c->g, fields_of(c), c->g.origin, c->stream));
+    if (c->g.pml) HIPCHK(c, launch_clear_pml_plane(c->g, c->pml, c->g.origin, c->stream));
     c->g.origin = c->g.origin + 1 == c->g.n[0] ? 0 : c->g.origin + 1;
     c->shift += 1;
     const int slab = c->g.n[0] - 1 - c->g.kill_hi;
@@ -582,11 +589,48 @@ pic_status finish_step(pic_ctx* c) {
 }
 
 
+// ---- transverse absorbing layer -----------------------------------------------
+// Buffer: the coefficient table (16 L floats), then y[0..3] (n[0] 2L n[2]
+// floats each), then z[0..3] (n[0] n[1] 2L each), every part 256-byte aligned.
+struct PmlLayout {
+    size_t coef, y[4], z[4], total;
+};
+
+bool pml_layout(const pic_grid_desc* d, const pic_pml_desc* p, PmlLayout* out) {
+    if (!d || !p || validate(d, nullptr, 0) != PIC_OK) return false;
+    const int L = p->layers;
+    if (L < 8 || 2 * L + 1 > d->n[1] || 2 * L + 1 > d->n[2]) return false;
+    auto up = [](size_t b) { return (b + kAlign - 1) / kAlign * kAlign; };
+    size_t o = 0;
+    out->coef = o;
+    o += up((size_t)16 * L * 4);
+    const size_t ny = (size_t)d->n[0] * 2 * L * d->n[2] * 4, nz = (size_t)d->n[0] * d->n[1] * 2 * L * 4;
+    for (int a = 0; a < 4; ++a) {
+        out->y[a] = o;
+        o += up(ny);
+    }
+    for (int a = 0; a < 4; ++a) {
+        out->z[a] = o;
+        o += up(nz);
+    }
+    out->total = o;
+    return true;
+}
+
+// sigma at position p (cells) along an axis of n cells with a layer of L cells
+double pml_sigma_at(double smax, double grade, int L, int n, double p) {
+    const double lo = (L - 1.0 - p) / L, hi = (p - (double)(n - L)) / L;
+    double depth = std::max(lo, hi);
+    if (!(depth > 0.0)) return 0.0;
+    depth = std::min(depth, 1.0);
+    return smax * pow(depth, grade);
+}
+
 // ---- checkpoint blob ---------------------------------------------------------
 // header, then E[3], B[3], J[3] (ncell floats each), then per species its
 // `count` particles as cell, off[3], u[3], w, id arrays (4 bytes per value).
 constexpr uint64_t kCkptMagic = 0x4b43353533434950ull;   // "PIC355CK" little-endian
-constexpr uint32_t kCkptVersion = 1;
+constexpr uint32_t kCkptVersion = 2;
 
 struct CkptHeader {
     uint64_t magic;
@@ -595,6 +639,8 @@ struct CkptHeader {
     int32_t n[3];
     int32_t origin;
     int32_t solver, bc_x;
+    int32_t pml_layers;
+    int32_t pad_;
     double d[3];
     double dt;
     int64_t step;
@@ -605,7 +651,7 @@ struct CkptHeader {
 constexpr int kCkptArrays = 9;   // cell, off[3], u[3], w, id
 
 size_t ckpt_bytes(const pic_ctx* c, const int64_t* count) {
-    size_t b = sizeof(CkptHeader) + 9 * (size_t)c->g.ncell * 4;
+    size_t b = sizeof(CkptHeader) + 9 * (size_t)c->g.ncell * 4 + (c->g.pml ? c->pml_state_bytes : 0);
     for (size_t s = 0; s < c->sp.size(); ++s) b += (size_t)count[s] * 4 * kCkptArrays;
     return b;
 }
@@ -1290,6 +1336,70 @@ pic_status pic_window_state(pic_ctx* c, int64_t* shift, int32_t* origin) {
     return PIC_OK;
 }
 
+size_t pic_pml_bytes(const pic_grid_desc* desc, const pic_pml_desc* pml) {
+    PmlLayout L;
+    return pml_layout(desc, pml, &L) ? L.total : 0;
+}
+
+pic_status pic_set_pml(pic_ctx* c, const pic_pml_desc* p, void* buffer, size_t bytes) {
+    if (!c || !p) return PIC_EINVAL;
+    if (c->mid_step) return fail(c, PIC_ESTATE, "absorbing layer changed inside a split-path step");
+    if (p->layers == 0) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        c->g.pml = 0;
+        c->pml = PmlDev{};
+        c->pml_buf = nullptr;
+        c->pml_state_bytes = 0;
+        return PIC_OK;
+    }
+    PmlLayout L;
+    if (!pml_layout(&c->desc, p, &L))
+        return fail(c, PIC_EINVAL, "absorbing layer of %d cells: need 8 <= layers and 2 layers + 1 <= n[1], n[2]",
+                    p->layers);
+    if (!buffer || (reinterpret_cast<uintptr_t>(buffer) & (kAlign - 1)) != 0)
+        return fail(c, PIC_EINVAL, "absorbing layer buffer null or not 256-byte aligned");
+    if (bytes < L.total) return fail(c, PIC_ENOMEM, "absorbing layer needs %zu bytes, buffer has %zu", L.total, bytes);
+    const double grade = p->grade > 0.0 ? p->grade : 3.0;
+    double smax[2];
+    for (int a = 0; a < 2; ++a) {
+        smax[a] = p->sigma_max[a] > 0.0 ? p->sigma_max[a] : 0.8 * (grade + 1.0) / c->desc.d[1 + a];
+        if (!isfinite(smax[a]) || !isfinite(grade) || grade > 16.0)
+            return fail(c, PIC_EINVAL, "invalid absorbing layer conductivity or grade");
+    }
+    // coefficient table: [axis][kind][b, b - 1][2L] (see PmlDev)
+    const int Ly = p->layers, L2 = 2 * Ly;
+    std::vector<float> coef((size_t)16 * Ly);
+    for (int axis = 0; axis < 2; ++axis) {
+        const int n = c->desc.n[1 + axis];
+        for (int kind = 0; kind < 2; ++kind)
+            for (int l = 0; l < L2; ++l) {
+                const int j = l < Ly ? l : n - L2 + l;
+                const double pos = kind == 0 ? j + 0.5 : (double)j;
+                const double sdt = pml_sigma_at(smax[axis], grade, Ly, n, pos) * c->desc.dt;
+                coef[(size_t)((axis * 2 + kind) * 2 + 0) * L2 + l] = (float)exp(-sdt);
+                coef[(size_t)((axis * 2 + kind) * 2 + 1) * L2 + l] = (float)expm1(-sdt);
+            }
+    }
+    char* base = reinterpret_cast<char*>(buffer);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemsetAsync(base, 0, L.total, c->stream));
+    HIPCHK(c, hipMemcpyAsync(base + L.coef, coef.data(), coef.size() * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->pml_desc = *p;
+    c->pml.coef = reinterpret_cast<const float*>(base + L.coef);
+    for (int a = 0; a < 4; ++a) {
+        c->pml.y[a] = reinterpret_cast<float*>(base + L.y[a]);
+        c->pml.z[a] = reinterpret_cast<float*>(base + L.z[a]);
+    }
+    c->pml.L = Ly;
+    c->pml_buf = base;
+    c->pml_state_bytes = L.total - L.y[0];
+    c->g.pml = Ly;
+    // species are re-sorted at their next step (the sort drops the layer's particles)
+    for (auto& sp : c->sp) sp.sorted = false;
+    return PIC_OK;
+}
+
 pic_status pic_checkpoint_bytes(pic_ctx* c, size_t* bytes) {
     if (!c || !bytes) return PIC_EINVAL;
     int64_t count[kMaxSpecies] = {};
@@ -1317,6 +1427,7 @@ pic_status pic_copy_out(pic_ctx* c, void* host_blob, size_t bytes) {
     h.origin = c->g.origin;
     h.solver = c->desc.solver;
     h.bc_x = c->desc.bc_x;
+    h.pml_layers = c->g.pml;
     h.dt = c->desc.dt;
     h.step = c->step;
     h.shift = c->shift;
@@ -1331,6 +1442,10 @@ pic_status pic_copy_out(pic_ctx* c, void* host_blob, size_t bytes) {
             HIPCHK(c, hipMemcpyAsync(p, F[k][a], fbytes, hipMemcpyDeviceToHost, c->stream));
             p += fbytes;
         }
+    if (c->g.pml) {
+        HIPCHK(c, hipMemcpyAsync(p, c->pml.y[0], c->pml_state_bytes, hipMemcpyDeviceToHost, c->stream));
+        p += c->pml_state_bytes;
+    }
     for (size_t s = 0; s < c->sp.size(); ++s) {
         void* arr[kCkptArrays];
         ckpt_arrays(c->sp[s].cur, arr);
@@ -1355,6 +1470,9 @@ pic_status pic_copy_in(pic_ctx* c, const void* host_blob, size_t bytes) {
             return fail(c, PIC_EINVAL, "checkpoint grid differs from the context's");
     if (h.dt != c->desc.dt || h.solver != c->desc.solver || h.bc_x != c->desc.bc_x)
         return fail(c, PIC_EINVAL, "checkpoint time step, solver or x boundary differs from the context's");
+    if (h.pml_layers != c->g.pml)
+        return fail(c, PIC_EINVAL, "checkpoint absorbing layer (%d cells) differs from the context's (%d)", h.pml_layers,
+                    c->g.pml);
     if (h.nspecies != c->sp.size()) return fail(c, PIC_EINVAL, "checkpoint has %u species, context %zu", h.nspecies,
                                                 c->sp.size());
     if (h.origin < 0 || h.origin >= c->g.n[0] || h.step < 0 || h.shift < 0 || (!c->g.window && (h.shift || h.origin)))
@@ -1373,6 +1491,10 @@ pic_status pic_copy_in(pic_ctx* c, const void* host_blob, size_t bytes) {
             HIPCHK(c, hipMemcpyAsync(F[k][a], p, fbytes, hipMemcpyHostToDevice, c->stream));
             p += fbytes;
         }
+    if (c->g.pml) {
+        HIPCHK(c, hipMemcpyAsync(c->pml.y[0], p, c->pml_state_bytes, hipMemcpyHostToDevice, c->stream));
+        p += c->pml_state_bytes;
+    }
     Small* sm = small_of(c);
     for (size_t s = 0; s < c->sp.size(); ++s) {
         Species& sp = c->sp[s];
@@ -1662,6 +1784,7 @@ pic_status pic_batch_create(pic_batch** out, pic_ctx* const* members, int32_t n,
         if (!members[i]) return PIC_EINVAL;
         if (members[i]->stream != st) return PIC_EINVAL;
         if (members[i]->sp.empty() || members[i]->sp.size() != members[0]->sp.size()) return PIC_EINVAL;
+        if (members[i]->g.pml) return PIC_EINVAL;   // the batched field kernels have no absorbing layer
         for (int32_t k = 0; k < i; ++k)
             if (members[k] == members[i]) return PIC_EINVAL;
     }
@@ -1693,9 +1816,11 @@ pic_status pic_batch_create(pic_batch** out, pic_ctx* const* members, int32_t n,
 
 pic_status pic_batch_step(pic_batch* b, int32_t nsteps) {
     if (!b || nsteps < 0) return PIC_EINVAL;
-    for (pic_ctx* c : b->m)
+    for (pic_ctx* c : b->m) {
         if (c->desc.jpost == PIC_JPOST_DENOISER)
             return bfail(b, PIC_EINVAL, "the batch runs the plain and binomial current paths only");
+        if (c->g.pml) return bfail(b, PIC_EINVAL, "the batch runs periodic transverse boundaries only");
+    }
     for (int32_t it = 0; it < nsteps; ++it) PICCHK(batch_one_step(b));
     return PIC_OK;
 }

@@ -26,6 +26,8 @@ struct Geom {
     int origin;    // storage x index of window cell 0
     int kill_lo;   // window mode: particles in window cells < kill_lo are removed
     int kill_hi;   // window mode: particles in window cells > n[0] - 1 - kill_hi are removed
+    int pml;       // transverse absorbing layer of pml cells at each y and z edge (0: y, z periodic);
+                   // particles in its cells are removed
     float dt;
     float dtd[3];  // dt / d  (converts velocity to cells per step)
     float inv_d[3];

@@ -26,10 +26,13 @@ __device__ __forceinline__ int window_x(const Geom& g, int i) {
     return xw < 0 ? xw + g.n[0] : xw;
 }
 
-// A live particle: valid cell, not in a window kill zone (removed at the next step).
+// A live particle: valid cell, not in a window kill zone or the transverse
+// absorbing layer (removed at the next step).
 __device__ __forceinline__ bool live_cell(const Geom& g, int cl) {
     if ((unsigned)cl >= (unsigned)g.ncell) return false;
-    return !(g.window && window_killed(g, cl % g.n[0]));
+    int c[3];
+    decompose(g, cl, c);
+    return !particle_killed(g, c);
 }
 
 __global__ void __launch_bounds__(256) k_axis_line(Geom g, const float* __restrict__ F, int j0, int k0, double ty,

@@ -14,6 +14,27 @@ struct FieldPtrs {
     float* B[3];
 };
 
+// Transverse absorbing layer of L cells at each y and z edge: the auxiliary
+// arrays of the convolutional form, each over the cells of its layer only,
+// in storage x order (they move with the window like the fields).
+//   y[0..3]: B_x by y, B_z by y, E_x by y, E_z by y; index i + nx (l + 2L k)
+//   z[0..3]: B_x by z, B_y by z, E_x by z, E_y by z; index i + nx (j + ny l)
+// l in [0, 2L) is the layer index of a cell: j for j < L, j - (n - 2L) for
+// j >= n - L.  coef[((axis * 2 + kind) * 2 + which) * 2L + l]: axis 0 = y,
+// 1 = z; kind 0 = the B updates (derivatives at l's half-integer position),
+// 1 = the E update (integer position); which 0 = b = exp(-sigma dt),
+// 1 = b - 1.
+struct PmlDev {
+    float* y[4];
+    float* z[4];
+    const float* coef;
+    int L;
+};
+
+__host__ __device__ inline int pml_index(int j, int n, int L) {
+    return j < L ? j : (j >= n - L ? j - (n - 2 * L) : -1);
+}
+
 // plasma profile (see pic_plasma_desc)
 struct PlasmaDev {
     double x_start, ramp, n_plateau;
@@ -191,9 +212,13 @@ hipError_t launch_tile_rest(const Geom& g, const FieldPtrs& f, const SpeciesDev&
                             int* d_err, hipStream_t st);
 
 // field kernels (pic_fields.hip)
+// pml: nullptr without the absorbing layer; store: the first of a step's two
+// B half steps advances the layer's B arrays, the second only reads them.
 hipError_t launch_bhalf(const Geom& g, int pd, const PDCoef& c, float* const E[3], float* const B[3], float h,
+                        const PmlDev* pml, int store, hipStream_t st);
+hipError_t launch_efull(const Geom& g, float* const E[3], float* const B[3], float* const J[3], const PmlDev* pml,
                         hipStream_t st);
-hipError_t launch_efull(const Geom& g, float* const E[3], float* const B[3], float* const J[3], hipStream_t st);
+hipError_t launch_clear_pml_plane(const Geom& g, const PmlDev& P, int ix, hipStream_t st);
 hipError_t launch_binomial(const Geom& g, float* const src[3], float* const dst[3], hipStream_t st);
 hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t st);
 

@@ -24,6 +24,14 @@ __device__ __forceinline__ bool window_killed(const Geom& g, int cx) {
     return xw < g.kill_lo || xw > g.n[0] - 1 - g.kill_hi;
 }
 
+// Removed at the start of a step: in a window kill zone, or in a transverse
+// cell of the absorbing layer.
+__device__ __forceinline__ bool particle_killed(const Geom& g, const int c[3]) {
+    if (window_killed(g, c[0])) return true;
+    if (g.pml == 0) return false;
+    return c[1] < g.pml || c[1] >= g.n[1] - g.pml || c[2] < g.pml || c[2] >= g.n[2] - g.pml;
+}
+
 // Shift between two cell indices along a periodic axis, mapped to (-n/2, n/2].
 __device__ __forceinline__ int unwrap_shift(int di, int n) {
     if (di > n / 2) di -= n;

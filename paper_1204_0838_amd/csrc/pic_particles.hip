@@ -22,7 +22,7 @@ __global__ void __launch_bounds__(256) k_gather_push(Geom g, FieldPtrs f, Specie
     float off[3] = {s.off[0][p], s.off[1][p], s.off[2][p]};
 #pragma unroll
     for (int d = 0; d < 3; ++d) prev.off[d][p] = off[d];
-    if (window_killed(g, c[0])) {
+    if (particle_killed(g, c)) {
         s.cell[p] = -1;
         prev.cell[p] = -1;
         return;

@@ -37,7 +37,9 @@ __global__ void __launch_bounds__(256) k_diag_particles(Geom g, const int* __res
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
         const int cl = cell[p];
         if ((unsigned)cl >= (unsigned)g.ncell) continue;
-        if (g.window && window_killed(g, cl % g.n[0])) continue;   // removed at the next step
+        int cc[3];
+        decompose(g, cl, cc);
+        if (particle_killed(g, cc)) continue;   // removed at the next step
         const double a = ux[p], b = uy[p], c = uz[p];
         const double u2 = a * a + b * b + c * c;
         q += qdv * (double)w[p];

@@ -56,7 +56,7 @@ __device__ __forceinline__ int sort_key(const Geom& g, const TileGeom& t, const 
     if ((unsigned)cl >= (unsigned)g.ncell) return -1;
     int c[3];
     cell_coords(g, sd, cl, c);
-    if (window_killed(g, c[0])) return -1;
+    if (particle_killed(g, c)) return -1;
     return tile_key(t, sd, c);
 }
 

@@ -258,7 +258,7 @@ __device__ __forceinline__ void tile_body(const Geom& g, const TileGeom& t, int 
         }
         int c[3];
         decompose(g, cell, c);
-        if (window_killed(g, c[0])) {
+        if (particle_killed(g, c)) {
             s.cell[p] = -1;
             keep_particle<GATHER>(s, p, o, u);
             continue;
@@ -401,7 +401,7 @@ __device__ __forceinline__ void rest_item(const Geom& g, const FieldPtrs& f, con
         const int cell = s.cell[p];
         if ((unsigned)cell >= (unsigned)g.ncell) return;
         decompose(g, cell, c);
-        if (window_killed(g, c[0])) {
+        if (particle_killed(g, c)) {
             s.cell[p] = -1;
             return;
         }

@@ -79,6 +79,11 @@ class BeamDiag(ctypes.Structure):
                 ("rms_r", ctypes.c_double * 2), ("rms_p", ctypes.c_double * 2)]
 
 
+class PmlDesc(ctypes.Structure):
+    _fields_ = [("layers", ctypes.c_int32), ("pad_", ctypes.c_int32), ("sigma_max", ctypes.c_double * 2),
+                ("grade", ctypes.c_double)]
+
+
 class Tiling(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32 * 3), ("guard", ctypes.c_int32), ("threads", ctypes.c_int32),
                 ("interleave", ctypes.c_int32), ("sort_interval", ctypes.c_int32)]
@@ -87,6 +92,8 @@ class Tiling(ctypes.Structure):
 # every symbol the header declares, with its ctypes signature
 _SIGS = {
     "pic_set_tiling": (ctypes.c_int, [_vp, ctypes.POINTER(Tiling)]),
+    "pic_pml_bytes": (ctypes.c_size_t, [ctypes.POINTER(GridDesc), ctypes.POINTER(PmlDesc)]),
+    "pic_set_pml": (ctypes.c_int, [_vp, ctypes.POINTER(PmlDesc), _vp, ctypes.c_size_t]),
     "pic_axis_line": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
     "pic_accelerating_length": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
     "pic_spectrum": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
@@ -371,6 +378,25 @@ class Simulation:
 
     def set_window(self, start_step):
         self._check(lib().pic_set_window(self.handle, int(start_step)))
+
+    def set_pml(self, layers=16, sigma_max=(0.0, 0.0), grade=0.0):
+        """Transverse absorbing layer of `layers` cells (0 removes it); its
+        device buffer is owned by this object.  sigma_max <= 0 and grade <= 0
+        select the library's defaults."""
+        P = PmlDesc(int(layers), 0)
+        P.sigma_max[0], P.sigma_max[1] = float(sigma_max[0]), float(sigma_max[1])
+        P.grade = float(grade)
+        if int(layers) == 0:
+            self._check(lib().pic_set_pml(self.handle, ctypes.byref(P), None, 0))
+            self.pml_buffer = None
+            return
+        nbytes = int(lib().pic_pml_bytes(ctypes.byref(self.desc), ctypes.byref(P)))
+        if nbytes == 0:
+            raise PicError(PIC_EINVAL, f"invalid absorbing layer of {layers} cells for this grid")
+        buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = (buf.data_ptr() + 255) // 256 * 256
+        self._check(lib().pic_set_pml(self.handle, ctypes.byref(P), ctypes.c_void_p(base), nbytes))
+        self.pml_buffer = buf
 
     def window_state(self):
         sh, org = ctypes.c_int64(), ctypes.c_int32()

@@ -1,5 +1,6 @@
 """Host-side checks of the C ABI: the library loads without a GPU, exports every
 symbol include/pic.h declares, and validates descriptors (no GPU calls)."""
+import ctypes
 import os
 import re
 
@@ -78,3 +79,21 @@ def test_workspace_size_grows_with_particles_and_rejects_invalid():
     b = pic.workspace_bytes(d, 100000)
     assert 0 < a < b
     assert pic.workspace_bytes(_desc(dt=1.0), 10) == 0
+
+
+def test_absorbing_layer_size_and_limits():
+    d = _desc(n=(64, 48, 40))
+
+    def nbytes(layers):
+        return int(pic.lib().pic_pml_bytes(ctypes.byref(d), ctypes.byref(pic.PmlDesc(layers, 0))))
+
+    # coefficient table (16 L floats) and four arrays per transverse axis over
+    # the 2 L layer cells, each part rounded up to 256 bytes
+    up = lambda b: (b + 255) // 256 * 256
+    L = 16
+    want = up(16 * L * 4) + 4 * up(64 * 2 * L * 40 * 4) + 4 * up(64 * 48 * 2 * L * 4)
+    assert nbytes(L) == want
+    assert nbytes(7) == 0                      # too thin for the particle margin
+    assert nbytes(20) == 0                     # 2 L + 1 > n[2] = 40
+    assert nbytes(19) > 0
+    assert int(pic.lib().pic_pml_bytes(ctypes.byref(_desc(dt=1.0)), ctypes.byref(pic.PmlDesc(8, 0)))) == 0
