@@ -343,7 +343,7 @@ def bench_c2(args):
     total = cfg["steps"]
     args.steps = args.steps or total - args.warmup
     t_setup = time.perf_counter()
-    sim = workloads.build_c2(cfg, sort_interval=args.sort_interval)
+    sim = workloads.build_c2(cfg, sort_interval=args.sort_interval, interleave=args.interleave)
     sim.sync()
     idx = timed_indices(total, args.warmup, args.steps)
     print(f"# setup {time.perf_counter() - t_setup:.1f}s, window from step {workloads.c2_window_start(cfg)}, "
@@ -397,7 +397,7 @@ def bench_c2(args):
                                    workloads.c2_window_start(cfg), total, K, idx[0], idx[-1]),
                    "timed_step_indices": idx if K <= 50 else "{}..{}".format(idx[0], idx[-1]),
                    "particles": int(npart), "cells": ncell, "tile": [32, 8], "guard": 1,
-                   "sort_interval": sim.desc.sort_interval or 2},
+                   "sort_interval": sim.desc.sort_interval or 2, "interleave": sim.desc.interleave or 32},
         "gather_push_deposit_particle_steps_per_s": part / ((prof["tile_ms"] + prof["loose_ms"]) * 1e-3),
         "phase_ms_per_step": {k[:-3]: prof[k] / max(1, prof["steps"]) for k in keys[:6]},
         "roofline": {"bound": "hbm", "kernel": "k_circ_tile", "achieved": achieved, "peak": HBM_PEAK_GBS,
@@ -421,11 +421,13 @@ def main():
     ap.add_argument("--sort-interval", type=int, default=0)
     ap.add_argument("--guard", type=int, default=-1)
     ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--interleave", type=int, default=0, help="sort transpose depth (default: tuned / library)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-json", type=str, default="", help="per-launch HBM bytes from rocprofv3 counters")
-    ap.add_argument("--workload", type=str, default="c1", choices=["c1", "c2", "c3", "c4"],
-                    help="c1 (default): the LWFA slab; c2: the quasi-cylindrical two-mode run; c3: the batched "
-                         "64-member parameter scan; c4: the 2-ppc run with the learned denoiser")
+    ap.add_argument("--workload", type=str, default="c1", choices=["c1", "c1p", "c2", "c3", "c4"],
+                    help="c1 (default): the LWFA slab; c1p: the same inside a 16-cell transverse PML; c2: the "
+                         "quasi-cylindrical two-mode run; c3: the batched 64-member parameter scan; c4: the 2-ppc "
+                         "run with the learned denoiser")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 5 device copies of 1 GiB (reference for the FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
@@ -472,7 +474,7 @@ def bench_c1(args):
 
     from paper_1204_0838_amd import workloads
 
-    cfg = workloads.C1
+    cfg = workloads.C1P if args.workload == "c1p" else workloads.C1
     if args.grid:
         cfg = workloads.scaled(cfg, [int(v) for v in args.grid.split(",")])
     total = cfg["steps"]
@@ -488,6 +490,8 @@ def bench_c1(args):
         tiling["guard"] = args.guard
     if args.threads:
         tiling["threads"] = args.threads
+    if args.interleave:
+        tiling["interleave"] = args.interleave
     t_setup = time.perf_counter()
     sim = workloads.build(cfg, **tiling)
     sim.sync()
@@ -553,11 +557,13 @@ def bench_c1(args):
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "C1 3D LWFA moving-window slab {}x{}x{}, dx=0.25 dy=dz=0.5 c/wp, perfect-dispersion "
+            "workload": "{} 3D LWFA moving-window slab {}x{}x{}{}, dx=0.25 dy=dz=0.5 c/wp, perfect-dispersion "
                         "solver c dt = dx, 8 ppc cold lattice plasma behind a 50-cell ramp, a0=4 w0=5 "
                         "FWHM 2.5 laser from the x boundary, window at c from step {}, {}-step run; timed steps "
                         "{}: {} spread evenly over steps {}-{} (untimed advance between them)".format(
-                            *cfg["n"], workloads.window_start_step(cfg), total, K,
+                            cfg["name"], *cfg["n"],
+                            " with a {}-cell transverse PML".format(cfg["pml"]) if cfg.get("pml") else "",
+                            workloads.window_start_step(cfg), total, K,
                             "every step" if K == total - args.warmup else "one in ~{}".format(
                                 round((total - args.warmup) / K)), idx[0], idx[-1]),
             "timed_step_indices": idx if K <= 50 else "{}..{}".format(idx[0], idx[-1]),

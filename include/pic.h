@@ -271,7 +271,13 @@ pic_status pic_species_view(pic_ctx *ctx, int32_t species, pic_species_bufs *out
  * conservation that the current of eq. 2.1 must obey), FP64 on the device:
  * max over nodes of |(rho^{n+1} - rho^n) dx/dt + sum_d (dx/d_d)(J_d - J_d[-e_d])|
  * with rho deposited in FP64 from the stored FP32 positions and J the FP32
- * current.  *resid and *max_abs_j are host outputs.  Synchronises. */
+ * current in the J planes.  When those hold the post-processed current
+ * (after the field step or pic_current_filter of a grid with jpost binomial
+ * or the denoiser, whose output B(J + sigma curl y) has the divergence of
+ * B J), rho passes through the same binomial stencil B first: the
+ * post-processed current conserves the filtered charge.  Right after
+ * pic_deposit the planes hold the raw current and rho is used as is.
+ * *resid and *max_abs_j are host outputs.  Synchronises. */
 pic_status pic_continuity(pic_ctx *ctx, int32_t species, double *resid, double *max_abs_j);
 
 /* pic_continuity without the workspace: for callers that cannot allocate

@@ -62,12 +62,19 @@ extern "C" {
  *   window_period with a moving window (pic_circ_set_window), the window
  *                 moves one cell every window_period steps; c dt = dz /
  *                 window_period is required then (0 = no window).
- *   sort_interval steps between cell sorts in pic_circ_step (0 = 2). */
+ *   sort_interval steps between cell sorts in pic_circ_step (0 = 2).
+ *   interleave    after a sort, each full block of 64 x interleave particles
+ *                 of a tile is stored interleave x 64 transposed, so that at
+ *                 interleave particles per cell a wavefront's lanes sit in
+ *                 different cells (0 = 32; 1 = plain cell order; at most 64).
+ *                 Results do not depend on it. */
 typedef struct {
     int32_t nz, nr;
     double dz, dr, dt;
     int32_t window_period;
     int32_t sort_interval;
+    int32_t interleave;
+    int32_t pad_;
 } pic_circ_desc;
 
 /* Caller-owned device planes: [component z, r, th][channel m0, Re m1, Im m1]. */

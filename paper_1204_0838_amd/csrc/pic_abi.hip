@@ -263,6 +263,9 @@ struct pic_ctx {
     Prof prof;
     // a split-path step is in progress (pic_gather_push since the last pic_field_step)
     bool mid_step = false;
+    // the J planes hold the post-processed current (binomial or denoiser
+    // output) rather than the raw deposit: the continuity check filters rho
+    bool j_filtered = false;
     // transverse absorbing layer (pic_set_pml); g.pml holds its thickness
     pic_pml_desc pml_desc{};
     PmlDev pml{};
@@ -558,6 +561,7 @@ pic_status filter_in_place(pic_ctx* c) {
         PICCHK(denoise(c, c->f.J, tmp));
     for (int a = 0; a < 3; ++a)
         HIPCHK(c, hipMemcpyAsync(c->f.J[a], tmp[a], (size_t)c->g.ncell * 4, hipMemcpyDeviceToDevice, c->stream));
+    c->j_filtered = true;
     return PIC_OK;
 }
 
@@ -581,6 +585,7 @@ pic_status finish_step(pic_ctx* c) {
         HIPCHK(c, launch_jfinal(c->g, acc_of(c), tmp, sc, 1, c->stream));
         PICCHK(denoise(c, tmp, c->f.J));
     }
+    c->j_filtered = c->desc.jpost != PIC_JPOST_NONE;
     PICCHK(prof_end(c, PH_JPOST, t0));
     PICCHK(prof_mark(c, &t1));
     PICCHK(field_update(c, Juse));
@@ -1101,6 +1106,7 @@ pic_status pic_deposit(pic_ctx* c, int32_t s) {
     double sc[3];
     jscale(c, sc);
     HIPCHK(c, launch_jfinal(c->g, acc_of(c), c->f.J, sc, 0, c->stream));
+    c->j_filtered = false;
     return PIC_OK;
 }
 
@@ -1182,7 +1188,8 @@ pic_status pic_continuity(pic_ctx* c, int32_t s, double* resid, double* max_abs_
     HIPCHK(c, launch_rho(c->g, d.cell, d.off, d.w, sp.user.q, 1.0, &sm->count[s], (int)sp.bound, rho, c->stream));
     HIPCHK(c, launch_rho(c->g, pv.cell, pv.off, d.w, sp.user.q, -1.0, &sm->count[s], (int)sp.bound, rho, c->stream));
     HIPCHK(c, launch_continuity(c->g, rho, c->f.J, c->desc.d[0] / c->desc.dt, c->desc.d[0] / c->desc.d[1],
-                                c->desc.d[0] / c->desc.d[2], &sm->contmax, c->stream));
+                                c->desc.d[0] / c->desc.d[2], c->j_filtered, &sm->contmax,
+                                c->stream));
     FieldPtrs f = fields_of(c);
     HIPCHK(c, launch_diag_fields(c->g, f.E, f.B, c->f.J, 1.0, sm->red, &sm->jmax, c->stream));
     unsigned long long cm = 0;
@@ -1219,7 +1226,8 @@ pic_status pic_continuity_noalloc(pic_ctx* c, int32_t s, double* resid, double* 
     HIPCHK(c, launch_rho(c->g, d.cell, d.off, d.w, sp.user.q, 1.0, &sm->count[s], (int)sp.bound, rho, c->stream));
     HIPCHK(c, launch_rho(c->g, pv.cell, pv.off, d.w, sp.user.q, -1.0, &sm->count[s], (int)sp.bound, rho, c->stream));
     HIPCHK(c, launch_continuity(c->g, rho, c->f.J, c->desc.d[0] / c->desc.dt, c->desc.d[0] / c->desc.d[1],
-                                c->desc.d[0] / c->desc.d[2], &head->contmax, c->stream));
+                                c->desc.d[0] / c->desc.d[2], c->j_filtered, &head->contmax,
+                                c->stream));
     FieldPtrs f = fields_of(c);
     HIPCHK(c, launch_diag_fields(c->g, f.E, f.B, c->f.J, 1.0, head->red, &head->jmax, c->stream));
     unsigned long long cm = 0;

@@ -99,6 +99,7 @@ pic_status cvalidate(const pic_circ_desc* d, char* msg, size_t len) {
     if (!(d->dt <= 0.95 / sqrt(1.0 / (d->dz * d->dz) + 4.0 / (d->dr * d->dr))))
         return bad("time step above the cylindrical Courant bound 0.95/sqrt(1/dz^2 + 4/dr^2)");
     if (d->window_period < 0 || d->sort_interval < 0) return bad("negative window period or sort interval");
+    if (d->interleave < 0 || d->interleave > 64) return bad("interleave outside [0, 64]");
     if (d->window_period > 0 && fabs(d->dt * d->window_period - d->dz) > 1e-12 * d->dz)
         return bad("a window moving one cell every window_period steps needs c dt = dz / window_period");
     if (msg && len) msg[0] = 0;
@@ -395,6 +396,7 @@ pic_status pic_circ_init(pic_circ_ctx** out, const pic_circ_desc* desc, const pi
     if (!c) return PIC_ENOMEM;
     c->desc = *desc;
     if (c->desc.sort_interval == 0) c->desc.sort_interval = 2;
+    if (c->desc.interleave == 0) c->desc.interleave = 32;
     c->f = *fields;
     c->stream = reinterpret_cast<hipStream_t>(stream);
     c->ws = reinterpret_cast<char*>(workspace);
@@ -502,7 +504,8 @@ pic_status pic_circ_step(pic_circ_ctx* c, int32_t nsteps) {
                 int* rank = reinterpret_cast<int*>(c->ws + c->L.rank) + sp.base;
                 CHIP(c, launch_sort(sort_geom(c), c->t, cdev(c, sp, sp.cur), cdev(c, sp, sp.alt), &sm->count[s],
                                     &sm->sorted[s], (int)sp.bound, reinterpret_cast<int*>(c->ws + c->L.hist), rank,
-                                    reinterpret_cast<int*>(c->ws + c->L.sums), 1, ctoff(c, s), true, c->stream));
+                                    reinterpret_cast<int*>(c->ws + c->L.sums), c->desc.interleave, ctoff(c, s), true,
+                                    c->stream));
                 std::swap(sp.cur, sp.alt);
                 sp.sorted = true;
                 sp.sort_step = c->step;

@@ -264,6 +264,6 @@ hipError_t noalloc_scratch(void** out);
 // max over nodes of |rho dx/dt + sum_d (dx/d_d)(J_d - J_d[-e_d])| as double bits
 // ry = dx/dy, rz = dx/dz
 hipError_t launch_continuity(const Geom& g, const double* rho, float* const J[3], double dx_dt, double ry,
-                             double rz, unsigned long long* maxbits, hipStream_t st);
+                             double rz, int filt, unsigned long long* maxbits, hipStream_t st);
 
 }  // namespace pic

@@ -107,10 +107,15 @@ __global__ void __launch_bounds__(256) k_rho(Geom g, const int* __restrict__ cel
                 atomicAdd(rho + (ix[0][i] + ix[1][j] + ix[2][k]), qw * wt[0][i] * wt[1][j] * wt[2][k]);
 }
 
+// filt: the current was post-processed by the binomial filter B (alone, or
+// as the last stage of the denoiser's J' = B(J + sigma curl y), whose
+// divergence is B div J): the charge is then B rho, evaluated here as the
+// same 27-point product stencil (zero across the window seam, periodic y and
+// z; the layer's cells hold no charge).
 __global__ void __launch_bounds__(256) k_continuity(Geom g, const double* __restrict__ rho,
                                                     const float* __restrict__ J0, const float* __restrict__ J1,
                                                     const float* __restrict__ J2, double dx_dt, double ry,
-                                                    double rz, unsigned long long* maxbits) {
+                                                    double rz, int filt, unsigned long long* maxbits) {
     double m = 0.0;
     for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < g.ncell; idx += gridDim.x * blockDim.x) {
         const int k = idx / g.nxy;
@@ -120,14 +125,29 @@ __global__ void __launch_bounds__(256) k_continuity(Geom g, const double* __rest
         const int im = i == 0 ? g.n[0] - 1 : i - 1;
         const int jm = j == 0 ? g.n[1] - 1 : j - 1;
         const int km = k == 0 ? g.n[2] - 1 : k - 1;
-        bool xm_ok = true;
+        bool xm_ok = true, xp_ok = true;
         if (g.window) {
             int xw = i - g.origin;
             if (xw < 0) xw += g.n[0];
             xm_ok = xw != 0;
+            xp_ok = xw != g.n[0] - 1;
+        }
+        double q = rho[idx];
+        if (filt) {
+            const int ip = i + 1 == g.n[0] ? 0 : i + 1;
+            const int jp = j + 1 == g.n[1] ? 0 : j + 1;
+            const int kp = k + 1 == g.n[2] ? 0 : k + 1;
+            const int xs[3] = {im, i, ip}, ys[3] = {jm, j, jp}, zs[3] = {km, k, kp};
+            const bool xok[3] = {xm_ok, true, xp_ok};
+            const double wt[3] = {0.25, 0.5, 0.25};
+            q = 0.0;
+            for (int c = 0; c < 3; ++c)
+                for (int b = 0; b < 3; ++b)
+                    for (int a = 0; a < 3; ++a)
+                        if (xok[a]) q += wt[a] * wt[b] * wt[c] * rho[xs[a] + g.n[0] * (ys[b] + g.n[1] * zs[c])];
         }
         const double jxm = xm_ok ? (double)J0[im + g.n[0] * (j + g.n[1] * k)] : 0.0;
-        double res = rho[idx] * dx_dt + ((double)J0[idx] - jxm);
+        double res = q * dx_dt + ((double)J0[idx] - jxm);
         res += ry * ((double)J1[idx] - (double)J1[i + g.n[0] * (jm + g.n[1] * k)]);
         res += rz * ((double)J2[idx] - (double)J2[i + g.n[0] * (j + g.n[1] * km)]);
         m = fmax(m, fabs(res));
@@ -168,9 +188,9 @@ hipError_t launch_rho(const Geom& g, const int* cell, float* const off[3], const
 }
 
 hipError_t launch_continuity(const Geom& g, const double* rho, float* const J[3], double dx_dt, double ry,
-                             double rz, unsigned long long* maxbits, hipStream_t st) {
+                             double rz, int filt, unsigned long long* maxbits, hipStream_t st) {
     hipLaunchKernelGGL(k_continuity, dim3(grid_for(g.ncell)), dim3(256), 0, st, g, rho, J[0], J[1], J[2], dx_dt, ry,
-                       rz, maxbits);
+                       rz, filt, maxbits);
     return hipGetLastError();
 }
 

@@ -3,7 +3,8 @@
 Configuration only (sizes, profiles, laser parameters); every step of the
 simulation runs in the HIP library through ``paper_1204_0838_amd.pic``.
 
-C1 is the 3D moving-window LWFA slab: 512 x 256 x 256 cells, dx = 0.25 c/w_p
+C1 is the 3D moving-window LWFA slab (C1P: the same inside a 16-cell
+transverse perfectly matched layer): 512 x 256 x 256 cells, dx = 0.25 c/w_p
 along the propagation axis with the perfect-dispersion solver at c dt = dx,
 dy = dz = 0.5 c/w_p, 8 electrons per cell on a 2x2x2 lattice behind a
 50-cell linear density ramp, and a y-polarised Gaussian laser (a0 = 4,
@@ -45,6 +46,13 @@ C1 = {
 }
 
 
+# C1 inside the paper's transverse boundary: its 256 x 256-cell cross-section
+# surrounded by a 16-cell perfectly matched layer on each side (Section 3.1),
+# 512 x 288 x 288 cells; particles are loaded over the whole cross-section and
+# those in the layer removed before their first push.
+C1P = dict(C1, name="C1P", n=(512, 288, 288), pml=16)
+
+
 C2 = {
     "name": "C2",
     "nz": 4096,
@@ -65,7 +73,8 @@ def c2_window_start(cfg: dict) -> int:
     return int(math.ceil(cfg["laser"]["t_end"] / cfg["dt"] - 1e-9))
 
 
-def build_c2(cfg: dict = C2, capacity_factor: float = 1.05, device="cuda:0", sort_interval: int = 0):
+def build_c2(cfg: dict = C2, capacity_factor: float = 1.05, device="cuda:0", sort_interval: int = 0,
+             interleave: int = 0):
     """A CircSimulation holding the C2 workload at t = 0 (plasma loaded, laser and window set)."""
     from .circ import CircSimulation
 
@@ -74,7 +83,7 @@ def build_c2(cfg: dict = C2, capacity_factor: float = 1.05, device="cuda:0", sor
     shifts = (cfg["steps"] - c2_window_start(cfg)) // cfg["window_period"] + 1
     cap = int(((nz - 2) * p["r_cells"] * p["ppc"]) * capacity_factor) + shifts * p["r_cells"] * p["ppc"]
     sim = CircSimulation(nz, nr, cfg["dz"], cfg["dr"], cfg["dt"], window_period=cfg["window_period"],
-                         sort_interval=sort_interval, max_particles=cap, device=device)
+                         sort_interval=sort_interval, max_particles=cap, device=device, interleave=interleave)
     sim.add_empty_species(cap)
     sim.set_plasma(0, p["z_start"], p["ramp"], p["n_plateau"], p["ppc"], p["r_cells"], p["seed"])
     sim.inject_plasma(0, 0, nz - 2)
@@ -141,6 +150,8 @@ def build(cfg: dict, capacity_factor: float = 1.05, device="cuda:0", tuned: bool
     sim.set_laser(L["a0"], L["omega0"], L["waist"], L["fwhm"], L["t_peak"], L["t_end"], ny * cfg["d"][1] / 2,
                   nz * cfg["d"][2] / 2, L["src_x"])
     sim.set_window(window_start_step(cfg))
+    if cfg.get("pml"):
+        sim.set_pml(cfg["pml"])
     return sim
 
 
