@@ -343,7 +343,7 @@ def bench_c2(args):
     total = cfg["steps"]
     args.steps = args.steps or total - args.warmup
     t_setup = time.perf_counter()
-    sim = workloads.build_c2(cfg, sort_interval=args.sort_interval, interleave=args.interleave)
+    sim = workloads.build_c2(cfg, sort_interval=args.sort_interval, interleave=args.interleave, threads=args.threads)
     sim.sync()
     idx = timed_indices(total, args.warmup, args.steps)
     print(f"# setup {time.perf_counter() - t_setup:.1f}s, window from step {workloads.c2_window_start(cfg)}, "
@@ -397,7 +397,8 @@ def bench_c2(args):
                                    workloads.c2_window_start(cfg), total, K, idx[0], idx[-1]),
                    "timed_step_indices": idx if K <= 50 else "{}..{}".format(idx[0], idx[-1]),
                    "particles": int(npart), "cells": ncell, "tile": [32, 8], "guard": 1,
-                   "sort_interval": sim.desc.sort_interval or 2, "interleave": sim.desc.interleave or 32},
+                   "sort_interval": sim.desc.sort_interval or 2, "interleave": sim.desc.interleave or 32,
+                   "threads": sim.desc.threads or 512},
         "gather_push_deposit_particle_steps_per_s": part / ((prof["tile_ms"] + prof["loose_ms"]) * 1e-3),
         "phase_ms_per_step": {k[:-3]: prof[k] / max(1, prof["steps"]) for k in keys[:6]},
         "roofline": {"bound": "hbm", "kernel": "k_circ_tile", "achieved": achieved, "peak": HBM_PEAK_GBS,

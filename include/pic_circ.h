@@ -67,14 +67,16 @@ extern "C" {
  *                 of a tile is stored interleave x 64 transposed, so that at
  *                 interleave particles per cell a wavefront's lanes sit in
  *                 different cells (0 = 32; 1 = plain cell order; at most 64).
- *                 Results do not depend on it. */
+ *                 Results do not depend on it.
+ *   threads       workgroup size of the fused tile kernel: 256, 512 or 1024
+ *                 (0 = 512).  Results do not depend on it. */
 typedef struct {
     int32_t nz, nr;
     double dz, dr, dt;
     int32_t window_period;
     int32_t sort_interval;
     int32_t interleave;
-    int32_t pad_;
+    int32_t threads;
 } pic_circ_desc;
 
 /* Caller-owned device planes: [component z, r, th][channel m0, Re m1, Im m1]. */

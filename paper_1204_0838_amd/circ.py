@@ -16,9 +16,9 @@ from .pic import (PIC_EINVAL, PIC_OK, CircDesc, CircFieldBufs, CircLaser, CircPl
                   SpeciesBufs, lib)
 
 
-def make_desc(nz, nr, dz, dr, dt, window_period=0, sort_interval=0, interleave=0):
+def make_desc(nz, nr, dz, dr, dt, window_period=0, sort_interval=0, interleave=0, threads=0):
     return CircDesc(int(nz), int(nr), float(dz), float(dr), float(dt), int(window_period), int(sort_interval),
-                    int(interleave), 0)
+                    int(interleave), int(threads))
 
 
 def validate(desc):
@@ -29,8 +29,8 @@ def validate(desc):
 
 class CircSimulation:
     def __init__(self, nz, nr, dz, dr, dt, window_period=0, sort_interval=0, max_particles=0, device="cuda:0",
-                 stream=None, interleave=0):
-        self.desc = make_desc(nz, nr, dz, dr, dt, window_period, sort_interval, interleave)
+                 stream=None, interleave=0, threads=0):
+        self.desc = make_desc(nz, nr, dz, dr, dt, window_period, sort_interval, interleave, threads)
         st, msg = validate(self.desc)
         if st != PIC_OK:
             raise PicError(st, msg)

@@ -430,8 +430,8 @@ struct CircTile {
 // One workgroup per tile of TZ x TR cells.  toff: tile ranges of the last
 // sort (tiles z-fastest: tile = tz + ntz * tr).  Particles outside the tile's
 // guard are appended to the rest list.
-template <int TZ, int TR, int G>
-__global__ void __launch_bounds__(256) k_circ_tile(CircGeom g, CircFields F, SpeciesDev s,
+template <int TZ, int TR, int G, int NT>
+__global__ void __launch_bounds__(NT) k_circ_tile(CircGeom g, CircFields F, SpeciesDev s,
                                                    const int* __restrict__ toff, int ntz, unsigned long long* gacc,
                                                    int* err, int* rest_n, int* rest_idx) {
     using T = CircTile<TZ, TR, G>;
@@ -873,21 +873,32 @@ hipError_t launch_circ_deposit(const CircGeom& g, const SpeciesDev& s, const Pre
     return hipGetLastError();
 }
 
-hipError_t launch_circ_tile(const CircGeom& g, const CircFields& F, const SpeciesDev& s, const int* toff, int ntz,
-                            int ntiles, unsigned long long* acc, int* err, int* rest_n, int* rest_idx,
-                            hipStream_t st) {
-    hipLaunchKernelGGL(k_circ_zero_rest, dim3(1), dim3(1), 0, st, rest_n);
+template <int NT>
+hipError_t launch_circ_tile_nt(const CircGeom& g, const CircFields& F, const SpeciesDev& s, const int* toff, int ntz,
+                               int ntiles, unsigned long long* acc, int* err, int* rest_n, int* rest_idx,
+                               hipStream_t st) {
     using T = CircTile<kCircTZ, kCircTR, kCircG>;
     static bool attr = false;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_circ_tile<kCircTZ, kCircTR, kCircG>,
+        hipError_t e = hipFuncSetAttribute((const void*)k_circ_tile<kCircTZ, kCircTR, kCircG, NT>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)T::kLds);
         if (e != hipSuccess) return e;
         attr = true;
     }
-    hipLaunchKernelGGL((k_circ_tile<kCircTZ, kCircTR, kCircG>), dim3(ntiles), dim3(256), T::kLds, st, g, F, s, toff,
-                       ntz, acc, err, rest_n, rest_idx);
+    hipLaunchKernelGGL((k_circ_tile<kCircTZ, kCircTR, kCircG, NT>), dim3(ntiles), dim3(NT), T::kLds, st, g, F, s,
+                       toff, ntz, acc, err, rest_n, rest_idx);
     return hipGetLastError();
+}
+
+hipError_t launch_circ_tile(const CircGeom& g, const CircFields& F, const SpeciesDev& s, const int* toff, int ntz,
+                            int ntiles, unsigned long long* acc, int* err, int* rest_n, int* rest_idx, int threads,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(k_circ_zero_rest, dim3(1), dim3(1), 0, st, rest_n);
+    switch (threads) {
+        case 256: return launch_circ_tile_nt<256>(g, F, s, toff, ntz, ntiles, acc, err, rest_n, rest_idx, st);
+        case 1024: return launch_circ_tile_nt<1024>(g, F, s, toff, ntz, ntiles, acc, err, rest_n, rest_idx, st);
+        default: return launch_circ_tile_nt<512>(g, F, s, toff, ntz, ntiles, acc, err, rest_n, rest_idx, st);
+    }
 }
 
 hipError_t launch_circ_rest(const CircGeom& g, const CircFields& F, const SpeciesDev& s, const int* d_sorted,

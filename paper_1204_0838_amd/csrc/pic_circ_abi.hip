@@ -100,6 +100,8 @@ pic_status cvalidate(const pic_circ_desc* d, char* msg, size_t len) {
         return bad("time step above the cylindrical Courant bound 0.95/sqrt(1/dz^2 + 4/dr^2)");
     if (d->window_period < 0 || d->sort_interval < 0) return bad("negative window period or sort interval");
     if (d->interleave < 0 || d->interleave > 64) return bad("interleave outside [0, 64]");
+    if (d->threads != 0 && d->threads != 256 && d->threads != 512 && d->threads != 1024)
+        return bad("threads per tile must be 0, 256, 512 or 1024");
     if (d->window_period > 0 && fabs(d->dt * d->window_period - d->dz) > 1e-12 * d->dz)
         return bad("a window moving one cell every window_period steps needs c dt = dz / window_period");
     if (msg && len) msg[0] = 0;
@@ -397,6 +399,7 @@ pic_status pic_circ_init(pic_circ_ctx** out, const pic_circ_desc* desc, const pi
     c->desc = *desc;
     if (c->desc.sort_interval == 0) c->desc.sort_interval = 2;
     if (c->desc.interleave == 0) c->desc.interleave = 32;
+    if (c->desc.threads == 0) c->desc.threads = 512;
     c->f = *fields;
     c->stream = reinterpret_cast<hipStream_t>(stream);
     c->ws = reinterpret_cast<char*>(workspace);
@@ -515,7 +518,7 @@ pic_status pic_circ_step(pic_circ_ctx* c, int32_t nsteps) {
             int* rest_idx = reinterpret_cast<int*>(c->ws + c->L.rank) + sp.base;
             CCHK(cmark(c, &t1));
             CHIP(c, launch_circ_tile(c->g, cfields(c), cdev(c, sp, sp.cur), ctoff(c, s), c->t.nt[0], c->t.ntiles,
-                                     cacc(c), &sm->err, &sm->rest_n[s], rest_idx, c->stream));
+                                     cacc(c), &sm->err, &sm->rest_n[s], rest_idx, c->desc.threads, c->stream));
             CCHK(cend(c, CP_TILE, t1));
             if (c->prof_on) c->ptiles += 1;
             CCHK(cmark(c, &t2));

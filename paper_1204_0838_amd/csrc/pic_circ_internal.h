@@ -15,8 +15,9 @@ hipError_t launch_circ_gather_push(const CircGeom& g, const CircFields& F, const
                                    const int* d_count, int max_count, int* err, hipStream_t st);
 hipError_t launch_circ_deposit(const CircGeom& g, const SpeciesDev& s, const PrevDev& prev, const int* d_count,
                                int max_count, float q, unsigned long long* acc, hipStream_t st);
+// threads: 256, 512 or 1024 per tile workgroup (other values: 512)
 hipError_t launch_circ_tile(const CircGeom& g, const CircFields& F, const SpeciesDev& s, const int* toff, int ntz,
-                            int ntiles, unsigned long long* acc, int* err, int* rest_n, int* rest_idx,
+                            int ntiles, unsigned long long* acc, int* err, int* rest_n, int* rest_idx, int threads,
                             hipStream_t st);
 hipError_t launch_circ_rest(const CircGeom& g, const CircFields& F, const SpeciesDev& s, const int* d_sorted,
                             const int* d_count, const int* rest_n, const int* rest_idx, int max_items,

@@ -168,7 +168,7 @@ _SIGS = {
 class CircDesc(ctypes.Structure):
     _fields_ = [("nz", ctypes.c_int32), ("nr", ctypes.c_int32), ("dz", ctypes.c_double), ("dr", ctypes.c_double),
                 ("dt", ctypes.c_double), ("window_period", ctypes.c_int32), ("sort_interval", ctypes.c_int32),
-                ("interleave", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("interleave", ctypes.c_int32), ("threads", ctypes.c_int32)]
 
 
 class CircFieldBufs(ctypes.Structure):

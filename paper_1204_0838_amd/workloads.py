@@ -74,7 +74,7 @@ def c2_window_start(cfg: dict) -> int:
 
 
 def build_c2(cfg: dict = C2, capacity_factor: float = 1.05, device="cuda:0", sort_interval: int = 0,
-             interleave: int = 0):
+             interleave: int = 0, threads: int = 0):
     """A CircSimulation holding the C2 workload at t = 0 (plasma loaded, laser and window set)."""
     from .circ import CircSimulation
 
@@ -83,7 +83,8 @@ def build_c2(cfg: dict = C2, capacity_factor: float = 1.05, device="cuda:0", sor
     shifts = (cfg["steps"] - c2_window_start(cfg)) // cfg["window_period"] + 1
     cap = int(((nz - 2) * p["r_cells"] * p["ppc"]) * capacity_factor) + shifts * p["r_cells"] * p["ppc"]
     sim = CircSimulation(nz, nr, cfg["dz"], cfg["dr"], cfg["dt"], window_period=cfg["window_period"],
-                         sort_interval=sort_interval, max_particles=cap, device=device, interleave=interleave)
+                         sort_interval=sort_interval, max_particles=cap, device=device, interleave=interleave,
+                         threads=threads)
     sim.add_empty_species(cap)
     sim.set_plasma(0, p["z_start"], p["ramp"], p["n_plateau"], p["ppc"], p["r_cells"], p["seed"])
     sim.inject_plasma(0, 0, nz - 2)
