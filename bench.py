@@ -345,7 +345,7 @@ def bench_c2(args):
     t_setup = time.perf_counter()
     sim = workloads.build_c2(cfg, sort_interval=args.sort_interval, interleave=args.interleave, threads=args.threads)
     sim.sync()
-    idx = timed_indices(total, args.warmup, args.steps)
+    idx = timed_indices(total, args.warmup, args.steps, sim.desc.sort_interval or 2)
     print(f"# setup {time.perf_counter() - t_setup:.1f}s, window from step {workloads.c2_window_start(cfg)}, "
           f"{len(idx)} timed steps from {idx[0]} to {idx[-1]}", file=sys.stderr, flush=True)
     st = sim.stream
@@ -464,10 +464,26 @@ def main():
     bench_c1(args)
 
 
-def timed_indices(total, warmup, k):
-    """K step indices spread evenly over [warmup, total) (all of them when k = total - warmup)."""
+def timed_indices(total, warmup, k, period=1):
+    """K step indices spread evenly over [warmup, total) (all of them when k =
+    total - warmup).  The cell sort runs on the steps whose index is a
+    multiple of `period` (the sort interval); the j-th index is moved within
+    its stretch to residue j mod period, so the timed steps include sorting
+    steps in the run's own proportion (exactly when period divides k)."""
     span = total - warmup
-    return [warmup + int((j + 0.5) * span / k) for j in range(k)]
+    if k >= span:
+        return list(range(warmup, total))
+    out = []
+    for j in range(k):
+        i = warmup + int((j + 0.5) * span / k)
+        if period > 1:
+            i = i - i % period + j % period
+            while i < warmup:
+                i += period
+            while i >= total:
+                i -= period
+        out.append(i)
+    return out
 
 
 def bench_c1(args):
@@ -496,7 +512,7 @@ def bench_c1(args):
     t_setup = time.perf_counter()
     sim = workloads.build(cfg, **tiling)
     sim.sync()
-    idx = timed_indices(total, args.warmup, args.steps)
+    idx = timed_indices(total, args.warmup, args.steps, sim.desc.sort_interval or 2)
     print(f"# setup {time.perf_counter() - t_setup:.1f}s, window starts at step "
           f"{workloads.window_start_step(cfg)}, {len(idx)} timed steps from {idx[0]} to {idx[-1]}",
           file=sys.stderr, flush=True)

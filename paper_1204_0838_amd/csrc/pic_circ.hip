@@ -338,6 +338,17 @@ __device__ __forceinline__ void load_particle(const SpeciesDev& s, int i, int nz
     p.w = s.w[i];
 }
 
+// The raw SoA values of particle i (cell, z offset, x, y, u, w).
+__device__ __forceinline__ void load_raw(const SpeciesDev& s, int i, int& cell, float o[3], float u[3], float& w) {
+    cell = s.cell[i];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        o[d] = s.off[d][i];
+        u[d] = s.u[d][i];
+    }
+    w = s.w[i];
+}
+
 __device__ __forceinline__ void store_particle(const SpeciesDev& s, int i, const CircGeom& g, const CircParticle& p,
                                                bool removed) {
     s.cell[i] = removed ? -1 : p.iz + g.nz * p.jr;
@@ -418,6 +429,21 @@ __global__ void k_circ_finalize_removed(int* cell, const int* __restrict__ d_cou
 
 // ------------------------------------------------------------------ fused tiled kernel
 
+// Tile of workgroup b: chunks of `chunk` consecutive tiles go round-robin
+// to the 8 XCDs (consecutive workgroup indices run on consecutive XCDs);
+// -1 past the last tile.  The launch has circ_xcd_blocks(ntiles, chunk)
+// workgroups.
+__device__ __forceinline__ int circ_xcd_tile(int b, int ntiles, int chunk) {
+    const int k = b % 8, j = b / 8;
+    const long long tile = (long long)(k + 8 * (j / chunk)) * chunk + j % chunk;
+    return tile < ntiles ? (int)tile : -1;
+}
+
+inline int circ_xcd_blocks(int ntiles, int chunk) {
+    const int nchunks = (ntiles + chunk - 1) / chunk;
+    return 8 * ((nchunks + 7) / 8) * chunk;
+}
+
 template <int TZ, int TR, int G>
 struct CircTile {
     static constexpr int SZ = TZ + 2 * G + 2, SR = TR + 2 * G + 2;       // staged field nodes
@@ -432,13 +458,16 @@ struct CircTile {
 // guard are appended to the rest list.
 template <int TZ, int TR, int G, int NT>
 __global__ void __launch_bounds__(NT) k_circ_tile(CircGeom g, CircFields F, SpeciesDev s,
-                                                   const int* __restrict__ toff, int ntz, unsigned long long* gacc,
-                                                   int* err, int* rest_n, int* rest_idx) {
+                                                   const int* __restrict__ toff, int ntz, int ntiles,
+                                                   unsigned long long* gacc, int* err, int* rest_n, int* rest_idx) {
     using T = CircTile<TZ, TR, G>;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     float* fl = reinterpret_cast<float*>(lds_raw);
     unsigned long long* al = reinterpret_cast<unsigned long long*>(lds_raw + T::kFieldFloats * 4);
-    const int tile = blockIdx.x;
+    // rows of tiles along z dealt round-robin to the 8 XCDs (neighbours in a
+    // row share their halos in one L2)
+    const int tile = circ_xcd_tile(blockIdx.x, ntiles, ntz);
+    if (tile < 0) return;
     const int tz = tile % ntz, tr = tile / ntz;
     const int z0 = tz * TZ, r0 = tr * TR;
     const int p_begin = toff[tile], p_end = toff[tile + 1];
@@ -464,15 +493,30 @@ __global__ void __launch_bounds__(NT) k_circ_tile(CircGeom g, CircFields F, Spec
     const LAcc la{al, ((z0 - G - 1) % g.nz + g.nz) % g.nz, r0 - G - 1, g.nz, T::AZ, T::AR};
     const float q = -s.mq;
     int e = 0;
-    for (int i = p_begin + threadIdx.x; i < p_end; i += blockDim.x) {
-        const int cl = s.cell[i];
+    // software pipeline: the next particle's SoA loads are issued before the
+    // current particle is processed
+    int i = p_begin + (int)threadIdx.x;
+    int cn = -1;
+    float on[3] = {0.f, 0.f, 0.f}, un[3] = {0.f, 0.f, 0.f}, wn = 0.f;
+    if (i < p_end) load_raw(s, i, cn, on, un, wn);
+    for (; i < p_end; i += NT) {
+        const int cl = cn;
+        CircParticle p0, p1;
+        p0.iz = cl % g.nz;
+        p0.jr = cl / g.nz;
+        p0.oz = on[0];
+        p0.x = on[1];
+        p0.y = on[2];
+        p0.u[0] = un[0];
+        p0.u[1] = un[1];
+        p0.u[2] = un[2];
+        p0.w = wn;
+        if (i + NT < p_end) load_raw(s, i + NT, cn, on, un, wn);
         if (cl < 0) continue;
-        if (circ_zkilled(g, cl % g.nz)) {
+        if (circ_zkilled(g, p0.iz)) {
             s.cell[i] = -1;
             continue;
         }
-        CircParticle p0, p1;
-        load_particle(s, i, g.nz, p0);
         int dz = p0.iz - z0;
         if (dz < -G) dz += g.nz;
         else if (dz >= g.nz - G) dz -= g.nz;
@@ -885,8 +929,8 @@ hipError_t launch_circ_tile_nt(const CircGeom& g, const CircFields& F, const Spe
         if (e != hipSuccess) return e;
         attr = true;
     }
-    hipLaunchKernelGGL((k_circ_tile<kCircTZ, kCircTR, kCircG, NT>), dim3(ntiles), dim3(NT), T::kLds, st, g, F, s,
-                       toff, ntz, acc, err, rest_n, rest_idx);
+    hipLaunchKernelGGL((k_circ_tile<kCircTZ, kCircTR, kCircG, NT>), dim3(circ_xcd_blocks(ntiles, ntz)), dim3(NT),
+                       T::kLds, st, g, F, s, toff, ntz, ntiles, acc, err, rest_n, rest_idx);
     return hipGetLastError();
 }
 
