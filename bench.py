@@ -466,22 +466,25 @@ def main():
 
 def timed_indices(total, warmup, k, period=1):
     """K step indices spread evenly over [warmup, total) (all of them when k =
-    total - warmup).  The cell sort runs on the steps whose index is a
-    multiple of `period` (the sort interval); the j-th index is moved within
-    its stretch to residue j mod period, so the timed steps include sorting
-    steps in the run's own proportion (exactly when period divides k)."""
+    total - warmup): the j-th lies in the j-th of k equal, disjoint stretches.
+    The cell sort runs on the steps whose index is a multiple of `period`
+    (the sort interval); where a stretch holds at least `period` steps, its
+    index is the one of residue j mod period nearest the stretch's middle, so
+    the timed steps include sorting steps in the run's own proportion (exactly
+    when period divides k)."""
     span = total - warmup
     if k >= span:
         return list(range(warmup, total))
     out = []
     for j in range(k):
-        i = warmup + int((j + 0.5) * span / k)
-        if period > 1:
-            i = i - i % period + j % period
-            while i < warmup:
-                i += period
-            while i >= total:
-                i -= period
+        lo = warmup + (j * span) // k
+        hi = warmup + ((j + 1) * span) // k          # exclusive; hi > lo since span > k
+        mid = (lo + hi - 1) // 2
+        i = mid
+        if period > 1 and hi - lo >= period:
+            want = j % period
+            cands = [v for v in range(lo, hi) if v % period == want]
+            i = min(cands, key=lambda v: abs(v - mid))
         out.append(i)
     return out
 

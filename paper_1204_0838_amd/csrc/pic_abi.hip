@@ -1735,9 +1735,18 @@ pic_status pic_denoiser_set(pic_ctx* c, const float* weights, const float* biase
     for (int t = 0; t < 27; ++t)
         for (int co = 0; co < 32; ++co)
             for (int ci = 0; ci < 32; ++ci) w2[(t * 32 + co) * 32 + ci] = bf(W2[(co * 32 + ci) * 27 + t]);
-    for (int t = 0; t < 27; ++t)
-        for (int co = 0; co < 3; ++co)
-            for (int ci = 0; ci < 32; ++ci) w3[(t * 16 + co) * 32 + ci] = bf(W3[(co * 32 + ci) * 27 + t]);
+    // W3 for the folded last layer: fragment (tap column zx, halo row r), column
+    // 4 blk + co carries tap (dz, r - blk, dx) when 0 <= r - blk <= 2
+    for (int zx = 0; zx < 9; ++zx)
+        for (int r = 0; r < 6; ++r)
+            for (int blk = 0; blk < 4; ++blk) {
+                const int dy = r - blk;
+                if (dy < 0 || dy > 2) continue;
+                const int t = (zx / 3) * 9 + dy * 3 + zx % 3;
+                for (int co = 0; co < 3; ++co)
+                    for (int ci = 0; ci < 32; ++ci)
+                        w3[((zx * 6 + r) * 16 + blk * 4 + co) * 32 + ci] = bf(W3[(co * 32 + ci) * 27 + t]);
+            }
     std::vector<float> b(kDnBias, 0.0f);
     for (int i = 0; i < 32; ++i) b[i] = biases[i];
     for (int i = 0; i < 32; ++i) b[32 + i] = biases[32 + i];

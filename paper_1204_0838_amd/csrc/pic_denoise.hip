@@ -137,8 +137,8 @@ __global__ void __launch_bounds__(DN_THREADS) k_dn_c4(DnArgs a) {
 }
 
 // Layers with a 32-channel input: 32 -> 32 channels (KIND 0: relu(acc + b),
-// 1: mask epilogue) or 32 -> 3 (KIND 2, 16 computed: y = acc + b as FP32
-// components into a.Jout).  Persistent: one workgroup per compute unit stages
+// 1: mask epilogue) or 32 -> 3 (KIND 2, the row blocks folded into the
+// matrix columns, dn_mma3: y = acc + b as FP32 components into a.Jout).  Persistent: one workgroup per compute unit stages
 // the weights once and walks the tiles t = blockIdx.x, + gridDim.x, ...; the
 // next tile's input halo is loaded into registers while the current tile's
 // matrix work runs.
@@ -150,7 +150,7 @@ __global__ void __launch_bounds__(DN_THREADS) k_dn_conv32(DnArgs a) {
     char* wl = dlds + DN_ACT_LDS;
     int ntx, nty;
     const int ntiles = dn_ntiles(a.n, &ntx, &nty);
-    dn_stage_weights<27 * 16 * NH>(a.w, wl);
+    dn_stage_weights<KIND == 2 ? 9 * DN_HY * 16 : 27 * 16 * NH>(a.w, wl);
     // XCD-aware walk (workgroups go round-robin over the 8 XCDs): the
     // workgroups of one XCD share a contiguous range of tiles and walk it
     // together, so the halos they share stay in that XCD's L2
@@ -184,29 +184,30 @@ __global__ void __launch_bounds__(DN_THREADS) k_dn_conv32(DnArgs a) {
             dn_tile_of(next, ntx, nty, t0);
             dn_load_act(a, box, t0, hc, v);
         }
-        f32x4 acc[4][NH];
-#pragma unroll
-        for (int blk = 0; blk < 4; ++blk)
-#pragma unroll
-            for (int h = 0; h < NH; ++h) acc[blk][h] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-        dn_mma32<NH>(act, wl, acc);
         if constexpr (KIND == 2) {
+            f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            dn_mma3(act, wl, acc);
             const int l = threadIdx.x & 63, lz = threadIdx.x >> 6;
-            const int co = l & 15, rq = l >> 4;
+            const int col = l & 15, rq = l >> 4;
+            const int blk = col >> 2, co = col & 3;
             if (co < 3) {
                 // pick the component's pointer among the three (indexing the
                 // argument array with a lane value would re-read it from memory)
                 float* out = co == 0 ? a.Jout[0] : (co == 1 ? a.Jout[1] : a.Jout[2]);
                 const float b = a.bias[co];
 #pragma unroll
-                for (int blk = 0; blk < 4; ++blk)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const int cell = dn_out_cell(a, cur, lz, blk, rq * 4 + j);
-                        if (cell >= 0) out[cell] = acc[blk][0][j] + b;
-                    }
+                for (int j = 0; j < 4; ++j) {
+                    const int cell = dn_out_cell(a, cur, lz, blk, rq * 4 + j);
+                    if (cell >= 0) out[cell] = acc[j] + b;
+                }
             }
         } else {
+            f32x4 acc[4][NH];
+#pragma unroll
+            for (int blk = 0; blk < 4; ++blk)
+#pragma unroll
+                for (int h = 0; h < NH; ++h) acc[blk][h] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            dn_mma32<NH>(act, wl, acc);
             __syncthreads();   // every wavefront is done reading the halo: reuse it for the output tile
             dn_store32<KIND>(a, cur, acc, act);
         }
@@ -418,7 +419,7 @@ hipError_t launch_dn_curl_adjoint(const DnCombine& c, hipStream_t st) {
     return hipGetLastError();
 }
 
-static size_t dn_lds(int cout) { return (size_t)DN_ACT_LDS + (size_t)27 * cout * 64; }
+static size_t dn_lds(int weight_rows) { return (size_t)DN_ACT_LDS + (size_t)weight_rows * 64; }
 
 template <class K>
 static hipError_t dn_launch(K kern, size_t lds, const DnArgs& a, hipStream_t st) {
@@ -453,9 +454,9 @@ hipError_t launch_dn_layer(int kind, const DnArgs& a, hipStream_t st) {
     switch (kind) {
         case DN_L1_J_ACT: return dn_launch(k_dn_c4<0, 0>, 0, a, st);
         case DN_L1_C4_MASK: return dn_launch(k_dn_c4<1, 1>, 0, a, st);
-        case DN_L2_ACT: return dn_launch_persistent(k_dn_conv32<0>, dn_lds(32), a, st);
-        case DN_L2_MASK: return dn_launch_persistent(k_dn_conv32<1>, dn_lds(32), a, st);
-        case DN_L3_Y: return dn_launch_persistent(k_dn_conv32<2>, dn_lds(16), a, st);
+        case DN_L2_ACT: return dn_launch_persistent(k_dn_conv32<0>, dn_lds(27 * 32), a, st);
+        case DN_L2_MASK: return dn_launch_persistent(k_dn_conv32<1>, dn_lds(27 * 32), a, st);
+        case DN_L3_Y: return dn_launch_persistent(k_dn_conv32<2>, dn_lds(9 * DN_HY * 16), a, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -6,7 +6,7 @@
 //   x  = bf16(J_d / s_d)                    layer 1: 3 (padded to 4) -> 32 channels
 //   a1 = bf16(relu(conv(x, W1) + b1))
 //   a2 = bf16(relu(conv(a1, W2) + b2))      layer 2: 32 -> 32 (84 % of the work)
-//   J'_d = J_d + s_d (conv(a2, W3) + b3)_d  layer 3: 32 -> 3 (padded to 16)
+//   J'_d = J_d + s_d (conv(a2, W3) + b3)_d  layer 3: 32 -> 3 (4 row blocks x 4 columns)
 //
 // conv is the "same"-size 3x3x3 cross-correlation; y and z are periodic, x is
 // periodic or (moving window) zero beyond the window's two ends, or zero
@@ -281,6 +281,31 @@ __device__ __forceinline__ void dn_mma32(const char* act, const char* wl, f32x4 
 #pragma unroll
                 for (int h = 0; h < NH; ++h)
                     acc[blk][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[blk + dy], B[h], acc[blk][h], 0, 0, 0);
+        }
+    }
+}
+
+// The 32 -> 3 layer with the output rows folded into the matrix columns:
+// column 4 blk + c (c < 3; c = 3 is zero) of one MFMA holds output channel c
+// of row block blk, so the halo row r (0..5) of a tap column (dz, dx) is one
+// A fragment multiplied by one B fragment whose column (blk, c) carries the
+// weight of tap (dz, r - blk, dx) when 0 <= r - blk <= 2 (else zero):
+// 6 MFMAs per tap column instead of 12 (4 row blocks x 3 dy taps), 12 of the
+// 16 columns useful instead of 3.  B fragment (zx, r) is rows
+// 16 (6 zx + r) .. + 15 of the packed weights.
+__device__ __forceinline__ void dn_mma3(const char* act, const char* wl, f32x4& acc) {
+    const int l = threadIdx.x & 63, lz = threadIdx.x >> 6;
+    const int m = l & 15, q = l >> 4;
+    const char* abase = act + (lz * DN_HY * DN_HX + m) * DN_ROWB + q * 16;
+    const char* bbase = wl + dn_chunk(m, q);
+#pragma unroll
+    for (int zx = 0; zx < 9; ++zx) {
+        const int dz = zx / 3, dx = zx % 3;
+#pragma unroll
+        for (int r = 0; r < DN_HY; ++r) {
+            const bf16x8 A = *reinterpret_cast<const bf16x8*>(abase + ((dz * DN_HY + r) * DN_HX + dx) * DN_ROWB);
+            const bf16x8 B = *reinterpret_cast<const bf16x8*>(bbase + (zx * DN_HY + r) * 1024);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B, acc, 0, 0, 0);
         }
     }
 }

@@ -167,9 +167,10 @@ constexpr int kP_W1 = 0, kP_W2 = kP_W1 + 32 * 3 * 27, kP_W3 = kP_W2 + 32 * 32 * 
 // Gradient buffers (FP32): dW1 [32][112], dW2 [32][864], dW3 [16][864] (rows < 4 used), db1 [32], db2 [32], db3 [4]
 constexpr int kG_W1 = 0, kG_W2 = kG_W1 + 32 * 112, kG_W3 = kG_W2 + 32 * 864, kG_B1 = kG_W3 + 16 * 864,
               kG_B2 = kG_B1 + 32, kG_B3 = kG_B2 + 32, kG_N = kG_B3 + 4;
-// bf16 packs: forward W1p [32][128], W2p [27][32][32], W3p [27][16][32];
+// bf16 packs: forward W1p [32][128], W2p [27][32][32], W3p [9 zx][6 r][16 (blk, co)][32] (the folded
+// last layer: column 4 blk + co of fragment (zx, r) carries tap (dz, r - blk, dx));
 // backward W3T [32][128] (k = tap * 4 + c: W3[c][co][26 - tap]), W2T [27][32][32] (W2[ci][co][26 - t])
-constexpr int kK_W1 = 0, kK_W2 = kK_W1 + 32 * 128, kK_W3 = kK_W2 + 27 * 32 * 32, kK_W3T = kK_W3 + 27 * 16 * 32,
+constexpr int kK_W1 = 0, kK_W2 = kK_W1 + 32 * 128, kK_W3 = kK_W2 + 27 * 32 * 32, kK_W3T = kK_W3 + 9 * 6 * 16 * 32,
               kK_W2T = kK_W3T + 32 * 128, kK_N = kK_W2T + 27 * 32 * 32;
 // FP32 biases of the kernels: b1 [32], b2 [32], b3 [16]
 constexpr int kB_N = 80;
@@ -219,7 +220,10 @@ __global__ void k_dn_adam_pack(float* __restrict__ P, float* __restrict__ M, flo
         K[kK_W2T + ((26 - t) * 32 + ci) * 32 + co] = b;
     } else if (i < kP_B1) {
         const int j = i - kP_W3, co = j / 864, r = j % 864, ci = r / 27, t = r % 27;
-        K[kK_W3 + (t * 16 + co) * 32 + ci] = b;
+        const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
+#pragma unroll
+        for (int blk = 0; blk < 4; ++blk)
+            K[kK_W3 + (((dz * 3 + dx) * 6 + blk + dy) * 16 + blk * 4 + co) * 32 + ci] = b;
         K[kK_W3T + ci * 128 + (26 - t) * 4 + co] = b;
     } else if (i < kP_B2) {
         Bk[i - kP_B1] = p;

@@ -163,7 +163,8 @@ struct DenoiseWeights {
     float sigma;      // output stage J' = B(J + sigma curl(y)), sigma = dx (s_x + s_y + s_z) / 3
     float inv_d[3];
 };
-constexpr size_t kDnW1 = 32 * 128, kDnW2 = 27 * 32 * 32, kDnW3 = 27 * 16 * 32;   // bf16 elements
+// bf16 elements; W3: 9 tap columns x 6 halo rows x 16 columns (4 row blocks x 4) x 32
+constexpr size_t kDnW1 = 32 * 128, kDnW2 = 27 * 32 * 32, kDnW3 = 9 * 6 * 16 * 32;
 constexpr size_t kDnBias = 32 + 32 + 16;                                            // floats
 
 // bc per axis: 0 periodic, 1 zero outside the box, 2 moving window (zero
