@@ -20,6 +20,16 @@ no grid-scale (Nyquist) modes.
    current then differs from the target by more than sampling noise.)
 2. Training: Adam on the matrix cores (pic_dn_trainer), per-component scale
    = RMS of the targets.
+2b. Optional rollout pairs (--rollout-steps N): pairs from the states the
+   denoised run itself visits, then further training from the trained
+   parameters.  One run carries the 2-ppc lattice at full density, whose
+   current, denoised, drives the fields (the denoised 2-ppc run), and the
+   32-ppc lattice at full density as passive particles pushed by the same
+   fields: at every step the split path pushes both species and deposits
+   the 2-ppc one (J_A, the input), and the field step runs on J_A alone; at
+   sampled steps the passive species is deposited too (J_A + J_B) and the
+   binomial filter of J_B, computed by the library on a particle-free grid
+   of the same shape, is the target.
 3. Evaluation: a 2-ppc run with the trained denoiser (fused step) and a
    2-ppc run with the binomial filter, both compared with the 32-ppc run on
    the wake field E_x over the whole window at fixed checkpoints; a second
@@ -118,6 +128,57 @@ def collect_pairs(base, steps, sample_steps, crop, ncrops, seed, axis_share=0.75
     return pairs, ex32, ms32, n32
 
 
+def collect_rollout_pairs(base, steps, sample_steps, crop, ncrops, seed, params, scale, axis_share=0.75):
+    """Aligned pairs from the denoised 2-ppc run's own states (see the module doc, 2b)."""
+    import torch
+
+    from . import pic, workloads
+
+    sim = workloads.build(_cfg(base, PPC32), jpost="denoiser", species=[(PPC2, 1.0), (PPC32, 1.0)])
+    sim.set_denoiser(params, scale)
+    filt = pic.Simulation(base["n"], base["d"], base["dt"], solver=base["solver"], bc_x=1, jpost="binomial",
+                          max_particles=1)
+    nx, ny, nz = base["n"]
+    cx, cy, cz = crop
+    rng = np.random.default_rng(seed)
+    per = int(math.ceil(ncrops / max(1, len(sample_steps))))
+    pairs = []
+    t0 = time.perf_counter()
+    for st in range(1, steps + 1):
+        _, org = sim.window_state()
+        sim.gather_push(0)
+        sim.gather_push(1)
+        sim.deposit(0)
+        ja = sim.J.clone()                     # the 2-ppc run's own current
+        if st in sample_steps and len(pairs) < ncrops:
+            sim.deposit(1)                     # + the passive 32-ppc particles
+            with torch.no_grad():              # J_B in window order: the filter grid's window has origin 0
+                filt.J.copy_(torch.roll(sim.J - ja, shifts=-org, dims=3))
+            filt.current_filter()              # the library's binomial filter of J_B
+            js = torch.roll(ja, shifts=-org, dims=3)
+            jb = filt.J
+            for _ in range(per):
+                if len(pairs) >= ncrops:
+                    break
+                x0 = int(rng.integers(0, nx - cx + 1))
+                if rng.random() < axis_share:
+                    y0 = min(max(ny // 2 - cy // 2 + int(rng.integers(-(cy // 4), cy // 4 + 1)), 0), ny - cy)
+                    z0 = min(max(nz // 2 - cz // 2 + int(rng.integers(-(cz // 4), cz // 4 + 1)), 0), nz - cz)
+                else:
+                    y0 = int(rng.integers(0, ny - cy + 1))
+                    z0 = int(rng.integers(0, nz - cz + 1))
+                sl = (slice(None), slice(z0, z0 + cz), slice(y0, y0 + cy), slice(x0, x0 + cx))
+                pairs.append((js[sl].contiguous(), jb[sl].contiguous()))
+        with torch.no_grad():
+            sim.J.copy_(ja)                    # the fields see the denoised 2-ppc current only
+        sim.field_step()
+        if st % 50 == 0:
+            _log(f"rollout run step {st}/{steps}, {len(pairs)} crops, {time.perf_counter() - t0:.0f} s")
+    sim.close()
+    filt.close()
+    return pairs
+
+
 def binomial_init(rng, noise=0.3):
     """Parameters whose network output is the binomial filter: J' = B(J).
 
@@ -129,7 +190,7 @@ def binomial_init(rng, noise=0.3):
     return [W1, np.zeros(32), W2, np.zeros(32), W3, np.zeros(3)]
 
 
-def train(pairs, crop, cell, epochs, lr, seed, batch=8):
+def train(pairs, crop, cell, epochs, lr, seed, batch=8, start=None, start_scale=None):
     """Adam on mini-batches of crops, starting from the binomial filter,
     with the biases held at zero.
 
@@ -139,13 +200,13 @@ def train(pairs, crop, cell, epochs, lr, seed, batch=8):
     from . import pic
 
     tgt_rms = np.sqrt(np.mean([[float((t[d] ** 2).mean()) for d in range(3)] for _, t in pairs], axis=0))
-    scale = np.maximum(tgt_rms, 1e-12).astype(np.float32)
+    scale = np.maximum(tgt_rms, 1e-12).astype(np.float32) if start_scale is None else start_scale
     rng = np.random.default_rng(seed)
     order = rng.permutation(len(pairs))
     nval = max(1, len(pairs) // 10)
     val = [pairs[i] for i in order[:nval]]
     trn = [pairs[i] for i in order[nval:]]
-    P = binomial_init(rng)
+    P = binomial_init(rng) if start is None else [np.asarray(a) for a in start]
     tr = pic.DenoiserTrainer(crop, cell=cell)
     tr.set_params(P, scale)
     tr.freeze_biases(True)     # zero biases: no correction where J = 0, and net(a J) = a net(J)
@@ -155,7 +216,7 @@ def train(pairs, crop, cell, epochs, lr, seed, batch=8):
 
     init = val_loss()
     best, best_params = init, tr.get_params()
-    hist = {"val_loss_binomial_start": init, "val_loss": [], "train_loss": []}
+    hist = {"val_loss_binomial_start" if start is None else "val_loss_start": init, "val_loss": [], "train_loss": []}
     nstep = epochs * ((len(trn) + batch - 1) // batch)
     k = 0
     t0 = time.perf_counter()
@@ -175,7 +236,7 @@ def train(pairs, crop, cell, epochs, lr, seed, batch=8):
             best, best_params = v, tr.get_params()
         _log(f"epoch {ep + 1}/{epochs}: train {hist['train_loss'][-1]:.5f}, held-out {v:.5f} "
              f"(binomial start {init:.5f}), {time.perf_counter() - t0:.0f} s")
-    hist["kept"] = "trained" if best < init else "binomial start"
+    hist["kept"] = "trained" if best < init else ("binomial start" if start is None else "start")
     hist["val_loss_kept"] = best
     tr.close()
     return best_params, scale, hist
@@ -240,6 +301,11 @@ def main():
     ap.add_argument("--out", type=str, default="c4_out")
     ap.add_argument("--no-floor", action="store_true", help="skip the second 32-ppc run (noise floor)")
     ap.add_argument("--axis-share", type=float, default=0.75, help="share of training crops containing the laser axis")
+    ap.add_argument("--rollout-steps", type=int, default=0,
+                    help="steps of the denoised run whose states give a second set of pairs (0: none)")
+    ap.add_argument("--rollout-epochs", type=int, default=4)
+    ap.add_argument("--alphas", type=str, default="",
+                    help="also evaluate the learned correction scaled by each of these factors (comma list)")
     args = ap.parse_args()
     sys.path.insert(0, os.path.dirname(HERE))
     from paper_1204_0838_amd import workloads
@@ -257,12 +323,27 @@ def main():
     _log(f"{len(pairs)} training pairs; 32-ppc run {ms32:.1f} ms/step, {n32} particles")
     t_train = time.perf_counter()
     params, scale, hist = train(pairs, crop, base["d"], args.epochs, args.lr, seed=6, batch=args.batch)
-    t_train = time.perf_counter() - t_train
     del pairs
+    hist_rollout = None
+    if args.rollout_steps > 0:
+        rs = args.rollout_steps
+        rsample = set(np.linspace(max(1, rs // 10), rs - 1, 16).astype(int).tolist())
+        rpairs = collect_rollout_pairs(base, rs, rsample, crop, args.crops // 2, seed=7, params=params, scale=scale,
+                                       axis_share=args.axis_share)
+        _log(f"{len(rpairs)} rollout pairs from steps {min(rsample)}..{max(rsample)}")
+        params, scale, hist_rollout = train(rpairs, crop, base["d"], args.rollout_epochs, args.lr * 0.3, seed=8,
+                                            batch=args.batch, start=params, start_scale=scale)
+        del rpairs
+    t_train = time.perf_counter() - t_train
     np.savez(os.path.join(args.out, "denoiser_params.npz"), W1=params[0], b1=params[1], W2=params[2], b2=params[3],
              W3=params[4], b3=params[5], scale=scale)
     exd, msd, nd, cont = run_eval(base, PPC2, "denoiser", steps, params, scale, continuity=True)
     exb, msb, nb, _ = run_eval(base, PPC2, "binomial", steps)
+    scaled = {}
+    for a in [float(v) for v in args.alphas.split(",") if v.strip()]:
+        pa = [params[0], params[1], params[2], params[3], a * np.asarray(params[4]), a * np.asarray(params[5])]
+        exa, _, _, _ = run_eval(base, PPC2, "denoiser", steps, pa, scale)
+        scaled[str(a)] = {str(k): _rel(exa[k], ex32[k]) for k in sorted(exa)}
     floor = None
     if not args.no_floor:
         exf, msf, nf, _ = run_eval(base, PPC32_ALT, "binomial", steps)
@@ -270,7 +351,8 @@ def main():
     out = {
         "grid": list(base["n"]), "steps": steps, "crop": list(crop), "crops": args.crops,
         "epochs": args.epochs, "batch": args.batch, "lr": args.lr, "axis_share": args.axis_share,
-        "train_seconds": t_train, "training": hist,
+        "train_seconds": t_train, "training": hist, "rollout_training": hist_rollout,
+        "rollout_steps": args.rollout_steps,
         "scale": scale.tolist(),
         "ms_per_step": {"ppc32_binomial": ms32, "ppc2_denoiser": msd, "ppc2_binomial": msb},
         "particles": {"ppc32": n32, "ppc2_denoiser": nd, "ppc2_binomial": nb},
@@ -279,6 +361,7 @@ def main():
             "ppc2_denoiser": {str(k): _rel(exd[k], ex32[k]) for k in sorted(exd)},
             "ppc2_binomial": {str(k): _rel(exb[k], ex32[k]) for k in sorted(exb)},
             "ppc32_other_lattice_noise_floor": floor,
+            "ppc2_denoiser_correction_scaled": scaled,
         },
         "denoised_continuity": cont,
     }
