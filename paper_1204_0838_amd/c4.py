@@ -235,7 +235,7 @@ def train(pairs, crop, cell, epochs, lr, seed, batch=8, start=None, start_scale=
         if v < best:
             best, best_params = v, tr.get_params()
         _log(f"epoch {ep + 1}/{epochs}: train {hist['train_loss'][-1]:.5f}, held-out {v:.5f} "
-             f"(binomial start {init:.5f}), {time.perf_counter() - t0:.0f} s")
+             f"({'binomial start' if start is None else 'start'} {init:.5f}), {time.perf_counter() - t0:.0f} s")
     hist["kept"] = "trained" if best < init else ("binomial start" if start is None else "start")
     hist["val_loss_kept"] = best
     tr.close()
