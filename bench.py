@@ -288,7 +288,7 @@ def bench_c4(args):
                    "particles": int(npart), "cells": ncell},
         "phase_ms_per_step": {k[:-3]: prof[k] / max(1, prof["steps"]) for k in
                               ("sort_ms", "tile_ms", "loose_ms", "jpost_ms", "field_ms", "window_ms")},
-        "roofline": {"bound": "mfma", "kernel": "denoiser (k_dn_c4, k_dn_c32, k_dn_c3 + output stage)",
+        "roofline": {"bound": "mfma", "kernel": "denoiser (k_dn_c4, k_dn_conv32<0>, k_dn_conv32<2>, k_dn_output)",
                      "achieved": achieved, "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / BF16_MFMA_PEAK_TFLOPS, "traffic": None,
                      "alg_flop_per_step": DN_FLOP_PER_CELL * ncell, "mean_denoiser_ms": dn_ms},
@@ -358,9 +358,13 @@ def bench_c2(args):
     last = time.perf_counter()
     for j, i in enumerate(idx):
         while done < i:
-            k = min(200, i - done)
+            k = min(20, i - done)
             sim.step(k)
             done += k
+            sim.sync()                        # (progress lines follow the device, also under a profiler)
+            if time.perf_counter() - last > 20:
+                print(f"# advanced to step {done}", file=sys.stderr, flush=True)
+                last = time.perf_counter()
         sim.sync()
         n_live = sim.reduce()["n_particles"]
         sim.profile_enable(True)
@@ -531,9 +535,13 @@ def bench_c1(args):
     last_note = time.perf_counter()
     for j, i in enumerate(idx):
         while done < i:                       # untimed advance to the next timed step
-            k = min(100, i - done)
+            k = min(10, i - done)
             sim.step(k)
             done += k
+            sim.sync()                        # (progress lines follow the device, also under a profiler)
+            if time.perf_counter() - last_note > 20:
+                print(f"# advanced to step {done}", file=sys.stderr, flush=True)
+                last_note = time.perf_counter()
         sim.sync()
         n_live = sim.reduce()["n_particles"]
         sim.profile_enable(True)
