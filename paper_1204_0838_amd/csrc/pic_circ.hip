@@ -206,6 +206,12 @@ __device__ __forceinline__ int circ_push(const CircGeom& g, const FA& fa, float 
 template <class AC>
 __device__ __forceinline__ void circ_deposit(const CircGeom& g, const AC& acc, float q, const CircParticle& p0,
                                              const CircParticle& p1) {
+    // A particle that kept its cell and position and has no transverse momentum
+    // contributes exactly zero to every mode (the charge-conserving parts are
+    // products of the position changes, the direct m = 0 azimuthal part is
+    // proportional to x u_y - y u_x): skip it (a cold plasma ahead of the pulse).
+    if (p1.iz == p0.iz && p1.oz == p0.oz && p1.x == p0.x && p1.y == p0.y && p1.u[0] == 0.0f && p1.u[1] == 0.0f)
+        return;
     float r0, s0, r1, s1;
     int K0, K1;
     circ_rcell(p0.x, p0.y, g.inv_dr, r0, K0, s0);
