@@ -27,27 +27,46 @@ namespace {
 
 // ------------------------------------------------------------------ field access
 
-// Global-memory reads: node (iz storage, jr); zero at or beyond the wall.
+// Field and accumulator access through a per-particle handle: at(bz, br)
+// fixes the particle's base node once, and get / add address the node
+// (bz + a, br + b) relative to it (a, b small constants), so the local
+// accessors need one offset per base instead of one wrap per node.
+
+// Global-memory reads: node (iz storage, jr); zero at or beyond the wall and
+// below the axis.
 struct GField {
     const CircGeom* g;
     const CircFields* F;
-    __device__ __forceinline__ float get(int f, int c, int ch, int iz, int jr) const {
-        if (jr >= g->nr) return 0.0f;
+    struct H {
+        int bz, br;
+    };
+    __device__ __forceinline__ H at(int bz, int br) const { return H{bz, br}; }
+    __device__ __forceinline__ float get(const H& h, int f, int c, int ch, int a, int b) const {
+        const int jr = h.br + b;
+        if (jr < 0 || jr >= g->nr) return 0.0f;
+        int iz = h.bz + a;
         iz = iz < 0 ? iz + g->nz : (iz >= g->nz ? iz - g->nz : iz);
         return F->F[f][c][ch][iz + g->nz * jr];
     }
 };
 
-// LDS reads: the tile's staged planes [18][SR][SZ], origin (fz0, fr0).
+// LDS reads: the tile's staged planes [18][SR][SZ], origin (fz0, fr0); rows
+// below the axis and beyond the wall are staged as zero.
 struct LField {
     const float* s;
     int fz0, fr0, nz;
     int SZ, SR;
-    __device__ __forceinline__ float get(int f, int c, int ch, int iz, int jr) const {
-        int dz = iz - fz0;
+    struct H {
+        int o;
+    };
+    __device__ __forceinline__ H at(int bz, int br) const {
+        int dz = bz - fz0;
         if (dz < 0) dz += nz;
         else if (dz >= nz) dz -= nz;
-        return s[((f * 3 + c) * 3 + ch) * (SZ * SR) + (jr - fr0) * SZ + dz];
+        return H{(br - fr0) * SZ + dz};
+    }
+    __device__ __forceinline__ float get(const H& h, int f, int c, int ch, int a, int b) const {
+        return s[((f * 3 + c) * 3 + ch) * (SZ * SR) + h.o + b * SZ + a];
     }
 };
 
@@ -55,23 +74,34 @@ struct LField {
 struct GAcc {
     unsigned long long* a;
     int nz, ncell;
-    __device__ __forceinline__ void add(int ch, int iz, int jr, long long v) const {
+    struct H {
+        int bz, br;
+    };
+    __device__ __forceinline__ H at(int bz, int br) const { return H{bz, br}; }
+    __device__ __forceinline__ void add(const H& h, int ch, int da, int db, long long v) const {
+        const int jr = h.br + db;
         if (v == 0 || jr < 0 || jr >= ncell / nz) return;
+        int iz = h.bz + da;
         iz = iz < 0 ? iz + nz : (iz >= nz ? iz - nz : iz);
         atomicAdd(a + (size_t)ch * ncell + iz + nz * jr, (unsigned long long)v);
     }
 };
 
-// LDS int64 accumulator: [9][AR][AZ], origin (az0, ar0).
+// LDS int64 accumulator: [9][AR][AZ], origin (az0, ar0) (a zero adds nothing).
 struct LAcc {
     unsigned long long* a;
     int az0, ar0, nz, AZ, AR;
-    __device__ __forceinline__ void add(int ch, int iz, int jr, long long v) const {
-        if (v == 0) return;
-        int dz = iz - az0;
+    struct H {
+        int o;
+    };
+    __device__ __forceinline__ H at(int bz, int br) const {
+        int dz = bz - az0;
         if (dz < 0) dz += nz;
         else if (dz >= nz) dz -= nz;
-        atomicAdd(a + (ch * AR + (jr - ar0)) * AZ + dz, (unsigned long long)v);
+        return H{(br - ar0) * AZ + dz};
+    }
+    __device__ __forceinline__ void add(const H& h, int ch, int da, int db, long long v) const {
+        atomicAdd(a + ch * AR * AZ + h.o + db * AZ + da, (unsigned long long)v);
     }
 };
 
@@ -96,20 +126,17 @@ __device__ __forceinline__ int zw(int iz, float oz, bool half, float w[2]) {
     return iz - 1;
 }
 
-// One mode channel of one component at the particle: integer or half r nodes.
+// One mode channel of one component at the particle from the 2 x 2 nodes at
+// handle h.  wr: the radial weights with the axis ghost already folded in
+// (see circ_gather).
 template <class FA>
-__device__ __forceinline__ float interp(const FA& fa, int f, int c, int ch, int bz, const float wz[2], int br,
-                                        const float wr[2], float parity) {
+__device__ __forceinline__ float interp(const FA& fa, const typename FA::H& h, int f, int c, int ch,
+                                        const float wz[2], const float wr[2]) {
     float acc = 0.0f;
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-        const int j = br + b;
+    for (int b = 0; b < 2; ++b)
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
-            const float v = j < 0 ? parity * fa.get(f, c, ch, bz + a, 0) : fa.get(f, c, ch, bz + a, j);
-            acc = fmaf(wz[a] * wr[b], v, acc);
-        }
-    }
+        for (int a = 0; a < 2; ++a) acc = fmaf(wz[a] * wr[b], fa.get(h, f, c, ch, a, b), acc);
     return acc;
 }
 
@@ -125,12 +152,19 @@ __device__ __forceinline__ void circ_gather(const CircGeom& g, const FA& fa, int
     const float th = r * g.inv_dr - 0.5f;
     const int Kh = (int)floorf(th);
     const float sh = th - (float)Kh;
-    const float wrh[2] = {1.0f - sh, sh};
+    // half-r nodes below dr/2 (Kh = -1): the ghost at -dr/2 is the node at dr/2
+    // times the channel's axis parity, so its weight moves onto that node
+    const bool ghost = Kh < 0;
+    const float wrh[2] = {ghost ? 0.0f : 1.0f - sh, sh};
+    const float wrg_even[2] = {0.0f, ghost ? sh + (1.0f - sh) : sh};     // parity +1
+    const float wrg_odd[2] = {0.0f, ghost ? sh - (1.0f - sh) : sh};      // parity -1
     float wzi[2], wzh[2];
     const int bzi = zw(iz, oz, false, wzi);
     const int bzh = zw(iz, oz, true, wzh);
-    const float ct = r > 0.0f ? x / r : 1.0f;
-    const float st = r > 0.0f ? y / r : 0.0f;
+    const typename FA::H h_ii = fa.at(bzi, K), h_hi = fa.at(bzh, K), h_ih = fa.at(bzi, Kh), h_hh = fa.at(bzh, Kh);
+    const float inv_r = r > 0.0f ? 1.0f / r : 0.0f;
+    const float ct = r > 0.0f ? x * inv_r : 1.0f;
+    const float st = r > 0.0f ? y * inv_r : 0.0f;
     float comp[2][3];
 #pragma unroll
     for (int f = 0; f < 2; ++f) {
@@ -142,14 +176,14 @@ __device__ __forceinline__ void circ_gather(const CircGeom& g, const FA& fa, int
             const bool rhalf = f == 0 ? c == 1 : c != 1;
             // axis parity of the half-r ghost: r, th components odd for m 0 and even
             // for m 1; the z component the other way round
-            const float p0 = c == 0 ? 1.0f : -1.0f;
+            const bool z_comp = c == 0;
             const float* wz = zhalf ? wzh : wzi;
-            const int bz = zhalf ? bzh : bzi;
-            const float* wr = rhalf ? wrh : wri;
-            const int br = rhalf ? Kh : K;
-            const float v0 = interp(fa, f, c, 0, bz, wz, br, wr, p0);
-            const float v1 = interp(fa, f, c, 1, bz, wz, br, wr, -p0);
-            const float v2 = interp(fa, f, c, 2, bz, wz, br, wr, -p0);
+            const typename FA::H& h = zhalf ? (rhalf ? h_hh : h_hi) : (rhalf ? h_ih : h_ii);
+            const float* w0 = rhalf ? (ghost ? (z_comp ? wrg_even : wrg_odd) : wrh) : wri;   // m 0 channel
+            const float* w1 = rhalf ? (ghost ? (z_comp ? wrg_odd : wrg_even) : wrh) : wri;   // m 1 channels
+            const float v0 = interp(fa, h, f, c, 0, wz, w0);
+            const float v1 = interp(fa, h, f, c, 1, wz, w1);
+            const float v2 = interp(fa, h, f, c, 2, wz, w1);
             comp[f][c] = v0 + fmaf(v1, ct, v2 * st);
         }
     }
@@ -244,8 +278,10 @@ __device__ __forceinline__ void circ_deposit(const CircGeom& g, const AC& acc, f
     db[2] = b1[2] - b0[2];
     db[0] = -(db[1] + db[2]);
     // phases kappa exp(i th)
-    const float c0r = r0 > 0.0f ? 2.0f * (p0.x / r0) : 2.0f, c0i = r0 > 0.0f ? 2.0f * (p0.y / r0) : 0.0f;
-    const float c1r = r1 > 0.0f ? 2.0f * (p1.x / r1) : 2.0f, c1i = r1 > 0.0f ? 2.0f * (p1.y / r1) : 0.0f;
+    const float k0 = r0 > 0.0f ? 2.0f / r0 : 0.0f, k1 = r1 > 0.0f ? 2.0f / r1 : 0.0f;
+    const float c0r = r0 > 0.0f ? p0.x * k0 : 2.0f, c0i = r0 > 0.0f ? p0.y * k0 : 0.0f;
+    const float c1r = r1 > 0.0f ? p1.x * k1 : 2.0f, c1i = r1 > 0.0f ? p1.y * k1 : 0.0f;
+    const typename AC::H h = acc.at(bz, br);
     const float dcr = c1r - c0r, dci = c1i - c0i;
     const double qw = (double)(q * p0.w / g.dt) * 0x1p40;       // charge rate, fixed-point scaled (exact in FP64)
     // J_z flux along z at half nodes bz+ii+1/2 (the last is zero)
@@ -260,9 +296,9 @@ __device__ __forceinline__ void circ_deposit(const CircGeom& g, const AC& acc, f
             run0 = fmaf(da[ii], B0, run0);
             runr = fmaf(da[ii], xr, runr);
             runi = fmaf(da[ii], xi, runi);
-            acc.add(0, bz + ii, br + jj, fix_mul(-qw, run0));
-            acc.add(1, bz + ii, br + jj, fix_mul(-qw, runr));
-            acc.add(2, bz + ii, br + jj, fix_mul(-qw, runi));
+            acc.add(h, 0, ii, jj, fix_mul(-qw, run0));
+            acc.add(h, 1, ii, jj, fix_mul(-qw, runr));
+            acc.add(h, 2, ii, jj, fix_mul(-qw, runi));
         }
     }
     // J_r flux along r at half nodes br+jj+1/2 (the last is zero)
@@ -277,9 +313,9 @@ __device__ __forceinline__ void circ_deposit(const CircGeom& g, const AC& acc, f
             run0 = fmaf(db[jj], A0, run0);
             runr = fmaf(db[jj], xr, runr);
             runi = fmaf(db[jj], xi, runi);
-            acc.add(3, bz + ii, br + jj, fix_mul(-qw, run0));
-            acc.add(4, bz + ii, br + jj, fix_mul(-qw, runr));
-            acc.add(5, bz + ii, br + jj, fix_mul(-qw, runi));
+            acc.add(h, 3, ii, jj, fix_mul(-qw, run0));
+            acc.add(h, 4, ii, jj, fix_mul(-qw, runr));
+            acc.add(h, 5, ii, jj, fix_mul(-qw, runi));
         }
     }
     // m 1 azimuthal charge rate W_th (off the axis)
@@ -290,8 +326,8 @@ __device__ __forceinline__ void circ_deposit(const CircGeom& g, const AC& acc, f
         for (int ii = 0; ii < 3; ++ii) {
             const float wgt = fmaf(da[ii] * db[jj], 1.0f / 3.0f,
                                    fmaf(0.5f * a0[ii], db[jj], fmaf(0.5f * da[ii], b0[jj], a0[ii] * b0[jj])));
-            acc.add(7, bz + ii, br + jj, fix_mul(qw, dcr * wgt));
-            acc.add(8, bz + ii, br + jj, fix_mul(qw, dci * wgt));
+            acc.add(h, 7, ii, jj, fix_mul(qw, dcr * wgt));
+            acc.add(h, 8, ii, jj, fix_mul(qw, dci * wgt));
         }
     }
     // m 0 azimuthal current at the midpoint: q w v_th with the midpoint shapes
@@ -308,11 +344,12 @@ __device__ __forceinline__ void circ_deposit(const CircGeom& g, const AC& acc, f
         const float oz = zc - fz;
         const float fm = circ_fr(Km, sm);
         const float wzz[2] = {1.0f - oz, oz}, wrr[2] = {1.0f - fm, fm};
+        const typename AC::H hm = acc.at(izm, Km);
         const double qv = (double)(q * p0.w) * 0x1p40;
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
-            for (int a = 0; a < 2; ++a) acc.add(6, izm + a, Km + b, fix_mul(qv, vth * (wzz[a] * wrr[b])));
+            for (int a = 0; a < 2; ++a) acc.add(hm, 6, a, b, fix_mul(qv, vth * (wzz[a] * wrr[b])));
     }
 }
 
