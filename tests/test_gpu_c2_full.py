@@ -1,6 +1,6 @@
 """The C2 workload at its full size (Nz = 4096, Nr = 256, 32 particles per
 (z, r) cell, 3.3e7 particles), in the launch configuration the benchmark
-times (fused tile step, 512-thread tiles, a sort every 4 steps), checked
+times (fused tile step, 512-thread tiles, a sort every 16 steps), checked
 against the FP64 quasi-cylindrical oracle on sampled outputs:
 
 - after advancing to step 901 (the window has moved since step 800; the
