@@ -203,7 +203,9 @@ __device__ __forceinline__ void tile_body(const Geom& g, const TileGeom& t, int 
     float* Fl = reinterpret_cast<float*>(lds_u64 + 3 * jr);
 
     for (int i = threadIdx.x; i < 3 * jr; i += NT) Jl[i] = 0ull;
-    // stage E, B (tile + halo, periodic wrap in storage coordinates)
+    // stage E, B (tile + halo, periodic wrap in storage coordinates); note
+    // whether any staged value is other than +0
+    unsigned int bits = 0u;
     for (int i = threadIdx.x; i < fx * fy * fz; i += NT) {
         const int lz = i / (fx * fy);
         const int rr = i - lz * fx * fy;
@@ -217,11 +219,17 @@ __device__ __forceinline__ void tile_body(const Geom& g, const TileGeom& t, int 
         const int li = lz * fpl + rr;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            Fl[c * fr + li] = f.E[c][gi];
-            Fl[(3 + c) * fr + li] = f.B[c][gi];
+            const float e = f.E[c][gi], b = f.B[c][gi];
+            Fl[c * fr + li] = e;
+            Fl[(3 + c) * fr + li] = b;
+            bits |= __float_as_uint(e) | __float_as_uint(b);
         }
     }
-    __syncthreads();
+    // A cold tile: every staged field value is +0 (ahead of the laser).  There a
+    // particle with u = +0 gathers E = B = +0, and the push, move and deposit
+    // leave it exactly as it is (u stays +0, the offsets and the cell do not
+    // change, nothing moves so nothing is deposited): it is skipped.
+    const bool cold_tile = __syncthreads_or(bits != 0u) == 0;
 
     float* const El[3] = {Fl, Fl + fr, Fl + 2 * fr};
     float* const Bl[3] = {Fl + 3 * fr, Fl + 4 * fr, Fl + 5 * fr};
@@ -282,6 +290,13 @@ __device__ __forceinline__ void tile_body(const Geom& g, const TileGeom& t, int 
             if (lane == leader) base = atomicAdd(rest_n, __popcll(m));
             base = __shfl(base, leader);
             rest_idx[base + __popcll(m & ((1ull << lane) - 1ull))] = p;
+            continue;
+        }
+        if (cold_tile && (__float_as_uint(u[0]) | __float_as_uint(u[1]) | __float_as_uint(u[2])) == 0u) {
+            if (GATHER) {   // the particle still moves to its sorted place
+                s.cell[p] = cell;
+                keep_particle<GATHER>(s, p, o, u);
+            }
             continue;
         }
         const float o0[3] = {o[0], o[1], o[2]};
