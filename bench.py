@@ -343,7 +343,8 @@ def bench_c2(args):
     total = cfg["steps"]
     args.steps = args.steps or total - args.warmup
     t_setup = time.perf_counter()
-    sim = workloads.build_c2(cfg, sort_interval=args.sort_interval, interleave=args.interleave, threads=args.threads)
+    sim = workloads.build_c2(cfg, sort_interval=args.sort_interval, interleave=max(0, args.interleave),
+                             threads=args.threads)
     sim.sync()
     idx = timed_indices(total, args.warmup, args.steps, sim.desc.sort_interval or 2)
     print(f"# setup {time.perf_counter() - t_setup:.1f}s, window from step {workloads.c2_window_start(cfg)}, "
@@ -426,7 +427,8 @@ def main():
     ap.add_argument("--sort-interval", type=int, default=0)
     ap.add_argument("--guard", type=int, default=-1)
     ap.add_argument("--threads", type=int, default=0)
-    ap.add_argument("--interleave", type=int, default=0, help="sort transpose depth (default: tuned / library)")
+    ap.add_argument("--interleave", type=int, default=-1,
+                    help="in-tile order of the sort: 0 level order, D >= 1 the transpose depth (default: tuned / library)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-json", type=str, default="", help="per-launch HBM bytes from rocprofv3 counters")
     ap.add_argument("--workload", type=str, default="c1", choices=["c1", "c1p", "c2", "c3", "c4"],
@@ -514,7 +516,7 @@ def bench_c1(args):
         tiling["guard"] = args.guard
     if args.threads:
         tiling["threads"] = args.threads
-    if args.interleave:
+    if args.interleave >= 0:
         tiling["interleave"] = args.interleave
     t_setup = time.perf_counter()
     sim = workloads.build(cfg, **tiling)
@@ -599,7 +601,7 @@ def bench_c1(args):
             "cells": ncell,
             "tiling": {"tile": [sim.desc.tile[a] or 8 for a in range(3)],
                        "guard": sim.desc.guard if sim.desc.guard >= 0 else 1,
-                       "threads": sim.desc.threads or 512, "interleave": sim.desc.interleave or 8,
+                       "threads": sim.desc.threads or 512, "interleave": sim.desc.interleave,
                        "sort_interval": sim.desc.sort_interval or 2,
                        "source": "explicit" if tiling else "autotune cache or library default"},
         },

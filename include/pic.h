@@ -99,10 +99,13 @@ enum { PIC_JPOST_NONE = 0, PIC_JPOST_BINOMIAL = 1, PIC_JPOST_DENOISER = 2 };
  *                PF = (Tx + 2 guard + 4)(Ty + 2 guard + 4) are padded up to
  *                8 mod 16 and 8 mod 32 words (150,720 B for 8x8x8, guard 1).
  *   threads      threads per tile workgroup (256, 512 or 1024; 0 = 512).
- *   interleave   depth D of the sort's in-tile block transpose: each full
- *                block of 64 D cell-sorted particles is stored D x 64
- *                transposed so a wavefront's lanes hold different cells
- *                (0 = default 8, 1 = plain cell order). */
+ *   interleave   order of the particles inside a tile after a sort.
+ *                0 (default): level order -- level r holds the (r+1)-th
+ *                particle of every cell that has one, cells in key order,
+ *                levels one after another, so a wavefront's lanes hold
+ *                different cells at any density.  D >= 1: each full block
+ *                of 64 D cell-sorted particles is stored D x 64 transposed
+ *                (lanes D apart in cell order; 1 = plain cell order). */
 typedef struct {
     int32_t n[3];
     int32_t solver;
@@ -256,9 +259,10 @@ pic_status pic_step(pic_ctx *ctx, int32_t nsteps);
  * Not part of the paper's method: a data layout of this library (particles
  * of one tile are contiguous so the fused step can stage the tile's fields
  * and current in on-chip memory); it changes no result.
- * Tiles of 8 x 2m x 4k cells are stored in 8x2x4-cell bricks (x fastest,
- * then z, then y inside a brick), other tiles in x-fastest cell order; then
- * the in-tile block transpose of the tiling's interleave depth.  The
+ * Tiles of 8 x 2m x 4k cells are keyed in 8x2x4-cell bricks (x fastest,
+ * then z, then y inside a brick), other tiles in x-fastest cell order; the
+ * particles of a tile are then stored in the order the tiling's interleave
+ * selects (level order, or a block transpose).  The
  * species' data may move to the workspace copy (see pic_species_view).
  * Asynchronous. */
 pic_status pic_sort(pic_ctx *ctx, int32_t species);

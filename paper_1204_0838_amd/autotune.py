@@ -26,12 +26,12 @@ import time
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "autotune_cache.json")
 
-DEFAULT = {"tile": (8, 8, 8), "guard": 1, "threads": 512, "interleave": 8, "sort_interval": 2}
+DEFAULT = {"tile": (8, 8, 8), "guard": 1, "threads": 512, "interleave": 0, "sort_interval": 2}
 SPACE = {
     "tile": [(8, 8, 8), (8, 8, 4), (8, 4, 4), (16, 8, 4), (16, 4, 4), (4, 4, 4), (16, 8, 8)],
     "guard": [0, 1, 2],
     "threads": [256, 512, 1024],
-    "interleave": [1, 4, 8, 16],
+    "interleave": [0, 1, 8, 16],   # 0: level order, else the transpose depth
     "sort_interval": [1, 2, 3, 4],
 }
 

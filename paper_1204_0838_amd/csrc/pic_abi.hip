@@ -45,7 +45,7 @@ Tiling tiling_of(const pic_grid_desc* d) {
     r.t.tcells = r.t.T[0] * r.t.T[1] * r.t.T[2];
     r.guard = d->guard < 0 ? 1 : d->guard;
     r.threads = d->threads > 0 ? d->threads : 512;
-    r.interleave = d->interleave > 0 ? d->interleave : 8;
+    r.interleave = d->interleave > 0 ? d->interleave : 0;   // 0: level order
     r.sort_interval = d->sort_interval > 0 ? d->sort_interval : 2;
     return r;
 }
@@ -53,7 +53,7 @@ Tiling tiling_of(const pic_grid_desc* d) {
 // Device workspace carve-up.  Per-particle arrays have max_particles entries;
 // species take consecutive sub-ranges of them.
 struct Layout {
-    size_t acc, jtmp, rho, small, prev_cell, prev_off, alt_cell, alt_off, alt_u, alt_w, alt_id, sort_rank, hist,
+    size_t acc, jtmp, rho, small, prev_cell, prev_off, alt_cell, alt_off, alt_u, alt_w, alt_id, sort_rank, hist, sort_lc,
         sums, toff, toff_stride, dn_w, dn_h1, dn_h2, diag, total;
 };
 
@@ -137,6 +137,7 @@ Layout layout(const pic_grid_desc* d, int64_t maxp) {
     L.alt_id = take((size_t)maxp * 4);
     L.sort_rank = take((size_t)maxp * 4);
     L.hist = take(((size_t)nkeys + 1) * 4);
+    L.sort_lc = take((size_t)nkeys * 4);
     L.sums = take((((size_t)nkeys + 1 + 1023) / 1024 + 1) * 4);
     L.toff_stride = align_up(((size_t)max_tiles(d) + 1) * 4);
     L.toff = take(kMaxSpecies * L.toff_stride);
@@ -394,6 +395,9 @@ FieldPtrs fields_of(pic_ctx* c) {
 
 unsigned long long* acc_of(pic_ctx* c) { return reinterpret_cast<unsigned long long*>(c->ws + c->L.acc); }
 int* hist_of(pic_ctx* c) { return reinterpret_cast<int*>(c->ws + c->L.hist); }
+// The level-order sort's scratch (one int per particle slot of the species):
+// the split path's saved positions, which every sort invalidates anyway.
+int* level_of(pic_ctx* c, const Species& sp) { return reinterpret_cast<int*>(c->ws + c->L.prev_cell) + sp.base; }
 int* toff_of(pic_ctx* c, int32_t s) { return reinterpret_cast<int*>(c->ws + c->L.toff + (size_t)s * c->L.toff_stride); }
 
 void jtmp_of(pic_ctx* c, float* out[3]) {
@@ -525,7 +529,8 @@ pic_status sort_species(pic_ctx* c, int32_t s, bool copy) {
     int* rank = reinterpret_cast<int*>(c->ws + c->L.sort_rank) + sp.base;
     HIPCHK(c, launch_sort(c->g, c->tl.t, dev_from(c, sp, sp.cur), dev_from(c, sp, sp.alt), &sm->count[s],
                           &sm->sorted[s], (int)sp.bound, hist_of(c), rank, reinterpret_cast<int*>(c->ws + c->L.sums),
-                          c->tl.interleave, toff_of(c, s), copy, c->stream));
+                          level_of(c, sp), reinterpret_cast<int*>(c->ws + c->L.sort_lc), c->tl.interleave,
+                          toff_of(c, s), copy, sp.sorted, c->stream));
     std::swap(sp.cur, sp.alt);
     sp.sorted = true;
     sp.sort_step = c->step;
@@ -760,6 +765,7 @@ void fill_desc(pic_ctx* c, int32_t s, InstDesc& d) {
     d.toff = toff_of(c, s);
     d.rank = reinterpret_cast<int*>(c->ws + c->L.sort_rank) + sp.base;
     d.sums = reinterpret_cast<int*>(c->ws + c->L.sums);
+    d.level = level_of(c, sp);
     d.acc = acc_of(c);
     Small* sm = small_of(c);
     d.err = &sm->err;
@@ -842,7 +848,7 @@ pic_status batch_one_step(pic_batch* b) {
     for (int32_t s = 0; s < b->nsp; ++s) {
         int total = 0;
         PICCHK(upload_tables(b, s, &dtab, &dbegin, &total));
-        int max_sort = 0, max_keys1 = 0, max_tiles1 = 0;
+        int max_sort = 0, max_keys1 = 0, max_tiles1 = 0, max_tcells = 1;
         bool any_sort = false, all_888g1 = true;
         size_t lds = 0;
         for (int i = 0; i < n; ++i) {
@@ -854,6 +860,7 @@ pic_status batch_one_step(pic_batch* b) {
                 max_sort = (int)std::max<int64_t>(max_sort, sp.bound);
                 max_keys1 = std::max(max_keys1, c->tl.t.ntiles * c->tl.t.tcells + 1);
                 max_tiles1 = std::max(max_tiles1, c->tl.t.ntiles + 1);
+                max_tcells = std::max(max_tcells, c->tl.t.tcells);
                 std::swap(sp.cur, sp.alt);
                 sp.sorted = true;
                 sp.sort_step = c->step;
@@ -865,7 +872,7 @@ pic_status batch_one_step(pic_batch* b) {
         hipEvent_t t0, t1, t2;
         if (any_sort) {
             PICCHK(bmark(b, &t0));
-            BHIPCHK(b, launch_batch_sort(dtab, n, max_sort, max_keys1, max_tiles1, b->stream));
+            BHIPCHK(b, launch_batch_sort(dtab, n, max_sort, max_keys1, max_tiles1, max_tcells, b->stream));
             PICCHK(bend(b, PH_SORT, t0));
             if (b->prof.on) b->prof.sorts += 1;
         }

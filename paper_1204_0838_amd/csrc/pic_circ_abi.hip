@@ -507,7 +507,8 @@ pic_status pic_circ_step(pic_circ_ctx* c, int32_t nsteps) {
                 int* rank = reinterpret_cast<int*>(c->ws + c->L.rank) + sp.base;
                 CHIP(c, launch_sort(sort_geom(c), c->t, cdev(c, sp, sp.cur), cdev(c, sp, sp.alt), &sm->count[s],
                                     &sm->sorted[s], (int)sp.bound, reinterpret_cast<int*>(c->ws + c->L.hist), rank,
-                                    reinterpret_cast<int*>(c->ws + c->L.sums), c->desc.interleave, ctoff(c, s), true,
+                                    reinterpret_cast<int*>(c->ws + c->L.sums), nullptr, nullptr, c->desc.interleave, ctoff(c, s),
+                                    true, false,
                                     c->stream));
                 std::swap(sp.cur, sp.alt);
                 sp.sorted = true;

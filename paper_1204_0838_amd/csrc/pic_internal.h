@@ -88,7 +88,7 @@ struct InstDesc {
     TileGeom t;
     int guard;
     int pd;                  // perfect-dispersion smoothing in the B update
-    int depth;               // in-tile block transpose of the sort
+    int depth;               // in-tile order of the sort (0: levels, else the block-transpose depth)
     int nkeys;               // sort keys (t.ntiles * t.tcells)
     SortDiv sdiv;            // the sort's divisors for g and t
     PDCoef c;
@@ -103,6 +103,7 @@ struct InstDesc {
     int* toff;               // tile ranges of the species (written by its sort)
     int* rank;
     int* sums;
+    int* level;              // level-order places of a depth-0 sort (member scratch, max_particles ints)
     unsigned long long* acc;
     int* err;
     int* count;              // particles in the arrays
@@ -131,7 +132,7 @@ __host__ __device__ inline const SpeciesDev& step_arrays(const InstDesc& d) { re
 // batched kernels: one launch per phase over `n` members (grid y = member,
 // except the tile step, whose work list is the concatenation of all tiles)
 hipError_t launch_batch_sort(const InstDesc* d, int n, int max_particles, int max_keys1, int max_tiles1,
-                             hipStream_t st);
+                             int max_tcells, hipStream_t st);
 // all_888g1: every member tiles 8x8x8 with guard 1 (the compile-time tile body)
 hipError_t launch_batch_tile(const InstDesc* d, const int* tile_begin, int n, int total_tiles, int threads,
                              size_t lds_bytes, bool all_888g1, hipStream_t st);
@@ -189,12 +190,16 @@ hipError_t launch_jfinal(const Geom& g, unsigned long long* acc, float* const J[
 
 // sort (pic_sort.hip): src -> dst, new count into d_count and d_sorted, tile
 // ranges into toff (t.ntiles + 1 entries); hist, rank, sums are scratch.
-// depth: in-tile block-transpose depth (1 = plain cell order).  copy = false
-// leaves only each destination's source index in dst.cell: the next tile
-// step (launch_pic_tile with src) then gathers the particles itself.
+// depth: 0 = level order inside a tile (level: scratch of max_count ints),
+// else the in-tile block-transpose depth (1 = plain cell order; level
+// unused).  copy = false leaves only each destination's source index in
+// dst.cell: the next tile step (launch_pic_tile with src) then gathers the
+// particles itself.  resort: particles [0, *d_sorted) still occupy the tile
+// ranges toff of the last sort with this tiling (counted tile by tile; lc:
+// scratch of t.ntiles * t.tcells ints).
 hipError_t launch_sort(const Geom& g, const TileGeom& t, const SpeciesDev& src, const SpeciesDev& dst,
-                       int* d_count, int* d_sorted, int max_count, int* hist, int* rank, int* sums, int depth,
-                       int* toff, bool copy, hipStream_t st);
+                       int* d_count, int* d_sorted, int max_count, int* hist, int* rank, int* sums, int* level,
+                       int* lc, int depth, int* toff, bool copy, bool resort, hipStream_t st);
 
 // fused tile kernel (pic_tile.hip)
 size_t tile_lds_bytes(const TileGeom& t, int guard);

@@ -89,19 +89,52 @@ __device__ __forceinline__ bool moved(const int c0[3], const int c1[3], const fl
 // with P_x the running sum of dS_x along x and M = S0 + dS/2 (this product form
 // equals dS_x (S0y S0z + dSy S0z/2 + S0y dSz/2 + dSy dSz/3) summed along x).
 // Emit::add(comp, jx, jy, jz, k) receives each contribution as the int64
-// k = round(2^40 (-q w) P Y) (the FP32 factors (-q w 2^40) Y and P multiplied
-// exactly and rounded once), (jx, jy, jz) being union-node indices 0..4 along
-// x, y, z.
+// k = round(2^40 (-q w) P Y), (jx, jy, jz) being union-node indices 0..4
+// along x, y, z: the FP32 factor Q = 2^40 (-q w) Y is formed as
+// fma((Q0 / 12) dS_y[b], dS_z[c], (Q0 M_y[b]) M_z[c]), Q0 = 2^40 (-q w), with
+// the two scaled arrays of the first transverse axis computed once per
+// component, and Q and P are multiplied exactly and rounded once.
 // Callers skip particles that did not move (every contribution is zero).
-template <class Emit>
+//
+// CELLREL: the indices passed to Emit::add are slots relative to the old
+// cell instead of union nodes.  Along an axis transverse to the component,
+// slots 0..3 are the nodes at cell - 1 .. cell + 2 whatever the crossing and
+// slot 4 is the node a crossing adds (cell + 3 forward, cell - 2 backward);
+// along the component's own axis slots 0..2 are cell - 1 .. cell + 1 and
+// slot 3 is cell + 2 (forward) or cell - 2 (backward).  A backward crossing
+// (union base -2) just rotates its arrays by one place, so every value goes
+// to the same node as with union indices, bit for bit.
+__device__ __forceinline__ void rotate_back5(bool back, float v[5]) {
+    const float v0 = v[0];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = back ? v[j + 1] : v[j];
+    v[4] = back ? v0 : v[4];
+}
+
+__device__ __forceinline__ void rotate_back4(bool back, float v[4]) {
+    const float v0 = v[0];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) v[j] = back ? v[j + 1] : v[j];
+    v[3] = back ? v0 : v[3];
+}
+
+template <bool CELLREL = false, class Emit>
 __device__ __forceinline__ void esirkepov(const Axis5 A[3], float qw, Emit& em) {
-    // (qw Y) 2^40 == (qw 2^40) Y bit for bit: scaling by a power of two is exact
-    const float qw40 = qw * PIC_FIX_SCALE;
-    float M[3][5];
+    const float qw40 = qw * PIC_FIX_SCALE;   // exact: a power-of-two scale
+    const float qw12 = qw40 * (1.0f / 12.0f);
+    float M[3][5], dS[3][5];
 #pragma unroll
-    for (int d = 0; d < 3; ++d)
+    for (int d = 0; d < 3; ++d) {
 #pragma unroll
-        for (int j = 0; j < 5; ++j) M[d][j] = fmaf(0.5f, A[d].dS[j], A[d].S0[j]);
+        for (int j = 0; j < 5; ++j) {
+            M[d][j] = fmaf(0.5f, A[d].dS[j], A[d].S0[j]);
+            dS[d][j] = A[d].dS[j];
+        }
+        if (CELLREL) {
+            rotate_back5(A[d].base < -1, M[d]);
+            rotate_back5(A[d].base < -1, dS[d]);
+        }
+    }
 #pragma unroll
     for (int comp = 0; comp < 3; ++comp) {
         const int t1 = comp == 0 ? 1 : (comp == 1 ? 2 : 0);
@@ -110,18 +143,24 @@ __device__ __forceinline__ void esirkepov(const Axis5 A[3], float qw, Emit& em) 
         P[0] = A[comp].dS[0];
 #pragma unroll
         for (int a = 1; a < 4; ++a) P[a] = P[a - 1] + A[comp].dS[a];
+        if (CELLREL) rotate_back4(A[comp].base < -1, P);
         double Pd[4];
 #pragma unroll
         for (int a = 0; a < 4; ++a) Pd[a] = (double)P[a];
         const int la = A[comp].len - 1, lb = A[t1].len, lc = A[t2].len;
+        float Mq[5], dSq[5];
+#pragma unroll
+        for (int b = 0; b < 5; ++b) {
+            Mq[b] = qw40 * M[t1][b];
+            dSq[b] = qw12 * dS[t1][b];
+        }
 #pragma unroll
         for (int cc = 0; cc < 5; ++cc) {
             if (cc >= lc) continue;
 #pragma unroll
             for (int b = 0; b < 5; ++b) {
                 if (b >= lb) continue;
-                const float Y = fmaf(A[t1].dS[b] * A[t2].dS[cc], 1.0f / 12.0f, M[t1][b] * M[t2][cc]);
-                const double qy = (double)(qw40 * Y);
+                const double qy = (double)fmaf(dSq[b], dS[t2][cc], Mq[b] * M[t2][cc]);
 #pragma unroll
                 for (int a = 0; a < 4; ++a) {
                     if (a >= la) continue;

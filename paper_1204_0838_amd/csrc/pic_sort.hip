@@ -11,14 +11,19 @@
 // particle through the source index and writes all its arrays), which saves
 // the copy pass's read and write of every particle.
 //
-// Inside a tile the cell-sorted sequence is stored block-transposed: each full
-// block of 64*D particles (D = the interleave depth) is written as a D x 64
-// transpose, so the 64 lanes of a wavefront that reads the block in order see
-// particles D apart in cell order -- different cells at D >= particles per
-// cell -- and their LDS current atomics rarely hit the same address, while
-// the loads stay coalesced.  Particles that kept their cell since the last
-// sort mostly keep their place (the histogram hands out ranks in row order),
-// so the gather is close to a streaming copy.
+// Order inside a tile.  Depth 0 (level order): level r holds the (r + 1)-th
+// particle of every cell of the tile that has one, cells in key order, and
+// the levels follow each other; the 64 lanes of a wavefront that reads the
+// tile in order then sit in 64 distinct cells, consecutive cells of one
+// level, whatever the density (where cells hold unequal counts, a transpose
+// puts several lanes of one atomic pass in one cell, and LDS atomics to one
+// address serialise).  Depth D >= 1: the cell-sorted sequence is stored
+// block-transposed: each full block of 64*D particles is written as a D x 64
+// transpose, so the lanes see particles D apart in cell order (different
+// cells where a cell holds D particles); D = 1 is plain cell order.  Either
+// way the loads stay coalesced, and particles that kept their cell since the
+// last sort mostly keep their place, so the gather is close to a streaming
+// copy.
 #include "pic_internal.h"
 #include "pic_particle_ops.h"
 
@@ -60,21 +65,26 @@ __device__ __forceinline__ int sort_key(const Geom& g, const TileGeom& t, const 
     return tile_key(t, sd, c);
 }
 
-// Histogram and rank of the kCountRows particles p0 + 64 r (r = 0..7): after a
-// sort these are the rows of one lane of a transposed block, i.e. mostly the
+// Histogram and rank of the kCountRows particles p0 + S r (r = 0..7), S the
+// row stride: after a transposing sort (S = 64) these are the rows of one
+// lane of a transposed block, after a level-order sort (S = cells per tile)
+// the same cell on successive levels where the levels are full; mostly the
 // particles of one cell, so one atomic per distinct key serves them all and
 // the ranks follow the row order (particles that kept their cell then mostly
 // keep their place, which keeps the scatter's stores coalesced).  Any
 // grouping is correct: a rank is a place among the particles of one key.
 constexpr int kCountRows = 8;
 
+// foreign: the ranks are places among a key's incoming particles of a
+// re-sort (after the key's local ones, see k_sort_count_tiles): stored as
+// -2 - rank.
 __device__ __forceinline__ void count_column(const Geom& g, const TileGeom& t, const SortDiv& sd,
-                                             const int* __restrict__ cell, int p0,
+                                             const int* __restrict__ cell, int p0, int stride, bool foreign,
                                              int n, int* __restrict__ hist, int* __restrict__ rank) {
     int key[kCountRows];
 #pragma unroll
     for (int r = 0; r < kCountRows; ++r) {
-        const int p = p0 + 64 * r;
+        const int p = p0 + stride * r;
         key[r] = p < n ? sort_key(g, t, sd, cell[p]) : -2;
     }
     int rk[kCountRows];
@@ -93,21 +103,153 @@ __device__ __forceinline__ void count_column(const Geom& g, const TileGeom& t, c
     }
 #pragma unroll
     for (int r = 0; r < kCountRows; ++r) {
-        const int p = p0 + 64 * r;
-        if (p < n) rank[p] = rk[r];
+        const int p = p0 + stride * r;
+        if (p < n) rank[p] = foreign && rk[r] >= 0 ? -2 - rk[r] : rk[r];
     }
 }
 
-// Thread i counts the column p0 = (i / 64) * 512 + i % 64.
-__device__ __forceinline__ int column_of(int i) { return (i >> 6) * (64 * kCountRows) + (i & 63); }
+// Row stride of the count for a sort of the given depth, and the column of
+// thread i: p0 = (i / S) * 8 S + i % S.
+__host__ __device__ __forceinline__ int count_stride(const TileGeom& t, int depth) {
+    return depth == 0 ? t.tcells : 64;
+}
+__device__ __forceinline__ int column_of(int i, int stride) {
+    const int b = i / stride;
+    return b * (stride * kCountRows) + (i - b * stride);
+}
+// threads that cover n particles in whole blocks of columns
+inline int count_threads(int n, int stride) {
+    const int blk = stride * kCountRows;
+    return (n + blk - 1) / blk * stride;
+}
 
+// Columns over particles [*d_begin, *d_count) (d_begin null: from 0).
 __global__ void __launch_bounds__(256) k_sort_count(Geom g, TileGeom t, SortDiv sd, const int* __restrict__ cell,
-                                                    const int* __restrict__ d_count, int* __restrict__ hist,
+                                                    const int* __restrict__ d_begin, const int* __restrict__ d_count,
+                                                    int stride, int foreign, int* __restrict__ hist,
                                                     int* __restrict__ rank) {
-    const int p0 = column_of(blockIdx.x * blockDim.x + threadIdx.x);
+    const int p0 = (d_begin ? *d_begin : 0) + column_of(blockIdx.x * blockDim.x + threadIdx.x, stride);
     const int n = *d_count;
     if (p0 >= n) return;
-    count_column(g, t, sd, cell, p0, n, hist, rank);
+    count_column(g, t, sd, cell, p0, stride, foreign != 0, n, hist, rank);
+}
+
+// Count pass of a re-sort over the particles that the last sort put in tile
+// ranges: workgroup b takes tile b's old range [toff[b], toff[b + 1]).  Most
+// of them are still in that tile (they move less than a cell per step): they
+// are ranked in an LDS histogram of the tile's keys (local ranks 0 .. lc - 1,
+// lc[key] stored for every key of the tile), with no global atomic.  A
+// particle that left its tile (and every particle appended since the sort)
+// takes a place among the key's incoming particles from the global
+// histogram, stored as -2 - place, and goes after the key's local ones
+// (rank lc[key] + place, resolved by the scatter); removed ones get -1.  The
+// histogram then adds lc: every key's count is complete and every rank unique.
+constexpr int kTileCountThreads = 512;
+
+__global__ void __launch_bounds__(kTileCountThreads) k_sort_count_tiles(Geom g, TileGeom t, SortDiv sd,
+                                                                        const int* __restrict__ cell,
+                                                                        const int* __restrict__ toff,
+                                                                        int* __restrict__ hist, int* __restrict__ lc,
+                                                                        int* __restrict__ rank) {
+    extern __shared__ int lh[];   // t.tcells counters
+    const int tile = blockIdx.x;
+    const int k0 = tile * t.tcells;
+    for (int i = threadIdx.x; i < t.tcells; i += kTileCountThreads) lh[i] = 0;
+    __syncthreads();
+    const int b = toff[tile], e = toff[tile + 1];
+    for (int p = b + (int)threadIdx.x; p < e; p += kTileCountThreads) {
+        const int key = sort_key(g, t, sd, cell[p]);
+        int r = -1;
+        if ((unsigned)(key - k0) < (unsigned)t.tcells) r = atomicAdd(&lh[key - k0], 1);
+        else if (key >= 0) r = -2 - atomicAdd(&hist[key], 1);
+        rank[p] = r;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < t.tcells; i += kTileCountThreads) lc[k0 + i] = lh[i];
+}
+
+__global__ void __launch_bounds__(256) k_add_counts(int* __restrict__ hist, const int* __restrict__ lc, int nkeys) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nkeys) hist[i] += lc[i];
+}
+
+// Level order of one tile (depth 0).  The scatter has stored the tile's
+// source indices in plain cell order in `src` (off[key] is the first
+// cell-order place of a key, off[key + 1] - off[key] its count); this writes
+// them to `out` in level order: the (r + 1)-th particle of key k goes to the
+// tile's start, plus the sizes of levels 0..r-1, plus the number of keys
+// before k holding more than r particles.  Consecutive keys of a level write
+// consecutive places (coalesced stores); the tile's cell-order slice is read
+// through LDS when it fits.  One workgroup per tile; thread i owns keys
+// i per .. i per + per - 1; one barrier per level (the wave totals alternate
+// between two LDS rows).
+constexpr int kLevelThreads = 512;
+constexpr int kLevelMaxPer = 8;      // tiles of up to 4096 cells
+constexpr int kLevelStage = 8192;    // particles of a tile staged in LDS
+
+__device__ __forceinline__ void sort_levels_tile(const int* __restrict__ off, int tcells, const int* __restrict__ src,
+                                                 int* __restrict__ out, int tile) {
+    __shared__ int wsum[2][kLevelThreads / 64];
+    __shared__ int stage[kLevelStage];
+    const int base = tile * tcells;
+    const int per = (tcells + kLevelThreads - 1) / kLevelThreads;
+    const int k0 = (int)threadIdx.x * per;
+    const int tb = off[base];
+    const int n = off[base + tcells] - tb;
+    const bool staged = n <= kLevelStage;
+    if (staged)
+        for (int i = threadIdx.x; i < n; i += kLevelThreads) stage[i] = src[tb + i];
+    int start[kLevelMaxPer], cnt[kLevelMaxPer];
+    int cmax = 0;
+#pragma unroll
+    for (int j = 0; j < kLevelMaxPer; ++j) {
+        const int k = k0 + j;
+        start[j] = 0;
+        cnt[j] = 0;
+        if (j < per && k < tcells) {
+            start[j] = off[base + k] - tb;
+            cnt[j] = off[base + k + 1] - tb - start[j];
+            cmax = max(cmax, cnt[j]);
+        }
+    }
+    const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
+    int lbase = tb;
+    bool more = __syncthreads_or(cmax > 0) != 0;   // (also: the staged slice is complete)
+    for (int r = 0; more; ++r) {
+        int mine = 0;
+#pragma unroll
+        for (int j = 0; j < kLevelMaxPer; ++j) mine += cnt[j] > r;
+        int incl;   // inclusive prefix of `mine` over the wavefront
+        if (per == 1) {
+            incl = __popcll(__ballot(mine != 0) << (63 - lane));
+        } else {
+            incl = mine;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += y;
+            }
+        }
+        if (lane == 63) wsum[r & 1][wv] = incl;
+        more = __syncthreads_or(cmax > r + 1) != 0;
+        int before = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < kLevelThreads / 64; ++w) {
+            const int v = wsum[r & 1][w];
+            total += v;
+            before += w < wv ? v : 0;
+        }
+        int pos = lbase + before + incl - mine;
+#pragma unroll
+        for (int j = 0; j < kLevelMaxPer; ++j)
+            if (cnt[j] > r) out[pos++] = staged ? stage[start[j] + r] : src[tb + start[j] + r];
+        lbase += total;
+    }
+}
+
+__global__ void __launch_bounds__(kLevelThreads) k_sort_levels(const int* __restrict__ off, int tcells,
+                                                               const int* __restrict__ src, int* __restrict__ out) {
+    sort_levels_tile(off, tcells, src, out, blockIdx.x);
 }
 
 // Exclusive scan, phase 1: per-block totals of 1024-element blocks.
@@ -186,15 +328,21 @@ __global__ void __launch_bounds__(1024) k_scan_apply(const int* in, int n, const
     scan_apply_block(in, n, sums, out, blockIdx.x);
 }
 
+// Source index of particle p to its place: out[off[key] + rank] in cell
+// order (an incoming particle of a re-sort, rank -2 - place, after the key's
+// lc[key] local ones), then the block transpose of depth > 1.  Depth 0 (level
+// order) stores cell order here; the level pass reorders it.
 __device__ __forceinline__ void scatter_one(const Geom& g, const TileGeom& t, const SortDiv& sd,
-                                            const SpeciesDev& src, const SpeciesDev& dst, int p,
-                                            const int* __restrict__ rank, const int* __restrict__ off, int depth) {
-    const int r = rank[p];
-    if (r < 0) return;
-    const int cl = src.cell[p];   // a ranked particle has a live cell
+                                            const int* __restrict__ src_cell, int* __restrict__ out, int p,
+                                            const int* __restrict__ rank, const int* __restrict__ off,
+                                            const int* __restrict__ lc, int depth) {
+    int r = rank[p];
+    if (r == -1) return;
+    const int cl = src_cell[p];   // a ranked particle has a live cell
     int c[3];
     cell_coords(g, sd, cl, c);
     const int key = tile_key(t, sd, c);
+    if (r < -1) r = lc[key] + (-2 - r);
     int dest = off[key] + r;
     if (depth > 1) {
         const int tile = fdiv(key, sd.tcells);
@@ -216,7 +364,7 @@ __device__ __forceinline__ void scatter_one(const Geom& g, const TileGeom& t, co
             }
         }
     }
-    dst.cell[dest] = p;   // the source index; the gather replaces it with the particle
+    out[dest] = p;   // the source index; the gather replaces it with the particle
 }
 
 // Second pass of the permutation, over destinations: dst.cell[i] holds the
@@ -236,13 +384,14 @@ __device__ __forceinline__ void gather_one(const SpeciesDev& src, const SpeciesD
     dst.id[i] = src.id[p];
 }
 
-__global__ void __launch_bounds__(256) k_sort_scatter(Geom g, TileGeom t, SortDiv sd, SpeciesDev src,
-                                                      SpeciesDev dst, const int* __restrict__ d_count,
-                                                      const int* __restrict__ rank, const int* __restrict__ off,
+__global__ void __launch_bounds__(256) k_sort_scatter(Geom g, TileGeom t, SortDiv sd,
+                                                      const int* __restrict__ src_cell, int* __restrict__ out,
+                                                      const int* __restrict__ d_count, const int* __restrict__ rank,
+                                                      const int* __restrict__ off, const int* __restrict__ lc,
                                                       int depth) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= *d_count) return;
-    scatter_one(g, t, sd, src, dst, p, rank, off, depth);
+    scatter_one(g, t, sd, src_cell, out, p, rank, off, lc, depth);
 }
 
 __global__ void __launch_bounds__(256) k_sort_gather(SpeciesDev src, SpeciesDev dst, const int* __restrict__ off,
@@ -276,13 +425,23 @@ __global__ void __launch_bounds__(256) k_batch_zero_hist(const InstDesc* __restr
 
 __global__ void __launch_bounds__(256) k_batch_sort_count(const InstDesc* __restrict__ tab) {
     const InstDesc& d = tab[blockIdx.y];
-    const int p0 = column_of(blockIdx.x * blockDim.x + threadIdx.x);
     if (!d.sorting) return;
+    const TileGeom t = d.t;
+    const int stride = count_stride(t, d.depth);
+    const int p0 = column_of(blockIdx.x * blockDim.x + threadIdx.x, stride);
     const int n = *d.count;
     if (p0 >= n) return;
     const Geom g = d.g;
-    const TileGeom t = d.t;
-    count_column(g, t, d.sdiv, d.s.cell, p0, n, d.hist, d.rank);
+    count_column(g, t, d.sdiv, d.s.cell, p0, stride, false, n, d.hist, d.rank);
+}
+
+// Level order of the sorting members with depth 0 (after their scatter):
+// grid x = tile, y = member.
+__global__ void __launch_bounds__(kLevelThreads) k_batch_sort_levels(const InstDesc* __restrict__ tab) {
+    const InstDesc& d = tab[blockIdx.y];
+    if (!d.sorting || d.depth != 0 || (int)blockIdx.x >= d.t.ntiles) return;
+    // (the workgroup returns as a whole: the condition is uniform)
+    sort_levels_tile(d.hist, d.t.tcells, d.level, d.alt.cell, blockIdx.x);
 }
 
 __global__ void __launch_bounds__(1024) k_batch_scan_reduce(const InstDesc* __restrict__ tab) {
@@ -312,7 +471,7 @@ __global__ void __launch_bounds__(256) k_batch_sort_scatter(const InstDesc* __re
     const Geom g = d.g;
     const TileGeom t = d.t;
     const SpeciesDev src = d.s, dst = d.alt;
-    scatter_one(g, t, d.sdiv, src, dst, p, d.rank, d.hist, d.depth);
+    scatter_one(g, t, d.sdiv, src.cell, d.depth == 0 ? d.level : dst.cell, p, d.rank, d.hist, nullptr, d.depth);
 }
 
 __global__ void __launch_bounds__(256) k_batch_sort_finish(const InstDesc* __restrict__ tab) {
@@ -327,40 +486,57 @@ __global__ void __launch_bounds__(256) k_batch_sort_finish(const InstDesc* __res
 }
 
 hipError_t launch_batch_sort(const InstDesc* d, int n, int max_particles, int max_keys1, int max_tiles1,
-                             hipStream_t st) {
+                             int max_tcells, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     const int np = max_particles > 0 ? max_particles : 1;
     const int nb = (max_keys1 + 1023) / 1024;
     hipLaunchKernelGGL(k_batch_zero_hist, dim3((max_keys1 + 255) / 256, n), dim3(256), 0, st, d);
-    const int ncol = (np + kCountRows - 1) / kCountRows + 64;   // whole 512-particle blocks of columns
+    // enough columns for every member's stride S (64, or its cells per tile):
+    // whole blocks of 8 S rows need at most n / 8 + S threads
+    const int ncol = (np + kCountRows - 1) / kCountRows + std::max(max_tcells, 64);
     hipLaunchKernelGGL(k_batch_sort_count, dim3((ncol + 255) / 256, n), dim3(256), 0, st, d);
     hipLaunchKernelGGL(k_batch_scan_reduce, dim3(nb, n), dim3(1024), 0, st, d);
     hipLaunchKernelGGL(k_batch_scan_sums, dim3(1, n), dim3(1024), 0, st, d);
     hipLaunchKernelGGL(k_batch_scan_apply, dim3(nb, n), dim3(1024), 0, st, d);
     hipLaunchKernelGGL(k_batch_sort_scatter, dim3((np + 255) / 256, n), dim3(256), 0, st, d);
+    hipLaunchKernelGGL(k_batch_sort_levels, dim3(max_tiles1 - 1, n), dim3(kLevelThreads), 0, st, d);
     // (no copy pass: each sorting member's tile step gathers its particles)
     hipLaunchKernelGGL(k_batch_sort_finish, dim3((max_tiles1 + 255) / 256, n), dim3(256), 0, st, d);
     return hipGetLastError();
 }
 
 hipError_t launch_sort(const Geom& g, const TileGeom& t, const SpeciesDev& src, const SpeciesDev& dst,
-                       int* d_count, int* d_sorted, int max_count, int* hist, int* rank, int* sums, int depth,
-                       int* toff, bool copy, hipStream_t st) {
+                       int* d_count, int* d_sorted, int max_count, int* hist, int* rank, int* sums, int* level,
+                       int* lc, int depth, int* toff, bool copy, bool resort, hipStream_t st) {
     const int nkeys = t.ntiles * t.tcells;
+    if (depth == 0 && (level == nullptr || t.tcells > kLevelThreads * kLevelMaxPer)) return hipErrorInvalidValue;
+    if (resort && lc == nullptr) return hipErrorInvalidValue;
     hipError_t e = hipMemsetAsync(hist, 0, ((size_t)nkeys + 1) * sizeof(int), st);
     if (e != hipSuccess) return e;
     const int np = max_count > 0 ? max_count : 1;
-    const int ncol = (np + kCountRows - 1) / kCountRows + 64;   // whole 512-particle blocks of columns
+    const int stride = count_stride(t, depth);
+    const int ncol = count_threads(np, stride);
     const SortDiv sd = make_sortdiv(g, t);
-    hipLaunchKernelGGL(k_sort_count, dim3((ncol + 255) / 256), dim3(256), 0, st, g, t, sd, src.cell, d_count, hist,
-                       rank);
+    if (resort) {   // [0, *d_sorted) sit in the tile ranges toff of the last sort; appended ones after them
+        hipLaunchKernelGGL(k_sort_count_tiles, dim3(t.ntiles), dim3(kTileCountThreads), t.tcells * sizeof(int), st,
+                           g, t, sd, src.cell, toff, hist, lc, rank);
+        hipLaunchKernelGGL(k_sort_count, dim3((ncol + 255) / 256), dim3(256), 0, st, g, t, sd, src.cell, d_sorted,
+                           d_count, stride, 1, hist, rank);
+        hipLaunchKernelGGL(k_add_counts, dim3((nkeys + 255) / 256), dim3(256), 0, st, hist, lc, nkeys);
+    } else {
+        hipLaunchKernelGGL(k_sort_count, dim3((ncol + 255) / 256), dim3(256), 0, st, g, t, sd, src.cell, nullptr,
+                           d_count, stride, 0, hist, rank);
+    }
     const int n = nkeys + 1;
     const int nb = (n + 1023) / 1024;
     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(1024), 0, st, hist, n, sums);
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, sums, nb);
     hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(1024), 0, st, hist, n, sums, hist);
-    hipLaunchKernelGGL(k_sort_scatter, dim3((np + 255) / 256), dim3(256), 0, st, g, t, sd, src, dst, d_count, rank,
-                       hist, depth);
+    hipLaunchKernelGGL(k_sort_scatter, dim3((np + 255) / 256), dim3(256), 0, st, g, t, sd, src.cell,
+                       depth == 0 ? level : dst.cell, d_count, rank, hist, lc, depth);
+    if (depth == 0)
+        hipLaunchKernelGGL(k_sort_levels, dim3(t.ntiles), dim3(kLevelThreads), 0, st, hist, t.tcells, level,
+                           dst.cell);
     if (copy) hipLaunchKernelGGL(k_sort_gather, dim3((np + 255) / 256), dim3(256), 0, st, src, dst, hist, nkeys);
     hipLaunchKernelGGL(k_sort_finish, dim3(1), dim3(1), 0, st, hist, nkeys, d_count, d_sorted);
     hipLaunchKernelGGL(k_tile_offsets, dim3((t.ntiles + 1 + 255) / 256), dim3(256), 0, st, hist, t.tcells, t.ntiles,

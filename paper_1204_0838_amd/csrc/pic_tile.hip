@@ -33,12 +33,22 @@
 
 namespace pic {
 
+// LDS current tile, addressed by slots relative to the particle's old cell
+// (esirkepov<true>): every lane's atomics for slots 0..3 (0..2 along the
+// component's own axis) sit at its old cell plus the same offset, so lanes in
+// distinct cells stay in distinct banks whether or not, and which way, they
+// crossed a cell face; only the one extra slot of a crossing axis depends on
+// the direction.  M: transverse-axis slots, P: own-axis slots.
 struct LdsEmit {
     unsigned long long* J;   // LDS current tile, 3 components of jr nodes
     int jr;
-    int X[5], Y[5], Z[5];
+    int XM[5], YM[5], ZM[5];
+    int XP[5], YP[5], ZP[5];
     __device__ __forceinline__ void add(int comp, int jx, int jy, int jz, long long k) const {
-        atomicAdd(J + (comp * jr + X[jx] + Y[jy] + Z[jz]), (unsigned long long)k);
+        const int x = comp == 0 ? XP[jx] : XM[jx];
+        const int y = comp == 1 ? YP[jy] : YM[jy];
+        const int z = comp == 2 ? ZP[jz] : ZM[jz];
+        atomicAdd(J + (comp * jr + x + y + z), (unsigned long long)k);
     }
 };
 
@@ -329,13 +339,21 @@ __device__ __forceinline__ void tile_body(const Geom& g, const TileGeom& t, int 
         LdsEmit em;
         em.J = Jl;
         em.jr = jr;
+        {
+            int* const M[3] = {em.XM, em.YM, em.ZM};
+            int* const P[3] = {em.XP, em.YP, em.ZP};
 #pragma unroll
-        for (int j = 0; j < 5; ++j) {
-            em.X[j] = (lc[0] + guard + 2 + A[0].base + j) * jstride[0];
-            em.Y[j] = (lc[1] + guard + 2 + A[1].base + j) * jstride[1];
-            em.Z[j] = (lc[2] + guard + 2 + A[2].base + j) * jstride[2];
+            for (int d = 0; d < 3; ++d) {
+                const int n0 = lc[d] + guard + 2;   // the old cell's node
+                const bool back = A[d].base < -1;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) M[d][j] = P[d][j] = (n0 - 1 + j) * jstride[d];
+                M[d][4] = (n0 + (back ? -2 : 3)) * jstride[d];
+                P[d][3] = (n0 + (back ? -2 : 2)) * jstride[d];
+                P[d][4] = M[d][4];   // (never used)
+            }
         }
-        esirkepov(A, wq, em);
+        esirkepov<true>(A, wq, em);
     }
     if (errs) atomicOr(d_err, errs);
     __syncthreads();

@@ -40,7 +40,8 @@ CASES = [
     dict(tile=(8, 8, 8), guard=1, interleave=17, sort_interval=2, threads=512),
     dict(tile=(4, 4, 4), guard=0, interleave=1, sort_interval=3, threads=256),
     dict(tile=(8, 4, 4), guard=2, interleave=5, sort_interval=1, threads=1024),
-    dict(tile=(5, 3, 7), guard=1, interleave=17, sort_interval=4, threads=512),
+    dict(tile=(5, 3, 7), guard=1, interleave=0, sort_interval=4, threads=512),
+    dict(tile=(8, 8, 8), guard=1, interleave=0, sort_interval=3, threads=1024),
 ]
 
 
@@ -117,6 +118,43 @@ def _brick_key(c, n, T):
     tile = x // T[0] + nt[0] * (y // T[1] + nt[1] * (z // T[2]))
     lx, ly, lz = x % T[0], y % T[1], z % T[2]
     return tile, lx + 8 * (lz % 4) + 32 * (ly % 2) + 64 * (ly // 2 + (T[1] // 2) * (lz // 4))
+
+
+def test_sort_stores_tiles_in_level_order():
+    """Default storage (level order): inside each tile, level r holds the
+    (r + 1)-th particle of every cell with more than r particles, cells in
+    brick-key order, levels one after another -- checked slot by slot against
+    the order computed here from the cell counts, on a plasma of uneven
+    counts (Poisson per cell, one dense slab) with ragged tiles."""
+    grid = inputs.Grid(n=(24, 20, 16), d=(0.25, 0.5, 0.5), dt=0.25, solver="pd")
+    ncell = 24 * 20 * 16
+    rng = np.random.default_rng(46)
+    cell = rng.integers(0, ncell, 6 * ncell)                 # Poisson counts
+    slab = rng.integers(0, ncell, 6 * ncell)
+    cell = np.concatenate([cell, slab[(slab % 24 >= 8) & (slab % 24 < 12)]]).astype(np.int32)   # a dense slab
+    off = rng.random((3, cell.size)).astype(np.float32)
+    u = np.zeros((3, cell.size), np.float32)
+    w = np.full(cell.size, 0.1, np.float32)
+    ids = np.arange(cell.size, dtype=np.int32)
+    T = (8, 8, 8)
+    sim = pic.Simulation(grid.n, grid.d, grid.dt, solver="pd", tile=T, max_particles=cell.size)
+    sim.add_species(cell, off, u, w, ids)
+    sim.sort(0)
+    got = sim.particles_host(0)
+    assert np.array_equal(np.sort(got["id"]), ids)
+    tile, key = _brick_key(got["cell"].astype(np.int64), grid.n, T)
+    ct, ck = _brick_key(cell.astype(np.int64), grid.n, T)
+    want_t, want_k = [], []
+    for t in range(int(ct.max()) + 1):
+        cnt = np.bincount(ck[ct == t], minlength=512)
+        for r in range(int(cnt.max()) if cnt.size else 0):
+            ks = np.nonzero(cnt > r)[0]
+            want_t.append(np.full(ks.size, t))
+            want_k.append(ks)
+    per_cell = np.bincount(cell, minlength=ncell)
+    assert per_cell.max() > 2 * np.median(per_cell)              # counts are uneven
+    assert np.array_equal(tile, np.concatenate(want_t))
+    assert np.array_equal(key, np.concatenate(want_k))
 
 
 def test_sort_orders_tiles_in_bricks():
