@@ -3,13 +3,17 @@ workgroup, in-tile interleave depth and sort interval.
 
 It times ``pic_step`` on a live simulation for each candidate, switching the
 tiling with ``pic_set_tiling`` (which never changes results: the current is
-summed in integers), by coordinate descent from the default, and keeps the
-fastest measured ms/step.  Timed windows span a multiple of every sort
+summed in integers).  The default search (tune_phases) times every one-knob
+change of the default at several points of one run, since the cost of a
+step changes over the run, combines the knobs that help and checks the
+combination over a whole fresh run; ``--instant`` runs a coordinate descent
+at one instant instead.  Timed windows span a multiple of every sort
 interval so the sort cost is amortised fairly.  Results are cached in JSON
 keyed by grid shape, particles per cell and solver; ``bench.py`` and
 ``workloads.build`` read the cache.
 
-    python -m paper_1204_0838_amd.autotune --warmup 600 --steps 12
+    python -m paper_1204_0838_amd.autotune --phases 150,450,750 --steps 12
+    python -m paper_1204_0838_amd.autotune --instant --warmup 600 --steps 12
     python -m paper_1204_0838_amd.autotune --batch --warmup 60 --steps 6
 
 The batched form tunes the members of a parameter scan per instance-size
@@ -105,6 +109,111 @@ def tune(sim, steps: int = 12, rounds: int = 2, log=sys.stderr):
     sim.set_tiling(**best)
     table.sort(key=lambda r: r[1] / r[2])
     return best, best_ms, [(c, ms) for c, ms, _ in table]
+
+
+def knob_variants(base: dict) -> list:
+    """Every one-knob change of `base` to another value of SPACE that fits LDS."""
+    out = []
+    for knob, values in SPACE.items():
+        for v in values:
+            c = dict(base)
+            c[knob] = v
+            if c != base and feasible(c):
+                out.append(c)
+    return out
+
+
+def run_ms(cfg: dict, tiling: dict, steps: int, chunk: int = 20) -> float:
+    """Mean ms per step of a fresh run of `steps` steps from t = 0 with `tiling`."""
+    import torch
+
+    from . import workloads
+
+    sim = workloads.build(cfg, tuned=False, **tiling)
+    sim.sync()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    total = 0.0
+    done = 0
+    while done < steps:
+        k = min(chunk, steps - done)
+        e0.record(sim.stream)
+        sim.step(k)
+        e1.record(sim.stream)
+        sim.sync()
+        total += e0.elapsed_time(e1)
+        done += k
+    sim.close()
+    return total / steps
+
+
+def tune_phases(cfg: dict, phases=(150, 450, 750), steps: int = 12, base_every: int = 3, log=sys.stderr):
+    """Search over the whole run instead of one instant (the cost of a step
+    changes as the wake forms and particles move).
+
+    One run from t = 0 times, at each phase, every one-knob change of the
+    default (knob_variants) for `steps` steps, each against a fresh timing of
+    the default taken at most `base_every` candidates before it, as a ratio.
+    Each knob keeps its value of least mean ratio over the phases if that is
+    below 0.99; the knobs so chosen are combined, and the combination is kept
+    only if a full fresh run with it is faster than one with the default.
+    Returns (best, ms per step of best over the run, table of (candidate,
+    mean ratio, per-phase ratios), note)."""
+    from . import workloads
+
+    base = dict(DEFAULT)
+    cands = knob_variants(base)
+    ratios = {i: [] for i in range(len(cands))}
+    sim = workloads.build(cfg, tuned=False, **base)
+    done = 0
+    for ph in phases:
+        if ph < done:
+            raise ValueError("phases overlap: the timings of one phase reach past the start of the next")
+        while done < ph:
+            k = min(100, ph - done)
+            sim.step(k)
+            done += k
+        sim.sync()
+        ref = None
+        for i, c in enumerate(cands):
+            if i % base_every == 0:
+                ref = time_candidate(sim, base, steps)
+                done += steps + 1
+            ms = time_candidate(sim, c, steps)
+            done += steps + 1
+            ratios[i].append(ms / ref)
+            if log:
+                print(f"# phase {ph} (step {done}): {c} -> {ms:.3f} ms/step, default {ref:.3f}", file=log, flush=True)
+    sim.close()
+    table = []
+    for i, c in enumerate(cands):
+        r = ratios[i]
+        table.append((c, sum(r) / len(r), r))
+    best = dict(base)
+    for knob in SPACE:
+        rows = [(m, c) for c, m, _ in table if c[knob] != base[knob]]
+        if rows:
+            m, c = min(rows, key=lambda x: x[0])
+            if m < 0.99:
+                best[knob] = c[knob]
+    if not feasible(best):
+        best = min(table, key=lambda x: x[1])[0] if min(r[1] for r in table) < 0.99 else dict(base)
+    total = int(cfg.get("steps", 1000))
+    ms_base = run_ms(cfg, base, total)
+    note = f"one-knob changes of the default timed at steps {list(phases)} of one run ({steps} steps each)"
+    if best != base:
+        ms_best = run_ms(cfg, best, total)
+        if log:
+            print(f"# whole run: default {ms_base:.3f}, combined {best} {ms_best:.3f} ms/step", file=log, flush=True)
+        note += f"; whole {total}-step runs: combined {ms_best:.2f}, default {ms_base:.2f} ms per step"
+        if ms_best >= ms_base:
+            best, ms_best = dict(base), ms_base
+            note += " (default kept)"
+    else:
+        ms_best = ms_base
+        note += f"; no knob improved; whole run {ms_base:.2f} ms per step"
+    table.sort(key=lambda r: r[1])
+    return best, ms_best, table, note
 
 
 def class_key(cls: str, cfg: dict) -> str:
@@ -214,12 +323,19 @@ def save_classes(cfg: dict, best: dict, best_ms: float, note: str, path: str = C
 
 
 def save(cfg: dict, best: dict, best_ms: float, table, note: str, path: str = CACHE):
+    """table: (candidate, ms per step) or (candidate, mean ratio to the default, per-phase ratios)."""
     cache = {}
     if os.path.exists(path):
         with open(path) as f:
             cache = json.load(f)
-    cache[key_of(cfg)] = {"best": best, "ms_per_step": best_ms, "note": note,
-                          "measured": [{"tiling": c, "ms_per_step": ms} for c, ms in table[:12]]}
+    rows = []
+    for r in table[:16]:
+        if len(r) == 2:
+            rows.append({"tiling": r[0], "ms_per_step": r[1]})
+        else:
+            rows.append({"tiling": r[0], "ratio_to_default": round(r[1], 4),
+                         "phase_ratios": [round(v, 4) for v in r[2]]})
+    cache[key_of(cfg)] = {"best": best, "ms_per_step": best_ms, "note": note, "measured": rows}
     with open(path, "w") as f:
         json.dump(cache, f, indent=1)
 
@@ -230,6 +346,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=600)
     ap.add_argument("--steps", type=int, default=12)
     ap.add_argument("--batch", action="store_true", help="tune the C3 parameter scan per size class")
+    ap.add_argument("--instant", action="store_true",
+                    help="coordinate descent at one instant (--warmup) instead of the whole-run search")
+    ap.add_argument("--phases", type=str, default="150,450,750", help="steps of the run at which candidates are timed")
+    ap.add_argument("--workload", choices=("c1", "c1p"), default="c1")
     args = ap.parse_args()
     sys.path.insert(0, os.path.dirname(HERE))
     from paper_1204_0838_amd import workloads
@@ -247,9 +367,16 @@ def main():
         print(json.dumps({"best": best, "batch_ms_per_step": best_ms}))
         return
 
-    cfg = workloads.C1
+    cfg = workloads.C1P if args.workload == "c1p" else workloads.C1
     if args.grid:
         cfg = workloads.scaled(cfg, [int(v) for v in args.grid.split(",")])
+    if not args.instant:
+        t0 = time.perf_counter()
+        best, best_ms, table, note = tune_phases(cfg, tuple(int(v) for v in args.phases.split(",")), args.steps)
+        best["tile"] = list(best["tile"])
+        save(cfg, best, best_ms, table, note + f", {time.perf_counter() - t0:.0f} s")
+        print(json.dumps({"key": key_of(cfg), "best": best, "ms_per_step": best_ms}))
+        return
     sim = workloads.build(cfg, tuned=False)
     t0 = time.perf_counter()
     done = 0

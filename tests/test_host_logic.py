@@ -62,3 +62,24 @@ def test_binomial_start_is_the_filter():
 def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, "bench.py", "--gpus", "2"], capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_autotuner_knob_variants_change_one_knob_and_fit():
+    """The whole-run search times every one-knob change of the default that
+    fits in LDS: each variant differs from the default in exactly one knob,
+    every value of every knob appears unless it does not fit, and none
+    repeats the default."""
+    base = dict(autotune.DEFAULT)
+    vs = autotune.knob_variants(base)
+    seen = {k: set() for k in autotune.SPACE}
+    for c in vs:
+        diff = [k for k in autotune.SPACE if c[k] != base[k]]
+        assert len(diff) == 1
+        assert autotune.feasible(c)
+        seen[diff[0]].add(c[diff[0]] if diff[0] != "tile" else tuple(c["tile"]))
+    for k, values in autotune.SPACE.items():
+        for v in values:
+            c = dict(base)
+            c[k] = v
+            if c != base and autotune.feasible(c):
+                assert (tuple(v) if k == "tile" else v) in seen[k]
