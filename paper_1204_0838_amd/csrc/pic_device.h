@@ -116,14 +116,22 @@ __device__ __forceinline__ float interp3(const float* __restrict__ F, const int 
     float acc = 0.0f;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-        float accy = 0.0f;
+        // the 16 values of one z-plane are loaded before any is used, so their
+        // loads are in flight together
+        float v[4][4];
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             const float* row = F + (iz[c] + iy[b]);
-            float ax = wx[0] * row[ix[0]];
-            ax = fmaf(wx[1], row[ix[1]], ax);
-            ax = fmaf(wx[2], row[ix[2]], ax);
-            ax = fmaf(wx[3], row[ix[3]], ax);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) v[b][a] = row[ix[a]];
+        }
+        float accy = 0.0f;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            float ax = wx[0] * v[b][0];
+            ax = fmaf(wx[1], v[b][1], ax);
+            ax = fmaf(wx[2], v[b][2], ax);
+            ax = fmaf(wx[3], v[b][3], ax);
             accy = fmaf(wy[b], ax, accy);
         }
         acc = fmaf(wz[c], accy, acc);
