@@ -766,6 +766,8 @@ void fill_desc(pic_ctx* c, int32_t s, InstDesc& d) {
     d.rank = reinterpret_cast<int*>(c->ws + c->L.sort_rank) + sp.base;
     d.sums = reinterpret_cast<int*>(c->ws + c->L.sums);
     d.level = level_of(c, sp);
+    d.lc = reinterpret_cast<int*>(c->ws + c->L.sort_lc);
+    d.resort = d.sorting && sp.sorted;   // (the batch step marks the species sorted after this)
     d.acc = acc_of(c);
     Small* sm = small_of(c);
     d.err = &sm->err;

@@ -104,6 +104,8 @@ struct InstDesc {
     int* rank;
     int* sums;
     int* level;              // level-order places of a depth-0 sort (member scratch, max_particles ints)
+    int* lc;                 // per-key local counts of a re-sort (member scratch, nkeys ints)
+    int resort;              // 1: the sort's particles [0, *sorted) still sit in the tile ranges toff
     unsigned long long* acc;
     int* err;
     int* count;              // particles in the arrays

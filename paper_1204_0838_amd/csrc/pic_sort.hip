@@ -146,13 +146,10 @@ __global__ void __launch_bounds__(256) k_sort_count(Geom g, TileGeom t, SortDiv 
 // histogram then adds lc: every key's count is complete and every rank unique.
 constexpr int kTileCountThreads = 512;
 
-__global__ void __launch_bounds__(kTileCountThreads) k_sort_count_tiles(Geom g, TileGeom t, SortDiv sd,
-                                                                        const int* __restrict__ cell,
-                                                                        const int* __restrict__ toff,
-                                                                        int* __restrict__ hist, int* __restrict__ lc,
-                                                                        int* __restrict__ rank) {
-    extern __shared__ int lh[];   // t.tcells counters
-    const int tile = blockIdx.x;
+__device__ __forceinline__ void count_tile(const Geom& g, const TileGeom& t, const SortDiv& sd,
+                                           const int* __restrict__ cell, const int* __restrict__ toff,
+                                           int* __restrict__ hist, int* __restrict__ lc, int* __restrict__ rank,
+                                           int tile, int* lh) {
     const int k0 = tile * t.tcells;
     for (int i = threadIdx.x; i < t.tcells; i += kTileCountThreads) lh[i] = 0;
     __syncthreads();
@@ -166,6 +163,15 @@ __global__ void __launch_bounds__(kTileCountThreads) k_sort_count_tiles(Geom g, 
     }
     __syncthreads();
     for (int i = threadIdx.x; i < t.tcells; i += kTileCountThreads) lc[k0 + i] = lh[i];
+}
+
+__global__ void __launch_bounds__(kTileCountThreads) k_sort_count_tiles(Geom g, TileGeom t, SortDiv sd,
+                                                                        const int* __restrict__ cell,
+                                                                        const int* __restrict__ toff,
+                                                                        int* __restrict__ hist, int* __restrict__ lc,
+                                                                        int* __restrict__ rank) {
+    extern __shared__ int lh[];   // t.tcells counters
+    count_tile(g, t, sd, cell, toff, hist, lc, rank, blockIdx.x, lh);
 }
 
 __global__ void __launch_bounds__(256) k_add_counts(int* __restrict__ hist, const int* __restrict__ lc, int nkeys) {
@@ -423,16 +429,35 @@ __global__ void __launch_bounds__(256) k_batch_zero_hist(const InstDesc* __restr
     d.hist[i] = 0;
 }
 
+// Columns of the members that sort: all particles, or for a re-sort those
+// appended since the last one (after the member's tile-by-tile count).
 __global__ void __launch_bounds__(256) k_batch_sort_count(const InstDesc* __restrict__ tab) {
     const InstDesc& d = tab[blockIdx.y];
     if (!d.sorting) return;
     const TileGeom t = d.t;
     const int stride = count_stride(t, d.depth);
-    const int p0 = column_of(blockIdx.x * blockDim.x + threadIdx.x, stride);
+    const int p0 = (d.resort ? *d.sorted : 0) + column_of(blockIdx.x * blockDim.x + threadIdx.x, stride);
     const int n = *d.count;
     if (p0 >= n) return;
     const Geom g = d.g;
-    count_column(g, t, d.sdiv, d.s.cell, p0, stride, false, n, d.hist, d.rank);
+    count_column(g, t, d.sdiv, d.s.cell, p0, stride, d.resort != 0, n, d.hist, d.rank);
+}
+
+// Tile-by-tile count of the members that re-sort: grid x = tile, y = member.
+__global__ void __launch_bounds__(kTileCountThreads) k_batch_sort_count_tiles(const InstDesc* __restrict__ tab) {
+    extern __shared__ int lh[];
+    const InstDesc& d = tab[blockIdx.y];
+    if (!d.sorting || !d.resort || (int)blockIdx.x >= d.t.ntiles) return;   // (uniform per workgroup)
+    const Geom g = d.g;
+    const TileGeom t = d.t;
+    count_tile(g, t, d.sdiv, d.s.cell, d.toff, d.hist, d.lc, d.rank, blockIdx.x, lh);
+}
+
+__global__ void __launch_bounds__(256) k_batch_add_counts(const InstDesc* __restrict__ tab) {
+    const InstDesc& d = tab[blockIdx.y];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (!d.sorting || !d.resort || i >= d.nkeys) return;
+    d.hist[i] += d.lc[i];
 }
 
 // Level order of the sorting members with depth 0 (after their scatter):
@@ -471,7 +496,7 @@ __global__ void __launch_bounds__(256) k_batch_sort_scatter(const InstDesc* __re
     const Geom g = d.g;
     const TileGeom t = d.t;
     const SpeciesDev src = d.s, dst = d.alt;
-    scatter_one(g, t, d.sdiv, src.cell, d.depth == 0 ? d.level : dst.cell, p, d.rank, d.hist, nullptr, d.depth);
+    scatter_one(g, t, d.sdiv, src.cell, d.depth == 0 ? d.level : dst.cell, p, d.rank, d.hist, d.lc, d.depth);
 }
 
 __global__ void __launch_bounds__(256) k_batch_sort_finish(const InstDesc* __restrict__ tab) {
@@ -494,7 +519,10 @@ hipError_t launch_batch_sort(const InstDesc* d, int n, int max_particles, int ma
     // enough columns for every member's stride S (64, or its cells per tile):
     // whole blocks of 8 S rows need at most n / 8 + S threads
     const int ncol = (np + kCountRows - 1) / kCountRows + std::max(max_tcells, 64);
+    hipLaunchKernelGGL(k_batch_sort_count_tiles, dim3(max_tiles1 - 1, n), dim3(kTileCountThreads),
+                       max_tcells * sizeof(int), st, d);
     hipLaunchKernelGGL(k_batch_sort_count, dim3((ncol + 255) / 256, n), dim3(256), 0, st, d);
+    hipLaunchKernelGGL(k_batch_add_counts, dim3((max_keys1 + 255) / 256, n), dim3(256), 0, st, d);
     hipLaunchKernelGGL(k_batch_scan_reduce, dim3(nb, n), dim3(1024), 0, st, d);
     hipLaunchKernelGGL(k_batch_scan_sums, dim3(1, n), dim3(1024), 0, st, d);
     hipLaunchKernelGGL(k_batch_scan_apply, dim3(nb, n), dim3(1024), 0, st, d);
