@@ -34,21 +34,28 @@
 namespace pic {
 
 // LDS current tile, addressed by slots relative to the particle's old cell
-// (esirkepov<true>): every lane's atomics for slots 0..3 (0..2 along the
-// component's own axis) sit at its old cell plus the same offset, so lanes in
-// distinct cells stay in distinct banks whether or not, and which way, they
-// crossed a cell face; only the one extra slot of a crossing axis depends on
-// the direction.  M: transverse-axis slots, P: own-axis slots.
+// (esirkepov<true>): `base` is the lane's node at its old cell - 1 along each
+// axis (slot 0, component 0), and every core slot is base plus an offset
+// that is a compile-time constant for the compiled tile shapes (the whole
+// core stencil of all three components lies within the 16-bit immediate
+// offset of ds_add_u64), so lanes in distinct cells stay in distinct banks
+// whether or not, and which way, they crossed a cell face.  Only the one
+// extra slot of a crossing axis takes a per-lane correction: it is written
+// as the forward node (slot 4 = old cell + 3, or along the component's own
+// axis slot 3 = old cell + 2) and moved to old cell - 2 for a backward
+// crossing.
 struct LdsEmit {
-    unsigned long long* J;   // LDS current tile, 3 components of jr nodes
-    int jr;
-    int XM[5], YM[5], ZM[5];
-    int XP[5], YP[5], ZP[5];
-    __device__ __forceinline__ void add(int comp, int jx, int jy, int jz, long long k) const {
-        const int x = comp == 0 ? XP[jx] : XM[jx];
-        const int y = comp == 1 ? YP[jy] : YM[jy];
-        const int z = comp == 2 ? ZP[jz] : ZM[jz];
-        atomicAdd(J + (comp * jr + x + y + z), (unsigned long long)k);
+    unsigned long long* base;
+    int jx, jpl, jr;                // row, plane and component strides
+    int dxm, dym, dzm;              // backward corrections of the transverse extra slot (elements)
+    int dxp, dyp, dzp;              // ... and of the own-axis extra slot
+    __device__ __forceinline__ void add(int comp, int sx, int sy, int sz, long long k) const {
+        const int off = comp * jr + sx + sy * jx + sz * jpl;
+        int corr = 0;
+        if (comp == 0 ? sx == 3 : sx == 4) corr += comp == 0 ? dxp : dxm;
+        if (comp == 1 ? sy == 3 : sy == 4) corr += comp == 1 ? dyp : dym;
+        if (comp == 2 ? sz == 3 : sz == 4) corr += comp == 2 ? dzp : dzm;
+        atomicAdd(base + (off + corr), (unsigned long long)k);
     }
 };
 
@@ -337,22 +344,18 @@ __device__ __forceinline__ void tile_body(const Geom& g, const TileGeom& t, int 
 #pragma unroll
         for (int d = 0; d < 3; ++d) axis5(unwrap_shift(c1[d] - c[d], g.n[d]), o0[d], o[d], A[d]);
         LdsEmit em;
-        em.J = Jl;
+        em.base = Jl + ((lc[0] + guard + 1) + (lc[1] + guard + 1) * jstride[1] + (lc[2] + guard + 1) * jstride[2]);
+        em.jx = jstride[1];
+        em.jpl = jstride[2];
         em.jr = jr;
-        {
-            int* const M[3] = {em.XM, em.YM, em.ZM};
-            int* const P[3] = {em.XP, em.YP, em.ZP};
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const int n0 = lc[d] + guard + 2;   // the old cell's node
-                const bool back = A[d].base < -1;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) M[d][j] = P[d][j] = (n0 - 1 + j) * jstride[d];
-                M[d][4] = (n0 + (back ? -2 : 3)) * jstride[d];
-                P[d][3] = (n0 + (back ? -2 : 2)) * jstride[d];
-                P[d][4] = M[d][4];   // (never used)
-            }
-        }
+        // backward crossing: the transverse extra slot moves from +4 to -1
+        // slots, the own-axis one from +3 to -1
+        em.dxm = A[0].base < -1 ? -5 : 0;
+        em.dxp = A[0].base < -1 ? -4 : 0;
+        em.dym = A[1].base < -1 ? -5 * jstride[1] : 0;
+        em.dyp = A[1].base < -1 ? -4 * jstride[1] : 0;
+        em.dzm = A[2].base < -1 ? -5 * jstride[2] : 0;
+        em.dzp = A[2].base < -1 ? -4 * jstride[2] : 0;
         esirkepov<true>(A, wq, em);
     }
     if (errs) atomicOr(d_err, errs);
