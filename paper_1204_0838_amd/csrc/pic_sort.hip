@@ -193,8 +193,26 @@ constexpr int kLevelThreads = 512;
 constexpr int kLevelMaxPer = 8;      // tiles of up to 4096 cells
 constexpr int kLevelStage = 8192;    // particles of a tile staged in LDS
 
-__device__ __forceinline__ void sort_levels_tile(const int* __restrict__ off, int tcells, const int* __restrict__ src,
-                                                 int* __restrict__ out, int tile) {
+// The particles that stayed in a tile since the last sort (a re-sort, see
+// k_sort_count_tiles): workgroup `tile` also reads its old range [ob, oe)
+// and puts each particle of rank r >= 0 (it stayed, so its key is in this
+// tile) straight at its cell-order place -- in LDS, or in `src` for a tile too
+// large to stage -- so that only the particles that changed tile go through
+// the scatter (see k_sort_scatter_moved); lc[key] of a key's places are
+// local, the rest are read from `src`.
+struct LocalPlace {
+    Geom g;
+    TileGeom t;
+    SortDiv sd;
+    const int* cell;
+    const int* rank;
+    const int* toff;   // the last sort's tile ranges
+    const int* lc;
+};
+
+__device__ __forceinline__ void sort_levels_tile(const int* __restrict__ off, int tcells, int* __restrict__ src,
+                                                 int* __restrict__ out, int tile,
+                                                 const LocalPlace* __restrict__ lp = nullptr) {
     __shared__ int wsum[2][kLevelThreads / 64];
     __shared__ int stage[kLevelStage];
     const int base = tile * tcells;
@@ -203,8 +221,6 @@ __device__ __forceinline__ void sort_levels_tile(const int* __restrict__ off, in
     const int tb = off[base];
     const int n = off[base + tcells] - tb;
     const bool staged = n <= kLevelStage;
-    if (staged)
-        for (int i = threadIdx.x; i < n; i += kLevelThreads) stage[i] = src[tb + i];
     int start[kLevelMaxPer], cnt[kLevelMaxPer];
     int cmax = 0;
 #pragma unroll
@@ -217,6 +233,25 @@ __device__ __forceinline__ void sort_levels_tile(const int* __restrict__ off, in
             cnt[j] = off[base + k + 1] - tb - start[j];
             cmax = max(cmax, cnt[j]);
         }
+    }
+    if (lp) {
+        const int ob = lp->toff[tile], oe = lp->toff[tile + 1];
+        for (int p = ob + (int)threadIdx.x; p < oe; p += kLevelThreads) {
+            const int r = lp->rank[p];
+            if (r < 0) continue;   // removed, or moved to another tile
+            int c[3];
+            cell_coords(lp->g, lp->sd, lp->cell[p], c);
+            const int slot = off[tile_key(lp->t, lp->sd, c)] - tb + r;
+            if (staged) stage[slot] = p;
+            else src[tb + slot] = p;   // (read back by this workgroup after the barrier)
+        }
+        if (staged)
+#pragma unroll
+            for (int j = 0; j < kLevelMaxPer; ++j)
+                if (j < per && k0 + j < tcells)
+                    for (int q = lp->lc[base + k0 + j]; q < cnt[j]; ++q) stage[start[j] + q] = src[tb + start[j] + q];
+    } else if (staged) {
+        for (int i = threadIdx.x; i < n; i += kLevelThreads) stage[i] = src[tb + i];
     }
     const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
     int lbase = tb;
@@ -254,8 +289,14 @@ __device__ __forceinline__ void sort_levels_tile(const int* __restrict__ off, in
 }
 
 __global__ void __launch_bounds__(kLevelThreads) k_sort_levels(const int* __restrict__ off, int tcells,
-                                                               const int* __restrict__ src, int* __restrict__ out) {
+                                                               int* __restrict__ src, int* __restrict__ out) {
     sort_levels_tile(off, tcells, src, out, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(kLevelThreads) k_sort_levels_local(const int* __restrict__ off, int tcells,
+                                                                     int* __restrict__ src, int* __restrict__ out,
+                                                                     LocalPlace lp) {
+    sort_levels_tile(off, tcells, src, out, blockIdx.x, &lp);
 }
 
 // Exclusive scan, phase 1: per-block totals of 1024-element blocks.
@@ -371,6 +412,19 @@ __device__ __forceinline__ void scatter_one(const Geom& g, const TileGeom& t, co
         }
     }
     out[dest] = p;   // the source index; the gather replaces it with the particle
+}
+
+// Re-sort in level order: only the particles that changed tile since the
+// last sort, and those appended since (rank -2 - place), go to their
+// cell-order place here; the level pass places the others.
+__global__ void __launch_bounds__(256) k_sort_scatter_moved(Geom g, TileGeom t, SortDiv sd,
+                                                            const int* __restrict__ src_cell, int* __restrict__ out,
+                                                            const int* __restrict__ d_count,
+                                                            const int* __restrict__ rank, const int* __restrict__ off,
+                                                            const int* __restrict__ lc) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= *d_count || rank[p] > -2) return;
+    scatter_one(g, t, sd, src_cell, out, p, rank, off, lc, 0);
 }
 
 // Second pass of the permutation, over destinations: dst.cell[i] holds the
@@ -560,11 +614,20 @@ hipError_t launch_sort(const Geom& g, const TileGeom& t, const SpeciesDev& src, 
     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(1024), 0, st, hist, n, sums);
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, sums, nb);
     hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(1024), 0, st, hist, n, sums, hist);
-    hipLaunchKernelGGL(k_sort_scatter, dim3((np + 255) / 256), dim3(256), 0, st, g, t, sd, src.cell,
-                       depth == 0 ? level : dst.cell, d_count, rank, hist, lc, depth);
-    if (depth == 0)
-        hipLaunchKernelGGL(k_sort_levels, dim3(t.ntiles), dim3(kLevelThreads), 0, st, hist, t.tcells, level,
-                           dst.cell);
+    if (depth == 0 && resort) {
+        // toff still holds the last sort's tile ranges (rewritten at the end)
+        hipLaunchKernelGGL(k_sort_scatter_moved, dim3((np + 255) / 256), dim3(256), 0, st, g, t, sd, src.cell, level,
+                           d_count, rank, hist, lc);
+        LocalPlace lp{g, t, sd, src.cell, rank, toff, lc};
+        hipLaunchKernelGGL(k_sort_levels_local, dim3(t.ntiles), dim3(kLevelThreads), 0, st, hist, t.tcells, level,
+                           dst.cell, lp);
+    } else {
+        hipLaunchKernelGGL(k_sort_scatter, dim3((np + 255) / 256), dim3(256), 0, st, g, t, sd, src.cell,
+                           depth == 0 ? level : dst.cell, d_count, rank, hist, lc, depth);
+        if (depth == 0)
+            hipLaunchKernelGGL(k_sort_levels, dim3(t.ntiles), dim3(kLevelThreads), 0, st, hist, t.tcells, level,
+                               dst.cell);
+    }
     if (copy) hipLaunchKernelGGL(k_sort_gather, dim3((np + 255) / 256), dim3(256), 0, st, src, dst, hist, nkeys);
     hipLaunchKernelGGL(k_sort_finish, dim3(1), dim3(1), 0, st, hist, nkeys, d_count, d_sorted);
     hipLaunchKernelGGL(k_tile_offsets, dim3((t.ntiles + 1 + 255) / 256), dim3(256), 0, st, hist, t.tcells, t.ntiles,

@@ -157,6 +157,56 @@ def test_sort_stores_tiles_in_level_order():
     assert np.array_equal(key, np.concatenate(want_k))
 
 
+def _level_order(cells, n, T):
+    """(tile, in-tile key) sequence of the level order of the given cells."""
+    ct, ck = _brick_key(cells.astype(np.int64), n, T)
+    want_t, want_k = [], []
+    for t in range(int(ct.max()) + 1):
+        cnt = np.bincount(ck[ct == t], minlength=512)
+        for r in range(int(cnt.max()) if cnt.size else 0):
+            ks = np.nonzero(cnt > r)[0]
+            want_t.append(np.full(ks.size, t))
+            want_k.append(ks)
+    return np.concatenate(want_t), np.concatenate(want_k)
+
+
+def test_resort_keeps_level_order():
+    """A re-sort (particles still in the last sort's tile ranges: counted tile
+    by tile, those that stayed in their tile placed by the level pass, the
+    others scattered) stores the same level order as a first sort: after
+    steps that move particles across cells and tiles, and with more
+    particles appended by hand, slot by slot against the order computed from
+    the new cells; also for a tile too dense to be staged in LDS (more than
+    8192 particles)."""
+    grid = inputs.Grid(n=(24, 16, 16), d=(0.25, 0.5, 0.5), dt=0.25, solver="pd")
+    ncell = 24 * 16 * 16
+    rng = np.random.default_rng(48)
+    cell = rng.integers(0, ncell, 5 * ncell)
+    dense = np.full(9000, 3 + 24 * (2 + 16 * 3))               # one cell of tile 0 over the staging size
+    cell = np.concatenate([cell, dense]).astype(np.int32)
+    off = rng.random((3, cell.size)).astype(np.float32)
+    u = (0.6 * rng.standard_normal((3, cell.size))).astype(np.float32)   # ~0.3-0.6 cells per step
+    w = np.full(cell.size, 0.01, np.float32)
+    ids = np.arange(cell.size, dtype=np.int32)
+    T = (8, 8, 8)
+    sim = pic.Simulation(grid.n, grid.d, grid.dt, solver="pd", tile=T, sort_interval=100,
+                         max_particles=cell.size)
+    sim.add_species(cell, off, u, w, ids)
+    sim.sort(0)                                                   # first sort
+    for _ in range(3):
+        sim.gather_push(0)                                        # moves particles, keeps their places
+    before = sim.particles_host(0)
+    sim.sort(0)                                                   # re-sort
+    got = sim.particles_host(0)
+    assert np.array_equal(np.sort(got["id"]), ids)
+    moved = np.mean(before["cell"] != cell[before["id"]])
+    assert moved > 0.3                                            # many particles changed cell
+    tile, key = _brick_key(got["cell"].astype(np.int64), grid.n, T)
+    wt, wk = _level_order(got["cell"], grid.n, T)
+    assert np.array_equal(tile, wt)
+    assert np.array_equal(key, wk)
+
+
 def test_sort_orders_tiles_in_bricks():
     """With plain (depth-1) storage the sorted particles of 8x8x8 tiles follow
     the brick order of their cells; the key is a bijection onto the tile's
