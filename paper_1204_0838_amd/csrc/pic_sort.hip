@@ -31,9 +31,10 @@ namespace pic {
 
 // Cell order inside a tile: for tiles of 8 x 2m x 4k cells, 64-cell bricks
 // of 8x2x4 cells (x fastest, then z, then y inside a brick; bricks y-major),
-// so that a wavefront reading one transposed block of such a brick has its
-// lanes in 8 x-cells of successive z-planes (the tile kernel pads its LDS
-// planes to match); plain x-fastest order for every other shape.
+// so that a wavefront reading 64 consecutive cells of a level (or one
+// transposed block) of such a brick has its lanes in 8 x-cells of
+// successive z-planes (the tile kernel pads its LDS planes to match); plain
+// x-fastest order for every other shape.
 __device__ __forceinline__ int local_key(const TileGeom& t, int lx, int ly, int lz) {
     if (t.T[0] == 8 && (t.T[1] & 1) == 0 && (t.T[2] & 3) == 0)
         return lx + 8 * (lz & 3) + 32 * (ly & 1) + 64 * ((ly >> 1) + (t.T[1] >> 1) * (lz >> 2));
