@@ -155,12 +155,24 @@ __device__ __forceinline__ void count_tile(const Geom& g, const TileGeom& t, con
     for (int i = threadIdx.x; i < t.tcells; i += kTileCountThreads) lh[i] = 0;
     __syncthreads();
     const int b = toff[tile], e = toff[tile + 1];
-    for (int p = b + (int)threadIdx.x; p < e; p += kTileCountThreads) {
-        const int key = sort_key(g, t, sd, cell[p]);
-        int r = -1;
-        if ((unsigned)(key - k0) < (unsigned)t.tcells) r = atomicAdd(&lh[key - k0], 1);
-        else if (key >= 0) r = -2 - atomicAdd(&hist[key], 1);
-        rank[p] = r;
+    // four particles per thread at a time, their cells loaded together
+    for (int p0 = b + (int)threadIdx.x; p0 < e; p0 += 4 * kTileCountThreads) {
+        int cl[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int p = p0 + u * kTileCountThreads;
+            cl[u] = p < e ? cell[p] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int p = p0 + u * kTileCountThreads;
+            if (p >= e) continue;
+            const int key = sort_key(g, t, sd, cl[u]);
+            int r = -1;
+            if ((unsigned)(key - k0) < (unsigned)t.tcells) r = atomicAdd(&lh[key - k0], 1);
+            else if (key >= 0) r = -2 - atomicAdd(&hist[key], 1);
+            rank[p] = r;
+        }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < t.tcells; i += kTileCountThreads) lc[k0 + i] = lh[i];
@@ -193,6 +205,7 @@ __global__ void __launch_bounds__(256) k_add_counts(int* __restrict__ hist, cons
 constexpr int kLevelThreads = 512;
 constexpr int kLevelMaxPer = 8;      // tiles of up to 4096 cells
 constexpr int kLevelStage = 8192;    // particles of a tile staged in LDS
+constexpr int kPlaceUnroll = 4;
 
 // The particles that stayed in a tile since the last sort (a re-sort, see
 // k_sort_count_tiles): workgroup `tile` also reads its old range [ob, oe)
@@ -237,14 +250,34 @@ __device__ __forceinline__ void sort_levels_tile(const int* __restrict__ off, in
     }
     if (lp) {
         const int ob = lp->toff[tile], oe = lp->toff[tile + 1];
-        for (int p = ob + (int)threadIdx.x; p < oe; p += kLevelThreads) {
-            const int r = lp->rank[p];
-            if (r < 0) continue;   // removed, or moved to another tile
-            int c[3];
-            cell_coords(lp->g, lp->sd, lp->cell[p], c);
-            const int slot = off[tile_key(lp->t, lp->sd, c)] - tb + r;
-            if (staged) stage[slot] = p;
-            else src[tb + slot] = p;   // (read back by this workgroup after the barrier)
+        // kPlaceUnroll particles per thread at a time, each stage's loads
+        // issued for all of them before any is used (the chain rank, cell ->
+        // key -> off[key] is otherwise one round trip after another)
+        constexpr int U = kPlaceUnroll;
+        for (int p0 = ob + (int)threadIdx.x; p0 < oe; p0 += U * kLevelThreads) {
+            int r[U], cl[U], o[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int p = p0 + u * kLevelThreads;
+                r[u] = p < oe ? lp->rank[p] : -1;
+                cl[u] = p < oe ? lp->cell[p] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                o[u] = 0;
+                if (r[u] >= 0) {   // (r < 0: removed, or moved to another tile)
+                    int c[3];
+                    cell_coords(lp->g, lp->sd, cl[u], c);
+                    o[u] = off[tile_key(lp->t, lp->sd, c)];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (r[u] < 0) continue;
+                const int slot = o[u] - tb + r[u];
+                if (staged) stage[slot] = p0 + u * kLevelThreads;
+                else src[tb + slot] = p0 + u * kLevelThreads;   // (read back by this workgroup after the barrier)
+            }
         }
         if (staged)
 #pragma unroll
