@@ -259,9 +259,9 @@ __device__ __forceinline__ void tile_body(const Geom& g, const TileGeom& t, int 
     // current particle is processed
     int pn = pb + (int)threadIdx.x, celln = -1;
     float on[3] = {0.f, 0.f, 0.f}, un[3] = {0.f, 0.f, 0.f}, wn = 0.f;
-    if (NT < 1024 && (int)threadIdx.x < n) load_particle<GATHER>(s, src, pn, celln, on, un, wn);
+    if ((NT < 1024 || !GATHER) && (int)threadIdx.x < n) load_particle<GATHER>(s, src, pn, celln, on, un, wn);
     for (int q = threadIdx.x; q < n; q += NT) {
-        if (NT >= 1024) {
+        if (NT >= 1024 && GATHER) {
             pn = pb + q;
             load_particle<GATHER>(s, src, pn, celln, on, un, wn);
         }
@@ -270,9 +270,9 @@ __device__ __forceinline__ void tile_body(const Geom& g, const TileGeom& t, int 
         float o[3] = {on[0], on[1], on[2]};
         float u[3] = {un[0], un[1], un[2]};
         const float wq = s.mq * wn;
-        // (1024-thread workgroups keep four waves per SIMD; there the hardware
-        // hides the load latency and the prefetch registers would spill)
-        if (NT < 1024 && q + NT < n) {
+        // (not in the 1024-thread launch right after a sort, whose loads go
+        // through the source index: measured slower there with it)
+        if ((NT < 1024 || !GATHER) && q + NT < n) {
             pn = p + NT;
             load_particle<GATHER>(s, src, pn, celln, on, un, wn);
         }
