@@ -549,12 +549,19 @@ __global__ void __launch_bounds__(256) k_batch_add_counts(const InstDesc* __rest
 }
 
 // Level order of the sorting members with depth 0 (after their scatter):
-// grid x = tile, y = member.
+// grid x = tile, y = member.  A member that re-sorts places the particles
+// that stayed in their tile here, from its last tile ranges (its scatter
+// moved only the others), as the single simulation's re-sort does.
 __global__ void __launch_bounds__(kLevelThreads) k_batch_sort_levels(const InstDesc* __restrict__ tab) {
     const InstDesc& d = tab[blockIdx.y];
     if (!d.sorting || d.depth != 0 || (int)blockIdx.x >= d.t.ntiles) return;
     // (the workgroup returns as a whole: the condition is uniform)
-    sort_levels_tile(d.hist, d.t.tcells, d.level, d.alt.cell, blockIdx.x);
+    if (d.resort) {
+        const LocalPlace lp{d.g, d.t, d.sdiv, d.s.cell, d.rank, d.toff, d.lc};
+        sort_levels_tile(d.hist, d.t.tcells, d.level, d.alt.cell, blockIdx.x, &lp);
+    } else {
+        sort_levels_tile(d.hist, d.t.tcells, d.level, d.alt.cell, blockIdx.x);
+    }
 }
 
 __global__ void __launch_bounds__(1024) k_batch_scan_reduce(const InstDesc* __restrict__ tab) {
@@ -581,6 +588,9 @@ __global__ void __launch_bounds__(256) k_batch_sort_scatter(const InstDesc* __re
     const InstDesc& d = tab[blockIdx.y];
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (!d.sorting || p >= *d.count) return;
+    // a level-order re-sort: only the particles that changed tile or were
+    // appended (rank < -1); the level pass places the others
+    if (d.resort && d.depth == 0 && d.rank[p] > -2) return;
     const Geom g = d.g;
     const TileGeom t = d.t;
     const SpeciesDev src = d.s, dst = d.alt;
