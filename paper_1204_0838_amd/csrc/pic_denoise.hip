@@ -344,16 +344,45 @@ __global__ void __launch_bounds__(DO_THREADS) k_dn_output(DnCombine c) {
     __shared__ float ys[3][DO_YZ * DO_YY * DO_YX];
     __shared__ float ts[3][DO_SZ * DO_SY * DO_SX];
     const int t0[3] = {(int)blockIdx.x * DO_TX, (int)blockIdx.y * DO_TY, (int)blockIdx.z * DO_TZ};
-    for (int i = threadIdx.x; i < DO_YZ * DO_YY * DO_YX; i += DO_THREADS) {
-        const int hx = i % DO_YX, r = i / DO_YX, hy = r % DO_YY, hz = r / DO_YY;
-        const int s = do_src(c, t0[0] - 2 + hx, t0[1] - 2 + hy, t0[2] - 2 + hz);
+    // Every global load of a thread is issued before the first of them is
+    // used (the y halo, then the current at the t cells, the latter in flight
+    // while the y halo is stored), so each staging pass waits for one memory
+    // latency rather than one per cell.
+    constexpr int NY = DO_YZ * DO_YY * DO_YX, PY = (NY + DO_THREADS - 1) / DO_THREADS;
+    constexpr int NT = DO_SZ * DO_SY * DO_SX, PT = (NT + DO_THREADS - 1) / DO_THREADS;
+    float yv[PY][3];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) ys[d][i] = dn_at(c.y[d], s);
+    for (int q = 0; q < PY; ++q) {
+        const int i = (int)threadIdx.x + q * DO_THREADS;
+        const int hx = i % DO_YX, r = i / DO_YX, hy = r % DO_YY, hz = r / DO_YY;
+        const int s = i < NY ? do_src(c, t0[0] - 2 + hx, t0[1] - 2 + hy, t0[2] - 2 + hz) : -1;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) yv[q][d] = dn_at(c.y[d], s);
+    }
+    int ts_src[PT];
+    float sv[PT][3];
+#pragma unroll
+    for (int q = 0; q < PT; ++q) {
+        const int i = (int)threadIdx.x + q * DO_THREADS;
+        const int hx = i % DO_SX, r = i / DO_SX, hy = r % DO_SY, hz = r / DO_SY;
+        ts_src[q] = i < NT ? do_src(c, t0[0] - 1 + hx, t0[1] - 1 + hy, t0[2] - 1 + hz) : -1;
+#pragma unroll
+        for (int comp = 0; comp < 3; ++comp) sv[q][comp] = dn_at(c.src[comp], ts_src[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < PY; ++q) {
+        const int i = (int)threadIdx.x + q * DO_THREADS;
+        if (i < NY)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) ys[d][i] = yv[q][d];
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < DO_SZ * DO_SY * DO_SX; i += DO_THREADS) {
+#pragma unroll
+    for (int q = 0; q < PT; ++q) {
+        const int i = (int)threadIdx.x + q * DO_THREADS;
+        if (i >= NT) continue;
         const int hx = i % DO_SX, r = i / DO_SX, hy = r % DO_SY, hz = r / DO_SY;
-        const int s = do_src(c, t0[0] - 1 + hx, t0[1] - 1 + hy, t0[2] - 1 + hz);
+        const int s = ts_src[q];
         const int yc = ((hz + 1) * DO_YY + (hy + 1)) * DO_YX + (hx + 1);   // the same cell in ys
         const int ym[3] = {yc - 1, yc - DO_YX, yc - DO_YX * DO_YY};          // one cell lower along x, y, z
 #pragma unroll
@@ -362,7 +391,7 @@ __global__ void __launch_bounds__(DO_THREADS) k_dn_output(DnCombine c) {
             float v = 0.0f;
             if (s >= 0) {
                 const float cu = (ys[t2][yc] - ys[t2][ym[t1]]) * c.inv_d[t1] - (ys[t1][yc] - ys[t1][ym[t2]]) * c.inv_d[t2];
-                v = fmaf(c.sigma, cu, c.src[comp][s]);
+                v = fmaf(c.sigma, cu, sv[q][comp]);
             }
             ts[comp][i] = v;
         }
