@@ -250,8 +250,8 @@ def bench_c4(args):
 
     from paper_1204_0838_amd import c4, workloads
 
-    cfg = c4._cfg(workloads.C1, c4.PPC2)
-    sim = workloads.build(cfg, jpost="denoiser", tuned=False)
+    cfg = c4.c4_config()
+    sim = workloads.build(cfg, jpost="denoiser")   # (the autotuner's tiling for it when cached)
     sim.set_denoiser(c4.binomial_init(np.random.default_rng(0)), [0.01, 0.01, 0.01])
     sim.step(args.warmup)
     sim.sync()

@@ -123,13 +123,13 @@ def knob_variants(base: dict) -> list:
     return out
 
 
-def run_ms(cfg: dict, tiling: dict, steps: int, chunk: int = 20) -> float:
+def run_ms(cfg: dict, tiling: dict, steps: int, chunk: int = 20, jpost: str = "none") -> float:
     """Mean ms per step of a fresh run of `steps` steps from t = 0 with `tiling`."""
     import torch
 
     from . import workloads
 
-    sim = workloads.build(cfg, tuned=False, **tiling)
+    sim = workloads.build(cfg, tuned=False, jpost=jpost, **tiling)
     sim.sync()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -147,7 +147,8 @@ def run_ms(cfg: dict, tiling: dict, steps: int, chunk: int = 20) -> float:
     return total / steps
 
 
-def tune_phases(cfg: dict, phases=(150, 450, 750), steps: int = 12, base_every: int = 3, log=sys.stderr):
+def tune_phases(cfg: dict, phases=(150, 450, 750), steps: int = 12, base_every: int = 3, log=sys.stderr,
+                jpost: str = "none"):
     """Search over the whole run instead of one instant (the cost of a step
     changes as the wake forms and particles move).
 
@@ -158,13 +159,14 @@ def tune_phases(cfg: dict, phases=(150, 450, 750), steps: int = 12, base_every: 
     below 0.99; the knobs so chosen are combined, and the combination is kept
     only if a full fresh run with it is faster than one with the default.
     Returns (best, ms per step of best over the run, table of (candidate,
-    mean ratio, per-phase ratios), note)."""
+    mean ratio, per-phase ratios), note).  jpost: the current post-processing
+    of the runs."""
     from . import workloads
 
     base = dict(DEFAULT)
     cands = knob_variants(base)
     ratios = {i: [] for i in range(len(cands))}
-    sim = workloads.build(cfg, tuned=False, **base)
+    sim = workloads.build(cfg, tuned=False, jpost=jpost, **base)
     done = 0
     for ph in phases:
         if ph < done:
@@ -199,10 +201,10 @@ def tune_phases(cfg: dict, phases=(150, 450, 750), steps: int = 12, base_every: 
     if not feasible(best):
         best = min(table, key=lambda x: x[1])[0] if min(r[1] for r in table) < 0.99 else dict(base)
     total = int(cfg.get("steps", 1000))
-    ms_base = run_ms(cfg, base, total)
+    ms_base = run_ms(cfg, base, total, jpost=jpost)
     note = f"one-knob changes of the default timed at steps {list(phases)} of one run ({steps} steps each)"
     if best != base:
-        ms_best = run_ms(cfg, best, total)
+        ms_best = run_ms(cfg, best, total, jpost=jpost)
         if log:
             print(f"# whole run: default {ms_base:.3f}, combined {best} {ms_best:.3f} ms/step", file=log, flush=True)
         note += f"; whole {total}-step runs: combined {ms_best:.2f}, default {ms_base:.2f} ms per step"
@@ -349,7 +351,9 @@ def main():
     ap.add_argument("--instant", action="store_true",
                     help="coordinate descent at one instant (--warmup) instead of the whole-run search")
     ap.add_argument("--phases", type=str, default="150,450,750", help="steps of the run at which candidates are timed")
-    ap.add_argument("--workload", choices=("c1", "c1p"), default="c1")
+    ap.add_argument("--workload", choices=("c1", "c1p", "c4"), default="c1",
+                    help="c4: the 2-ppc C1 geometry, tuned with the binomial filter standing in for the "
+                         "denoiser (the tiling changes the particle phases only)")
     args = ap.parse_args()
     sys.path.insert(0, os.path.dirname(HERE))
     from paper_1204_0838_amd import workloads
@@ -368,11 +372,20 @@ def main():
         return
 
     cfg = workloads.C1P if args.workload == "c1p" else workloads.C1
+    jpost = "none"
+    if args.workload == "c4":
+        from paper_1204_0838_amd import c4
+
+        cfg = c4.c4_config()
+        jpost = "binomial"
     if args.grid:
         cfg = workloads.scaled(cfg, [int(v) for v in args.grid.split(",")])
     if not args.instant:
         t0 = time.perf_counter()
-        best, best_ms, table, note = tune_phases(cfg, tuple(int(v) for v in args.phases.split(",")), args.steps)
+        best, best_ms, table, note = tune_phases(cfg, tuple(int(v) for v in args.phases.split(",")), args.steps,
+                                                 jpost=jpost)
+        if jpost != "none":
+            note += f" (current post-processing: {jpost})"
         best["tile"] = list(best["tile"])
         save(cfg, best, best_ms, table, note + f", {time.perf_counter() - t0:.0f} s")
         print(json.dumps({"key": key_of(cfg), "best": best, "ms_per_step": best_ms}))

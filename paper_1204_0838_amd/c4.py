@@ -68,6 +68,13 @@ def _cfg(base, ppc):
     return cfg
 
 
+def c4_config():
+    """The C4 workload: the C1 geometry at 2 particles per cell."""
+    from . import workloads
+
+    return _cfg(workloads.C1, PPC2)
+
+
 def _ex_window(sim):
     """E_x in window order (x index 0 = the window's trailing cell), host float32."""
     import torch
